@@ -23,7 +23,42 @@ instance sides, 7 loop-nest features, 1000+i interior of batched instance i.
 """
 from __future__ import annotations
 
+import ctypes
+import os
+import subprocess
+
 import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_FILL_SO = os.path.join(_HERE, "libgfinputs.so")
+_fill = None
+
+
+def build(force: bool = True) -> str:
+    """Compile the bulk-fill helper (fill.c) used for large grids and keys."""
+    if force or not os.path.exists(_FILL_SO):
+        tmp = _FILL_SO + ".tmp"
+        subprocess.check_call(["gcc", "-O2", "-std=c11", "-shared", "-fPIC", "-o", tmp,
+                               os.path.join(_HERE, "fill.c")])
+        os.replace(tmp, _FILL_SO)
+    return _FILL_SO
+
+
+def _fill_lib():
+    global _fill
+    if _fill is None:
+        if not os.path.exists(_FILL_SO):
+            try:
+                build(force=True)
+            except (OSError, subprocess.CalledProcessError):
+                return None
+        lib = ctypes.CDLL(_FILL_SO)
+        U64, I64, P = ctypes.c_uint64, ctypes.c_int64, ctypes.c_void_p
+        lib.gfi_u01.argtypes = [U64, U64, U64, I64, P]
+        lib.gfi_grid3d.argtypes = [I64, U64, U64, P]
+        lib.gfi_keys_u32.argtypes = [U64, U64, U64, I64, P]
+        _fill = lib
+    return _fill
 
 GAMMA = 0x9E3779B97F4A7C15
 _M1 = 0xBF58476D1CE4E5B9
@@ -89,8 +124,16 @@ def grid2d(n: int, seed: int = 1, stream: int = STREAM_GRID) -> np.ndarray:
     return u
 
 
-def grid3d(n: int, seed: int = 1, stream: int = STREAM_GRID, out: np.ndarray | None = None) -> np.ndarray:
-    """n^3 float64 grid u[z][y][x] (x fastest); interior U01; built plane by plane."""
+def grid3d(n: int, seed: int = 1, stream: int = STREAM_GRID, out: np.ndarray | None = None,
+           fast: bool = True) -> np.ndarray:
+    """n^3 float64 grid u[z][y][x] (x fastest); interior U01; built plane by plane.
+
+    fast=True uses the compiled fill (same definition) when it is available."""
+    lib = _fill_lib() if fast else None
+    if lib is not None:
+        u = np.empty((n, n, n), dtype=np.float64) if out is None else out
+        lib.gfi_grid3d(n, seed, stream, u.ctypes.data_as(ctypes.c_void_p))
+        return u
     u = np.zeros((n, n, n), dtype=np.float64) if out is None else out
     if out is not None:
         u[0] = 0.0
@@ -192,7 +235,12 @@ def cg_rhs(n: int, seed: int = 1) -> np.ndarray:
 # Histogram keys
 # --------------------------------------------------------------------------
 
-def hist_keys_uniform(n: int, seed: int = 1, chunk: int = 1 << 24) -> np.ndarray:
+def hist_keys_uniform(n: int, seed: int = 1, chunk: int = 1 << 24, fast: bool = True) -> np.ndarray:
+    lib = _fill_lib() if fast else None
+    if lib is not None:
+        keys = np.empty(n, dtype=np.uint32)
+        lib.gfi_keys_u32(seed, STREAM_HIST, 0, n, keys.ctypes.data_as(ctypes.c_void_p))
+        return keys
     keys = np.empty(n, dtype=np.uint32)
     for s in range(0, n, chunk):
         e = min(n, s + chunk)

@@ -1,0 +1,256 @@
+/*
+ * gf.h -- C ABI of libgf: GPU-First execution of legacy OpenMP-style loop
+ * programs on one MI355X (gfx950).
+ *
+ * Model (paper, Section 2.1 "OpenMP Execution Model" and Section 3.3
+ * "Multi-Team Execution and Kernel Split"): a legacy program is serial code
+ * run by one initial thread, interleaved with `parallel for` regions. Each
+ * region's iterations are spread over every thread of every workgroup with
+ * continuous global thread ids, and the implicit barrier at the end of a
+ * region spans all workgroups. Host-only library calls (printf) made by the
+ * initial thread are forwarded to the host by a synchronous client-server
+ * remote procedure call (Section 2.3 "Host Remote Procedural Call",
+ * Section 3.2 "Generating Remote Procedural Calls").
+ *
+ * A program is given as a step list (gf_program): a prologue run once and a
+ * body run `iters` times. A step is either a REGION (a loop body from the
+ * region catalogue below, optionally with one reduction clause into a scalar
+ * variable) or a SERIAL op of the initial thread (scalar arithmetic, pointer
+ * swap, history record, printf through RPC).
+ *
+ * Reductions: the paper does not rewrite reduction clauses (Section 4.3), so
+ * they follow OpenMP semantics: private copies start at the operator's
+ * identity; the variable ends as its original value combined with all
+ * contributions. The combination order of floating-point sums is
+ * unspecified; libgf fixes it per tile decomposition, so a given launch
+ * configuration is bit-reproducible.
+ *
+ * Conventions for every entry point:
+ *  - Pointers named d_* or held in gf_instance are DEVICE pointers (HIP
+ *    device memory, e.g. from torch tensors) owned by the caller; they must
+ *    stay valid until the enqueued work has completed on `hip_stream`.
+ *  - Host-side structs (gf_program, gf_instance, gf_launch) are copied
+ *    during the call; the caller may free them on return.
+ *  - `hip_stream` is a hipStream_t (NULL = the default stream). Runs and
+ *    reductions are enqueued asynchronously on it.
+ *  - Return value: GF_OK (0) or a negative gf_status. Argument errors are
+ *    detected before anything is enqueued. Device-side failures (barrier or
+ *    RPC watchdog, bad step) set a sticky error word that surfaces as
+ *    GF_EDEVICE / GF_ETIMEOUT from the next gf_sync or gf_region_run.
+ *  - gf_last_error(ctx) returns a message for the last failure on that ctx.
+ *  - No C++ exception crosses the ABI. A ctx is not thread-safe, except that
+ *    gf_rpc_poll may run concurrently on one server thread.
+ */
+#ifndef GF_H
+#define GF_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct gf_ctx gf_ctx;
+
+typedef enum {
+    GF_OK = 0,
+    GF_EINVAL = -1,       /* invalid argument or program; nothing enqueued */
+    GF_ENOMEM = -2,       /* host or device allocation failed */
+    GF_EHIP = -3,         /* a HIP runtime call failed */
+    GF_ETIMEOUT = -4,     /* a device watchdog (barrier or RPC wait) expired */
+    GF_ERPC = -5,         /* malformed RPC request */
+    GF_EDEVICE = -6,      /* device reported an error (bad step, ring overflow) */
+    GF_EUNSUPPORTED = -7  /* valid request this build does not implement */
+} gf_status;
+
+typedef enum { GF_OP_SUM = 0, GF_OP_MAX = 1, GF_OP_NONE = -1 } gf_op;
+typedef enum { GF_F64 = 0, GF_U32 = 1, GF_U64 = 2, GF_I64 = 3 } gf_dtype;
+
+typedef enum {
+    GF_EXEC_PER_REGION = 0,       /* one kernel launch per region (host walks the steps) */
+    GF_EXEC_PERSISTENT = 1,       /* one cooperative launch; grid barrier between regions */
+    GF_EXEC_PER_REGION_GRAPH = 2  /* per-region launches captured once into a HIP graph */
+} gf_exec;
+
+#define GF_MAX_ARRAYS 16
+#define GF_MAX_SCALARS 16
+#define GF_MAX_IPARAMS 8
+#define GF_MAX_STEPS 64
+#define GF_MAX_INSTANCES 4096
+
+/* ---- step kinds --------------------------------------------------------
+ * Region kinds: `parallel for` bodies. Operands are array slots (arr[]),
+ * scalar slots (sc[]) and a size taken from the instance (ip[np]).
+ *
+ * GF_R_JACOBI2D  arr[0]=u (in, n x n f64 row-major), arr[1]=w (out).
+ *                For every interior (j,i): v = ((W+E)+(S+N))*0.25, w = v,
+ *                d = v-u. Reduction clause (optional, op SUM): d*d into sc[0].
+ * GF_R_JACOBI3D  arr[0]=u (in, n^3 f64, x fastest), arr[1]=w (out).
+ *                v = (((xm+xp)+(ym+yp))+(zm+zp))*(1/6). Reduction (optional,
+ *                op MAX): |d| into sc[0].
+ * GF_R_SPMV      arr[0]=rowptr (i32, n+1), arr[1]=col (i32), arr[2]=val (f64),
+ *                arr[3]=x (f64), arr[4]=y (f64, out); y_i = sum_k val*x[col],
+ *                summed serially in column order per row. n = rows.
+ * GF_R_DOT       arr[0]=a, arr[1]=b (f64, n). Reduction SUM of a_i*b_i into sc[0].
+ * GF_R_AXPBY     arr[0]=out, arr[1]=x, arr[2]=y (f64, n; out may alias x or y):
+ *                out_i = x_i + s*y_i with s = scal[sc[1]] * c (c = +1 or -1
+ *                for exactness; any double allowed).
+ * GF_R_HIST      arr[0]=keys (u32, n), arr[1]=bins (u32); bins[key & mask] += 1.
+ * GF_R_OWNER     arr[0]=owner (i32, n): owner[i] = continuous global thread
+ *                id that executed iteration i under schedule(static[,chunk]).
+ *
+ * Serial kinds (the initial thread; scal = the instance's scalar variables,
+ * `iter` = 0-based body iteration, -1 in the prologue):
+ * GF_S_SET       scal[sc[0]] = c
+ * GF_S_COPY      scal[sc[0]] = scal[sc[1]]
+ * GF_S_DIV       scal[sc[0]] = scal[sc[1]] / scal[sc[2]]
+ * GF_S_SQRT      scal[sc[0]] = sqrt(scal[sc[1]])
+ * GF_S_SWAP      swap array slots arr[0] and arr[1]
+ * GF_S_RECORD    ((double*)arr-slot arr[0])[iter] = scal[sc[0]]
+ * GF_S_PRINTF    if ((iter+1) % every == 0): printf(format fmt_id) through
+ *                RPC with arguments (int)(iter+1), scal[sc[0]] .. scal[sc[nargs-2]]
+ *                (nargs counts the iteration argument). Posted (fire and
+ *                forget) unless flags & GF_STEP_BLOCKING.
+ */
+typedef enum {
+    GF_R_JACOBI2D = 1,
+    GF_R_JACOBI3D = 2,
+    GF_R_SPMV = 3,
+    GF_R_DOT = 4,
+    GF_R_AXPBY = 5,
+    GF_R_HIST = 6,
+    GF_R_OWNER = 7,
+    GF_S_SET = 32,
+    GF_S_COPY = 33,
+    GF_S_DIV = 34,
+    GF_S_SQRT = 35,
+    GF_S_SWAP = 36,
+    GF_S_RECORD = 37,
+    GF_S_PRINTF = 38
+} gf_step_kind;
+
+#define GF_STEP_BLOCKING 1u
+
+typedef struct {
+    int32_t kind;      /* gf_step_kind */
+    int32_t arr[5];    /* array slot indices (unused: -1) */
+    int32_t sc[3];     /* scalar slot indices (unused: -1) */
+    int32_t red_op;    /* reduction clause of a region: GF_OP_SUM / GF_OP_MAX / GF_OP_NONE */
+    int32_t np;        /* index into gf_instance.ip of the region's size */
+    int32_t every;     /* GF_S_PRINTF period (iterations) */
+    int32_t fmt_id;    /* GF_S_PRINTF format id from gf_rpc_register_format */
+    int32_t nargs;     /* GF_S_PRINTF argument count incl. the iteration number */
+    uint32_t flags;    /* GF_STEP_BLOCKING */
+    uint32_t mask;     /* GF_R_HIST bin mask (nbins - 1, nbins a power of two) */
+    int64_t chunk;     /* GF_R_OWNER schedule(static, chunk); 0 = schedule(static) */
+    double c;          /* constant of GF_S_SET / GF_R_AXPBY */
+} gf_step;
+
+typedef struct {
+    int32_t n_prologue;
+    const gf_step *prologue;
+    int32_t n_body;
+    const gf_step *body;
+    int32_t iters;     /* body repetitions (the program's main loop) */
+} gf_program;
+
+/* Bindings of one program instance. arr[] are device pointers; scal is a
+ * device array of GF_MAX_SCALARS doubles holding the scalar variables (read
+ * at start, written back at the end); ip[] are sizes. */
+typedef struct {
+    void *arr[GF_MAX_ARRAYS];
+    double *scal;
+    int64_t ip[GF_MAX_IPARAMS];
+} gf_instance;
+
+/* Launch configuration. Zero fields mean "choose": the persistent grid is
+ * sized from occupancy; tiles come from the tuning database, else defaults. */
+typedef struct {
+    int32_t wg_size;     /* threads per workgroup (multiple of 64, <= 1024) */
+    int32_t num_wg;      /* workgroups (persistent: <= co-resident capacity) */
+    int32_t tile_y;      /* stencil rows per tile (1..16) */
+    int32_t tile_z;      /* 3D stencil z-segment length */
+    int32_t items;       /* elements per thread for streaming regions */
+    int32_t xcd_remap;   /* 1: map consecutive tiles to one XCD (8 XCDs) */
+} gf_launch;
+
+typedef struct {
+    int32_t regions;       /* region executions enqueued */
+    int32_t launches;      /* kernel launches enqueued */
+    int32_t barriers;      /* grid barriers executed per persistent launch */
+    int32_t num_wg;        /* workgroups used (largest launch) */
+    int32_t wg_size;
+    int32_t rpc_posted;    /* filled by gf_sync: RPC requests serviced so far */
+} gf_run_stats;
+
+typedef struct {
+    int32_t rpc_slots;        /* ring slots (power of two, 8..4096); 0 = 256 */
+    int32_t rpc_capture;      /* 1: landing pads append output to a buffer read by
+                                 gf_rpc_take_output instead of writing stdout */
+    int32_t rpc_thread;       /* 1: libgf runs the RPC server thread itself */
+    int64_t rpc_timeout_us;   /* device watchdog for RPC slot waits; 0 = 2 s */
+    int64_t barrier_timeout_us; /* device watchdog for grid barriers; 0 = 10 s */
+} gf_ctx_opts;
+
+/* Create a context on HIP device `hip_device`: allocates the pinned RPC ring
+ * (hipHostMalloc, coherent), device scratch (reduction partials, barrier
+ * counters, error word, program copies). opts may be NULL (defaults). */
+gf_status gf_ctx_create(int32_t hip_device, const gf_ctx_opts *opts, gf_ctx **out);
+/* Waits for the device, stops the server thread, frees everything. NULL ok. */
+gf_status gf_ctx_destroy(gf_ctx *ctx);
+/* Message of the last failure on ctx (never NULL; "" if none). Valid until
+ * the next call on ctx. */
+const char *gf_last_error(const gf_ctx *ctx);
+
+/* Run a legacy program (Section 3.3): enqueue n_inst instances of `prog` on
+ * hip_stream in execution mode `mode`. With n_inst > 1 the instances run
+ * concurrently in one persistent launch, each on its own group of
+ * workgroups with group barriers (GF_EXEC_PERSISTENT), or as per-instance
+ * launches (per-region modes). launch may be NULL (tuning DB / defaults).
+ * stats (nullable) receives counts. Asynchronous: results are valid after
+ * the stream completes; call gf_sync to surface device errors. */
+gf_status gf_region_run(gf_ctx *ctx, const gf_program *prog, const gf_instance *inst,
+                        int32_t n_inst, int32_t mode, const gf_launch *launch,
+                        gf_run_stats *stats, void *hip_stream);
+
+/* A single reduction region over a device array: d_out[0] = op over
+ * d_in[0..n) (SUM: + ; MAX: max, F64 max starts from -infinity, unsigned
+ * from 0, I64 from INT64_MIN). U32 sums are widened: d_out is u64 for
+ * GF_U32/SUM and of type dt otherwise. F64 sums use a fixed two-pass tree
+ * (deterministic for a given n). n may be 0 (identity). */
+gf_status gf_reduce(gf_ctx *ctx, int32_t op, int32_t dt, const void *d_in, int64_t n,
+                    void *d_out, void *hip_stream);
+
+/* Service pending RPC requests in ticket (FIFO) order (Section 2.3: the
+ * host is the server of a synchronous client-server protocol): runs the
+ * landing pad of each request, writes its return value and marks it done.
+ * Waits up to timeout_us for the first request (0 = do not wait). Returns
+ * the number of requests serviced (>= 0) or a negative gf_status. */
+int32_t gf_rpc_poll(gf_ctx *ctx, int32_t max_requests, int32_t timeout_us);
+
+/* Register a printf format for device-side calls; sig lists the argument
+ * types: 'i' (64-bit int) or 'd' (double), e.g. "id". Returns id >= 0 or a
+ * negative gf_status. The host landing pad is selected by (callee, sig). */
+int32_t gf_rpc_register_format(gf_ctx *ctx, const char *fmt, const char *sig);
+
+/* Copy captured landing-pad output (rpc_capture=1) into buf (NUL-terminated,
+ * at most cap-1 bytes) and clear it. Returns bytes copied or gf_status. */
+int64_t gf_rpc_take_output(gf_ctx *ctx, char *buf, int64_t cap);
+
+/* Block until all work enqueued on hip_stream completes, service remaining
+ * posted RPCs, and surface the sticky device error word. */
+gf_status gf_sync(gf_ctx *ctx, void *hip_stream, gf_run_stats *stats);
+
+/* Persistent-launch capacity: co-resident workgroups of wg_size threads for
+ * the persistent kernel that would run `prog` (0 on error). */
+int32_t gf_persistent_capacity(gf_ctx *ctx, const gf_program *prog, int32_t wg_size);
+
+/* Device copy kernel (bandwidth probe for the HBM ceiling): d_dst = d_src,
+ * nbytes a multiple of 16. */
+gf_status gf_copy(gf_ctx *ctx, void *d_dst, const void *d_src, int64_t nbytes, int32_t num_wg,
+                  void *hip_stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

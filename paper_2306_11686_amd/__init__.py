@@ -1,0 +1,19 @@
+"""GPU-First execution of legacy loop programs on MI355X: Python binding.
+
+A thin ctypes layer over libgf.so (include/gf.h). Every step of a run
+executes in the library's HIP kernels; this module only marshals arguments.
+PyTorch supplies device memory (tensors) and streams. The library must be
+built (``python -m paper_2306_11686_amd.build``); importing the binding on a
+machine without it raises instead of falling back to anything else.
+"""
+from __future__ import annotations
+
+from .binding import (  # noqa: F401
+    GF_EXEC_PER_REGION, GF_EXEC_PERSISTENT, GF_EXEC_PER_REGION_GRAPH,
+    GF_OP_SUM, GF_OP_MAX, GF_OP_NONE, GF_F64, GF_U32, GF_U64, GF_I64,
+    GF_R_JACOBI2D, GF_R_JACOBI3D, GF_R_SPMV, GF_R_DOT, GF_R_AXPBY, GF_R_HIST, GF_R_OWNER,
+    GF_S_SET, GF_S_COPY, GF_S_DIV, GF_S_SQRT, GF_S_SWAP, GF_S_RECORD, GF_S_PRINTF,
+    GF_STEP_BLOCKING, GfError, Context, Step, Launch, Program, Instance, lib_path, load_library,
+    exported_symbols,
+)
+from . import programs  # noqa: F401

@@ -1,0 +1,249 @@
+"""ctypes marshalling for libgf.so; names and layouts mirror include/gf.h."""
+from __future__ import annotations
+
+import ctypes
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+_LIB_PATH = os.path.join(HERE, "libgf.so")
+
+GF_OK, GF_EINVAL, GF_ENOMEM, GF_EHIP, GF_ETIMEOUT, GF_ERPC, GF_EDEVICE, GF_EUNSUPPORTED = 0, -1, -2, -3, -4, -5, -6, -7
+_STATUS = {0: "GF_OK", -1: "GF_EINVAL", -2: "GF_ENOMEM", -3: "GF_EHIP", -4: "GF_ETIMEOUT", -5: "GF_ERPC",
+           -6: "GF_EDEVICE", -7: "GF_EUNSUPPORTED"}
+
+GF_OP_SUM, GF_OP_MAX, GF_OP_NONE = 0, 1, -1
+GF_F64, GF_U32, GF_U64, GF_I64 = 0, 1, 2, 3
+GF_EXEC_PER_REGION, GF_EXEC_PERSISTENT, GF_EXEC_PER_REGION_GRAPH = 0, 1, 2
+
+GF_R_JACOBI2D, GF_R_JACOBI3D, GF_R_SPMV, GF_R_DOT, GF_R_AXPBY, GF_R_HIST, GF_R_OWNER = 1, 2, 3, 4, 5, 6, 7
+GF_S_SET, GF_S_COPY, GF_S_DIV, GF_S_SQRT, GF_S_SWAP, GF_S_RECORD, GF_S_PRINTF = 32, 33, 34, 35, 36, 37, 38
+GF_STEP_BLOCKING = 1
+
+GF_MAX_ARRAYS = 16
+GF_MAX_SCALARS = 16
+GF_MAX_IPARAMS = 8
+
+
+class GfError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"{_STATUS.get(status, status)}: {msg}")
+        self.status = status
+
+
+class Step(ctypes.Structure):
+    _fields_ = [("kind", ctypes.c_int32), ("arr", ctypes.c_int32 * 5), ("sc", ctypes.c_int32 * 3),
+                ("red_op", ctypes.c_int32), ("np", ctypes.c_int32), ("every", ctypes.c_int32),
+                ("fmt_id", ctypes.c_int32), ("nargs", ctypes.c_int32), ("flags", ctypes.c_uint32),
+                ("mask", ctypes.c_uint32), ("chunk", ctypes.c_int64), ("c", ctypes.c_double)]
+
+    @classmethod
+    def make(cls, kind, arr=(), sc=(), red_op=GF_OP_NONE, np=0, every=0, fmt_id=0, nargs=0, flags=0,
+             mask=0, chunk=0, c=0.0):
+        s = cls()
+        s.kind = kind
+        for i in range(5):
+            s.arr[i] = arr[i] if i < len(arr) else -1
+        for i in range(3):
+            s.sc[i] = sc[i] if i < len(sc) else -1
+        s.red_op, s.np, s.every, s.fmt_id, s.nargs = red_op, np, every, fmt_id, nargs
+        s.flags, s.mask, s.chunk, s.c = flags, mask, chunk, float(c)
+        return s
+
+
+class Program(ctypes.Structure):
+    _fields_ = [("n_prologue", ctypes.c_int32), ("prologue", ctypes.POINTER(Step)),
+                ("n_body", ctypes.c_int32), ("body", ctypes.POINTER(Step)), ("iters", ctypes.c_int32)]
+
+    @classmethod
+    def make(cls, prologue, body, iters):
+        p = cls()
+        p._pro = (Step * max(1, len(prologue)))(*prologue)
+        p._body = (Step * max(1, len(body)))(*body)
+        p.n_prologue = len(prologue)
+        p.prologue = ctypes.cast(p._pro, ctypes.POINTER(Step))
+        p.n_body = len(body)
+        p.body = ctypes.cast(p._body, ctypes.POINTER(Step))
+        p.iters = iters
+        return p
+
+
+class Instance(ctypes.Structure):
+    _fields_ = [("arr", ctypes.c_void_p * GF_MAX_ARRAYS), ("scal", ctypes.c_void_p),
+                ("ip", ctypes.c_int64 * GF_MAX_IPARAMS)]
+
+    @classmethod
+    def make(cls, arrays: dict, scal_ptr: int, ip=()):
+        """arrays: {slot: device pointer (int) or a tensor}; scal_ptr: device pointer of 16 doubles."""
+        inst = cls()
+        for k, v in arrays.items():
+            inst.arr[k] = _ptr(v)
+        inst.scal = _ptr(scal_ptr)
+        for i, v in enumerate(ip):
+            inst.ip[i] = int(v)
+        return inst
+
+
+class Launch(ctypes.Structure):
+    _fields_ = [("wg_size", ctypes.c_int32), ("num_wg", ctypes.c_int32), ("tile_y", ctypes.c_int32),
+                ("tile_z", ctypes.c_int32), ("items", ctypes.c_int32), ("xcd_remap", ctypes.c_int32)]
+
+    @classmethod
+    def make(cls, wg_size=0, num_wg=0, tile_y=0, tile_z=0, items=0, xcd_remap=1):
+        return cls(wg_size, num_wg, tile_y, tile_z, items, xcd_remap)
+
+
+class RunStats(ctypes.Structure):
+    _fields_ = [("regions", ctypes.c_int32), ("launches", ctypes.c_int32), ("barriers", ctypes.c_int32),
+                ("num_wg", ctypes.c_int32), ("wg_size", ctypes.c_int32), ("rpc_posted", ctypes.c_int32)]
+
+    def as_dict(self):
+        return {f: getattr(self, f) for f, _ in self._fields_}
+
+
+class CtxOpts(ctypes.Structure):
+    _fields_ = [("rpc_slots", ctypes.c_int32), ("rpc_capture", ctypes.c_int32), ("rpc_thread", ctypes.c_int32),
+                ("rpc_timeout_us", ctypes.c_int64), ("barrier_timeout_us", ctypes.c_int64)]
+
+
+def _ptr(v) -> int:
+    if v is None:
+        return 0
+    if isinstance(v, int):
+        return v
+    if hasattr(v, "data_ptr"):
+        return v.data_ptr()
+    raise TypeError(f"cannot take a device pointer of {type(v)}")
+
+
+_lib = None
+
+# name -> (restype, argtypes); every function declared in include/gf.h
+_SIGS = {
+    "gf_ctx_create": (ctypes.c_int, [ctypes.c_int32, ctypes.POINTER(CtxOpts), ctypes.POINTER(ctypes.c_void_p)]),
+    "gf_ctx_destroy": (ctypes.c_int, [ctypes.c_void_p]),
+    "gf_last_error": (ctypes.c_char_p, [ctypes.c_void_p]),
+    "gf_region_run": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(Program), ctypes.POINTER(Instance),
+                                     ctypes.c_int32, ctypes.c_int32, ctypes.POINTER(Launch),
+                                     ctypes.POINTER(RunStats), ctypes.c_void_p]),
+    "gf_reduce": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_int32, ctypes.c_void_p, ctypes.c_int64,
+                                 ctypes.c_void_p, ctypes.c_void_p]),
+    "gf_rpc_poll": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_int32]),
+    "gf_rpc_register_format": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_char_p, ctypes.c_char_p]),
+    "gf_rpc_take_output": (ctypes.c_int64, [ctypes.c_void_p, ctypes.c_char_p, ctypes.c_int64]),
+    "gf_sync": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.POINTER(RunStats)]),
+    "gf_persistent_capacity": (ctypes.c_int32, [ctypes.c_void_p, ctypes.POINTER(Program), ctypes.c_int32]),
+    "gf_copy": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64, ctypes.c_int32,
+                               ctypes.c_void_p]),
+}
+
+
+def lib_path() -> str:
+    return _LIB_PATH
+
+
+def load_library():
+    """Load libgf.so (after torch, so both share torch's HIP runtime)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(_LIB_PATH):
+        raise RuntimeError(f"libgf.so is not built ({_LIB_PATH}); run python -m paper_2306_11686_amd.build")
+    import torch  # noqa: F401  -- binds the process to torch's HIP runtime first
+    lib = ctypes.CDLL(_LIB_PATH)
+    for name, (res, args) in _SIGS.items():
+        f = getattr(lib, name)
+        f.restype = res
+        f.argtypes = args
+    _lib = lib
+    return lib
+
+
+def exported_symbols():
+    return sorted(_SIGS)
+
+
+def _stream_handle(stream):
+    if stream is None:
+        import torch
+        return torch.cuda.current_stream().cuda_stream
+    if isinstance(stream, int):
+        return stream
+    return stream.cuda_stream
+
+
+class Context:
+    """One libgf context on a HIP device."""
+
+    def __init__(self, device: int = 0, rpc_slots: int = 0, rpc_capture: bool = False, rpc_thread: bool = False,
+                 rpc_timeout_us: int = 0, barrier_timeout_us: int = 0):
+        self.lib = load_library()
+        opts = CtxOpts(rpc_slots, 1 if rpc_capture else 0, 1 if rpc_thread else 0, rpc_timeout_us,
+                       barrier_timeout_us)
+        h = ctypes.c_void_p()
+        st = self.lib.gf_ctx_create(device, ctypes.byref(opts), ctypes.byref(h))
+        if st != GF_OK:
+            raise GfError(st, "gf_ctx_create failed")
+        self.h = h
+        self.device = device
+
+    def close(self):
+        if getattr(self, "h", None):
+            self.lib.gf_ctx_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()
+
+    def _check(self, st):
+        if st < 0:
+            raise GfError(st, self.lib.gf_last_error(self.h).decode())
+        return st
+
+    def last_error(self) -> str:
+        return self.lib.gf_last_error(self.h).decode()
+
+    def run(self, program: Program, instances, mode: int = GF_EXEC_PERSISTENT, launch: Launch | None = None,
+            stream=None) -> dict:
+        if isinstance(instances, Instance):
+            instances = [instances]
+        arr = (Instance * len(instances))(*instances)
+        stats = RunStats()
+        st = self.lib.gf_region_run(self.h, ctypes.byref(program), arr, len(instances), mode,
+                                    ctypes.byref(launch) if launch is not None else None, ctypes.byref(stats),
+                                    _stream_handle(stream))
+        self._check(st)
+        return stats.as_dict()
+
+    def reduce(self, op: int, dtype: int, d_in, n: int, d_out, stream=None):
+        self._check(self.lib.gf_reduce(self.h, op, dtype, _ptr(d_in), n, _ptr(d_out), _stream_handle(stream)))
+
+    def rpc_poll(self, max_requests: int = 1 << 20, timeout_us: int = 0) -> int:
+        return self._check(self.lib.gf_rpc_poll(self.h, max_requests, timeout_us))
+
+    def register_format(self, fmt: str, sig: str) -> int:
+        return self._check(self.lib.gf_rpc_register_format(self.h, fmt.encode(), sig.encode()))
+
+    def take_output(self, cap: int = 1 << 20) -> str:
+        buf = ctypes.create_string_buffer(cap)
+        self._check(self.lib.gf_rpc_take_output(self.h, buf, cap))
+        return buf.value.decode()
+
+    def sync(self, stream=None) -> dict:
+        stats = RunStats()
+        self._check(self.lib.gf_sync(self.h, _stream_handle(stream), ctypes.byref(stats)))
+        return stats.as_dict()
+
+    def capacity(self, program: Program, wg_size: int = 0) -> int:
+        return self.lib.gf_persistent_capacity(self.h, ctypes.byref(program), wg_size)
+
+    def copy(self, dst, src, nbytes: int, num_wg: int = 0, stream=None):
+        self._check(self.lib.gf_copy(self.h, _ptr(dst), _ptr(src), nbytes, num_wg, _stream_handle(stream)))

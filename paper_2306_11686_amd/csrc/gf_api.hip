@@ -1,0 +1,923 @@
+// gf_api.hip -- host runtime behind the C ABI declared in include/gf.h:
+// context and device scratch, program validation, the two execution modes
+// (persistent program kernel; one launch per region, optionally replayed
+// from a captured HIP graph), the stand-alone reduction, and the host side
+// of the RPC protocol (server loop and typed landing pads).
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <atomic>
+#include <chrono>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <mutex>
+#include <new>
+#include <string>
+#include <thread>
+#include <unordered_map>
+#include <utility>
+#include <vector>
+
+#include "gf_internal.h"
+
+using namespace gf;
+
+// ---------------------------------------------------------------------------
+// RPC landing pads (paper, Section 3.2): one non-variadic host wrapper per
+// argument-type signature of a variadic callee. The device sends opaque
+// 64-bit argument words; the pad reinterprets each by its signature letter
+// ('i' = 64-bit integer, 'd' = double) and makes the real call.
+// ---------------------------------------------------------------------------
+
+namespace {
+
+using Pad = int (*)(char *buf, size_t cap, const char *fmt, const uint64_t *a);
+
+template <typename T>
+T from_word(uint64_t w)
+{
+    if constexpr (std::is_same<T, double>::value) {
+        double d;
+        std::memcpy(&d, &w, sizeof d);
+        return d;
+    } else {
+        return (T)(int64_t)w;
+    }
+}
+
+template <typename... T>
+struct PrintfPad {
+    template <size_t... I>
+    static int call(char *buf, size_t cap, const char *fmt, const uint64_t *a, std::index_sequence<I...>)
+    {
+        return std::snprintf(buf, cap, fmt, from_word<T>(a[I])...);
+    }
+    static int pad(char *buf, size_t cap, const char *fmt, const uint64_t *a)
+    {
+        return call(buf, cap, fmt, a, std::index_sequence_for<T...>{});
+    }
+};
+
+template <int Depth, typename... T>
+void gen_pads(std::map<std::string, Pad> &m, const std::string &sig)
+{
+    m[sig] = &PrintfPad<T...>::pad;
+    if constexpr (Depth > 0) {
+        gen_pads<Depth - 1, T..., long long>(m, sig + "i");
+        gen_pads<Depth - 1, T..., double>(m, sig + "d");
+    }
+}
+
+const std::map<std::string, Pad> &printf_pads()
+{
+    static const std::map<std::string, Pad> m = [] {
+        std::map<std::string, Pad> t;
+        gen_pads<4>(t, "");
+        return t;
+    }();
+    return m;
+}
+
+struct Format {
+    std::string fmt;
+    std::string sig;
+    Pad pad;
+};
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// Context
+// ---------------------------------------------------------------------------
+
+struct GraphEntry {
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    gf_run_stats stats{};
+};
+
+struct gf_ctx {
+    int device = 0;
+    int num_cu = 0;
+    std::string err;
+
+    Scratch scr{};
+    void *d_scratch_lines = nullptr;
+
+    // RPC
+    RpcSlot *h_slots = nullptr;
+    RpcSlot *d_slots = nullptr;
+    uint64_t *d_ticket = nullptr;
+    uint32_t nslots = 0;
+    int64_t rpc_timeout_us = 0;
+    uint64_t next_ticket = 0;
+    std::mutex rpc_mu;
+    std::vector<Format> formats;
+    bool capture = false;
+    std::string captured;
+    std::atomic<int64_t> serviced{0};
+    std::thread server;
+    std::atomic<bool> stop{false};
+
+    hipStream_t capture_stream = nullptr;
+    std::unordered_map<std::string, GraphEntry> graphs;
+};
+
+namespace {
+
+gf_status fail(gf_ctx *ctx, gf_status st, const char *fmt, ...)
+{
+    if (ctx) {
+        char buf[512];
+        va_list ap;
+        va_start(ap, fmt);
+        std::vsnprintf(buf, sizeof buf, fmt, ap);
+        va_end(ap);
+        ctx->err = buf;
+    }
+    return st;
+}
+
+gf_status hipfail(gf_ctx *ctx, hipError_t e, const char *what)
+{
+    return fail(ctx, GF_EHIP, "%s: %s", what, hipGetErrorString(e));
+}
+
+RpcRing ring_of(const gf_ctx *ctx)
+{
+    RpcRing r;
+    r.slots = ctx->d_slots;
+    r.ticket = ctx->d_ticket;
+    r.mask = ctx->nslots - 1;
+    r.pad_ = 0;
+    r.timeout_ticks = ctx->rpc_timeout_us * 100;  // s_memrealtime runs at 100 MHz
+    return r;
+}
+
+int64_t now_us()
+{
+    return std::chrono::duration_cast<std::chrono::microseconds>(
+               std::chrono::steady_clock::now().time_since_epoch())
+        .count();
+}
+
+// Service requests; caller holds rpc_mu.
+int32_t poll_locked(gf_ctx *ctx, int32_t max_requests, int32_t timeout_us)
+{
+    int32_t done = 0;
+    const int64_t deadline = now_us() + (timeout_us > 0 ? timeout_us : 0);
+    char buf[1024];
+    while (done < max_requests) {
+        RpcSlot *slot = &ctx->h_slots[ctx->next_ticket & (ctx->nslots - 1)];
+        const uint64_t seq = __atomic_load_n(&slot->seq, __ATOMIC_ACQUIRE);
+        if (seq == ctx->next_ticket + 1) {
+            int64_t ret = -1;
+            if (slot->callee == kCalleePrintf && slot->fmt_id < ctx->formats.size()) {
+                const Format &f = ctx->formats[slot->fmt_id];
+                if (slot->nargs == f.sig.size()) {
+                    int k = f.pad(buf, sizeof buf, f.fmt.c_str(), slot->args);
+                    ret = k;
+                    if (k > 0) {
+                        const size_t len = std::min<size_t>((size_t)k, sizeof buf - 1);
+                        if (ctx->capture) {
+                            ctx->captured.append(buf, len);
+                        } else {
+                            std::fwrite(buf, 1, len, stdout);
+                            std::fflush(stdout);
+                        }
+                    }
+                }
+            }
+            slot->ret = ret;
+            __atomic_store_n(&slot->done, ctx->next_ticket + 1, __ATOMIC_RELEASE);
+            ++ctx->next_ticket;
+            ++done;
+            ctx->serviced.fetch_add(1);
+            continue;
+        }
+        if (done == 0 && now_us() < deadline) {
+            std::this_thread::yield();
+            continue;
+        }
+        break;
+    }
+    return done;
+}
+
+}  // namespace
+
+extern "C" {
+
+gf_status gf_ctx_create(int32_t hip_device, const gf_ctx_opts *opts, gf_ctx **out)
+{
+    if (!out)
+        return GF_EINVAL;
+    *out = nullptr;
+    gf_ctx *ctx = new (std::nothrow) gf_ctx();
+    if (!ctx)
+        return GF_ENOMEM;
+    gf_ctx_opts o{};
+    if (opts)
+        o = *opts;
+    hipError_t e = hipSetDevice(hip_device);
+    if (e != hipSuccess) {
+        delete ctx;
+        return GF_EHIP;
+    }
+    ctx->device = hip_device;
+    hipDeviceProp_t prop;
+    if (hipGetDeviceProperties(&prop, hip_device) != hipSuccess) {
+        delete ctx;
+        return GF_EHIP;
+    }
+    ctx->num_cu = prop.multiProcessorCount;
+
+    // device scratch: partials (two halves), counter lines, error word
+    const int64_t cap = 1 << 20;
+    const size_t part_bytes = 2 * cap * sizeof(double);
+    const size_t line_bytes = (size_t)kNumLines * 128;
+    const size_t total = part_bytes + line_bytes + 256;
+    char *base = nullptr;
+    if ((e = hipMalloc((void **)&base, total)) != hipSuccess) {
+        delete ctx;
+        return GF_ENOMEM;
+    }
+    ctx->d_scratch_lines = base;
+    if ((e = hipMemset(base + part_bytes, 0, line_bytes + 256)) != hipSuccess) {
+        hipFree(base);
+        delete ctx;
+        return GF_EHIP;
+    }
+    ctx->scr.partials = (double *)base;
+    ctx->scr.partials_cap = cap;
+    ctx->scr.lines = (uint32_t *)(base + part_bytes);
+    ctx->scr.error = (int32_t *)(base + part_bytes + line_bytes);
+    const int64_t btus = o.barrier_timeout_us > 0 ? o.barrier_timeout_us : 10 * 1000 * 1000;
+    ctx->scr.barrier_timeout_ticks = btus * 100;
+
+    // RPC ring
+    uint32_t ns = o.rpc_slots > 0 ? (uint32_t)o.rpc_slots : 256u;
+    if (ns < 8 || ns > 4096 || (ns & (ns - 1))) {
+        hipFree(base);
+        delete ctx;
+        return GF_EINVAL;
+    }
+    ctx->nslots = ns;
+    if ((e = hipHostMalloc((void **)&ctx->h_slots, ns * sizeof(RpcSlot), hipHostMallocCoherent | hipHostMallocMapped)) !=
+        hipSuccess) {
+        hipFree(base);
+        delete ctx;
+        return GF_ENOMEM;
+    }
+    std::memset(ctx->h_slots, 0, ns * sizeof(RpcSlot));
+    if (hipHostGetDevicePointer((void **)&ctx->d_slots, ctx->h_slots, 0) != hipSuccess)
+        ctx->d_slots = ctx->h_slots;
+    // the ticket counter lives in the last scratch line (device memory)
+    ctx->d_ticket = (uint64_t *)(base + part_bytes + line_bytes + 128);
+    ctx->rpc_timeout_us = o.rpc_timeout_us > 0 ? o.rpc_timeout_us : 2 * 1000 * 1000;
+    ctx->capture = o.rpc_capture != 0;
+    if (hipStreamCreateWithFlags(&ctx->capture_stream, hipStreamNonBlocking) != hipSuccess)
+        ctx->capture_stream = nullptr;
+    if (o.rpc_thread) {
+        ctx->server = std::thread([ctx] {
+            while (!ctx->stop.load()) {
+                int32_t k;
+                {
+                    std::lock_guard<std::mutex> g(ctx->rpc_mu);
+                    k = poll_locked(ctx, 1 << 20, 0);
+                }
+                if (k == 0)
+                    std::this_thread::sleep_for(std::chrono::microseconds(20));
+            }
+        });
+    }
+    *out = ctx;
+    return GF_OK;
+}
+
+gf_status gf_ctx_destroy(gf_ctx *ctx)
+{
+    if (!ctx)
+        return GF_OK;
+    hipSetDevice(ctx->device);
+    hipDeviceSynchronize();
+    if (ctx->server.joinable()) {
+        ctx->stop.store(true);
+        ctx->server.join();
+    }
+    for (auto &kv : ctx->graphs) {
+        if (kv.second.exec)
+            hipGraphExecDestroy(kv.second.exec);
+        if (kv.second.graph)
+            hipGraphDestroy(kv.second.graph);
+    }
+    if (ctx->capture_stream)
+        hipStreamDestroy(ctx->capture_stream);
+    if (ctx->h_slots)
+        hipHostFree(ctx->h_slots);
+    if (ctx->d_scratch_lines)
+        hipFree(ctx->d_scratch_lines);
+    delete ctx;
+    return GF_OK;
+}
+
+const char *gf_last_error(const gf_ctx *ctx)
+{
+    return ctx ? ctx->err.c_str() : "null context";
+}
+
+int32_t gf_rpc_register_format(gf_ctx *ctx, const char *fmt, const char *sig)
+{
+    if (!ctx || !fmt || !sig)
+        return GF_EINVAL;
+    auto it = printf_pads().find(sig);
+    if (it == printf_pads().end())
+        return fail(ctx, GF_EINVAL, "unsupported printf signature '%s' (up to 4 of 'i'/'d')", sig);
+    std::lock_guard<std::mutex> g(ctx->rpc_mu);
+    ctx->formats.push_back(Format{fmt, sig, it->second});
+    return (int32_t)ctx->formats.size() - 1;
+}
+
+int32_t gf_rpc_poll(gf_ctx *ctx, int32_t max_requests, int32_t timeout_us)
+{
+    if (!ctx || max_requests < 0)
+        return GF_EINVAL;
+    std::lock_guard<std::mutex> g(ctx->rpc_mu);
+    return poll_locked(ctx, max_requests, timeout_us);
+}
+
+int64_t gf_rpc_take_output(gf_ctx *ctx, char *buf, int64_t cap)
+{
+    if (!ctx || !buf || cap <= 0)
+        return GF_EINVAL;
+    std::lock_guard<std::mutex> g(ctx->rpc_mu);
+    const int64_t n = std::min<int64_t>((int64_t)ctx->captured.size(), cap - 1);
+    std::memcpy(buf, ctx->captured.data(), (size_t)n);
+    buf[n] = '\0';
+    ctx->captured.erase(0, (size_t)n);
+    return n;
+}
+
+}  // extern "C"
+
+// ---------------------------------------------------------------------------
+// Program validation and tiling
+// ---------------------------------------------------------------------------
+
+namespace {
+
+bool is_region(int k) { return k >= GF_R_JACOBI2D && k <= GF_R_OWNER; }
+bool is_serial(int k) { return k >= GF_S_SET && k <= GF_S_PRINTF; }
+
+int region_nops(int k)
+{
+    switch (k) {
+    case GF_R_JACOBI2D:
+    case GF_R_JACOBI3D:
+        return 2;
+    case GF_R_SPMV:
+        return 5;
+    case GF_R_DOT:
+        return 2;
+    case GF_R_AXPBY:
+        return 3;
+    case GF_R_HIST:
+        return 2;
+    case GF_R_OWNER:
+        return 1;
+    default:
+        return 0;
+    }
+}
+
+gf_status check_step(gf_ctx *ctx, const gf_step &s, int idx)
+{
+    auto slot_ok = [](int a) { return a >= 0 && a < GF_MAX_ARRAYS; };
+    auto sc_ok = [](int a) { return a >= 0 && a < GF_MAX_SCALARS; };
+    if (is_region(s.kind)) {
+        for (int k = 0; k < region_nops(s.kind); ++k)
+            if (!slot_ok(s.arr[k]))
+                return fail(ctx, GF_EINVAL, "step %d: array operand %d out of range", idx, k);
+        if (s.np < 0 || s.np >= GF_MAX_IPARAMS)
+            return fail(ctx, GF_EINVAL, "step %d: size index out of range", idx);
+        int allowed = GF_OP_NONE;
+        if (s.kind == GF_R_JACOBI2D || s.kind == GF_R_DOT)
+            allowed = GF_OP_SUM;
+        if (s.kind == GF_R_JACOBI3D)
+            allowed = GF_OP_MAX;
+        if (s.red_op != GF_OP_NONE && s.red_op != allowed)
+            return fail(ctx, GF_EINVAL, "step %d: reduction op %d not defined for region kind %d", idx, s.red_op,
+                        s.kind);
+        if (s.kind == GF_R_DOT && s.red_op == GF_OP_NONE)
+            return fail(ctx, GF_EINVAL, "step %d: DOT needs reduction(+)", idx);
+        if (s.red_op != GF_OP_NONE && !sc_ok(s.sc[0]))
+            return fail(ctx, GF_EINVAL, "step %d: reduction target out of range", idx);
+        if (s.kind == GF_R_AXPBY && !sc_ok(s.sc[1]))
+            return fail(ctx, GF_EINVAL, "step %d: AXPBY coefficient slot out of range", idx);
+        if (s.kind == GF_R_HIST && (s.mask & (s.mask + 1u)) != 0)
+            return fail(ctx, GF_EINVAL, "step %d: histogram mask must be 2^k - 1", idx);
+        if (s.kind == GF_R_OWNER && s.chunk < 0)
+            return fail(ctx, GF_EINVAL, "step %d: negative chunk", idx);
+        return GF_OK;
+    }
+    if (!is_serial(s.kind))
+        return fail(ctx, GF_EINVAL, "step %d: unknown kind %d", idx, s.kind);
+    switch (s.kind) {
+    case GF_S_SET:
+        if (!sc_ok(s.sc[0]))
+            return fail(ctx, GF_EINVAL, "step %d: scalar slot out of range", idx);
+        break;
+    case GF_S_COPY:
+    case GF_S_SQRT:
+        if (!sc_ok(s.sc[0]) || !sc_ok(s.sc[1]))
+            return fail(ctx, GF_EINVAL, "step %d: scalar slot out of range", idx);
+        break;
+    case GF_S_DIV:
+        if (!sc_ok(s.sc[0]) || !sc_ok(s.sc[1]) || !sc_ok(s.sc[2]))
+            return fail(ctx, GF_EINVAL, "step %d: scalar slot out of range", idx);
+        break;
+    case GF_S_SWAP:
+        if (!slot_ok(s.arr[0]) || !slot_ok(s.arr[1]))
+            return fail(ctx, GF_EINVAL, "step %d: swap slot out of range", idx);
+        break;
+    case GF_S_RECORD:
+        if (!slot_ok(s.arr[0]) || !sc_ok(s.sc[0]))
+            return fail(ctx, GF_EINVAL, "step %d: record operand out of range", idx);
+        break;
+    case GF_S_PRINTF: {
+        if (s.every < 1 || s.nargs < 1 || s.nargs > 4)
+            return fail(ctx, GF_EINVAL, "step %d: printf needs every >= 1 and 1..4 arguments", idx);
+        std::lock_guard<std::mutex> g(ctx->rpc_mu);
+        if (s.fmt_id < 0 || s.fmt_id >= (int)ctx->formats.size())
+            return fail(ctx, GF_EINVAL, "step %d: unregistered format id %d", idx, s.fmt_id);
+        const std::string &sig = ctx->formats[s.fmt_id].sig;
+        if ((int)sig.size() != s.nargs || sig[0] != 'i')
+            return fail(ctx, GF_EINVAL, "step %d: format signature '%s' does not match (int iter, %d doubles)", idx,
+                        sig.c_str(), s.nargs - 1);
+        for (size_t k = 1; k < sig.size(); ++k)
+            if (sig[k] != 'd' || !sc_ok(s.sc[k - 1]))
+                return fail(ctx, GF_EINVAL, "step %d: printf argument %zu must be a scalar variable", idx, k);
+        break;
+    }
+    default:
+        break;
+    }
+    return GF_OK;
+}
+
+DStep to_dev(const gf_step &s)
+{
+    DStep d;
+    std::memset(&d, 0, sizeof d);
+    d.kind = s.kind;
+    for (int k = 0; k < 5; ++k)
+        d.arr[k] = s.arr[k];
+    for (int k = 0; k < 3; ++k)
+        d.sc[k] = s.sc[k];
+    d.red_op = is_region(s.kind) ? s.red_op : GF_OP_NONE;
+    d.np = s.np;
+    d.every = s.every;
+    d.fmt_id = s.fmt_id;
+    d.nargs = s.nargs;
+    d.flags = s.flags;
+    d.mask = s.mask;
+    d.chunk = s.chunk;
+    d.c = s.c;
+    // operands a kind does not use are marked absent
+    if (is_region(s.kind))
+        for (int k = region_nops(s.kind); k < 5; ++k)
+            d.arr[k] = -1;
+    return d;
+}
+
+unsigned program_region_mask(const DProg &p)
+{
+    unsigned m = 0;
+    for (int i = 0; i < p.n_steps; ++i)
+        if (is_region(p.steps[i].kind))
+            m |= 1u << p.steps[i].kind;
+    return m;
+}
+
+// Defaults: 3D stencil 256-wide rows x 8 rows x 64-plane segments; 2D
+// stencil single-row tiles (the 2D grid is small and latency-bound);
+// streaming regions 4 elements per thread.
+Tiling choose_tiling(const DProg &p, const gf_launch *l)
+{
+    Tiling t;
+    std::memset(&t, 0, sizeof t);
+    const unsigned m = program_region_mask(p);
+    t.wg_size = 256;
+    t.tile_y = (m & (1u << GF_R_JACOBI3D)) ? 8 : ((m & (1u << GF_R_JACOBI2D)) ? 1 : 1);
+    t.tile_z = 64;
+    t.items = 4;
+    t.xcd_remap = 1;
+    if (l) {
+        if (l->wg_size)
+            t.wg_size = l->wg_size;
+        if (l->tile_y)
+            t.tile_y = l->tile_y;
+        if (l->tile_z)
+            t.tile_z = l->tile_z;
+        if (l->items)
+            t.items = l->items;
+        t.xcd_remap = l->xcd_remap;
+    }
+    return t;
+}
+
+gf_status check_tiling(gf_ctx *ctx, const Tiling &t)
+{
+    if (t.wg_size < 64 || t.wg_size > 256 || (t.wg_size % 64))
+        return fail(ctx, GF_EINVAL, "wg_size must be 64, 128, 192 or 256");
+    if (!(t.tile_y == 1 || t.tile_y == 2 || t.tile_y == 4 || t.tile_y == 8 || t.tile_y == 16))
+        return fail(ctx, GF_EINVAL, "tile_y must be 1, 2, 4, 8 or 16");
+    if (t.tile_z < 1 || t.tile_z > 1 << 20)
+        return fail(ctx, GF_EINVAL, "tile_z out of range");
+    if (t.items < 1 || t.items > 64)
+        return fail(ctx, GF_EINVAL, "items must be 1..64");
+    return GF_OK;
+}
+
+gf_status build_program(gf_ctx *ctx, const gf_program *prog, DProg *out)
+{
+    if (!prog)
+        return fail(ctx, GF_EINVAL, "null program");
+    if (prog->n_prologue < 0 || prog->n_body < 0 || prog->iters < 0)
+        return fail(ctx, GF_EINVAL, "negative program counts");
+    if (prog->n_prologue + prog->n_body > kMaxDevSteps)
+        return fail(ctx, GF_EINVAL, "program has %d steps; at most %d", prog->n_prologue + prog->n_body,
+                    kMaxDevSteps);
+    if ((prog->n_prologue && !prog->prologue) || (prog->n_body && !prog->body))
+        return fail(ctx, GF_EINVAL, "null step array");
+    if (prog->iters > 0 && prog->n_body == 0)
+        return fail(ctx, GF_EINVAL, "iters > 0 with an empty body");
+    std::memset(out, 0, sizeof *out);
+    out->n_pro = prog->n_prologue;
+    out->n_body = prog->n_body;
+    out->iters = prog->iters;
+    out->n_steps = prog->n_prologue + prog->n_body;
+    for (int i = 0; i < out->n_steps; ++i) {
+        const gf_step &s = i < prog->n_prologue ? prog->prologue[i] : prog->body[i - prog->n_prologue];
+        gf_status st = check_step(ctx, s, i);
+        if (st != GF_OK)
+            return st;
+        out->steps[i] = to_dev(s);
+    }
+    return GF_OK;
+}
+
+gf_status check_instance(gf_ctx *ctx, const DProg &p, const gf_instance &in, const Tiling &t, int idx)
+{
+    if (!in.scal)
+        return fail(ctx, GF_EINVAL, "instance %d: null scalar array", idx);
+    for (int i = 0; i < p.n_steps; ++i) {
+        const DStep &s = p.steps[i];
+        if (is_region(s.kind)) {
+            for (int k = 0; k < region_nops(s.kind); ++k)
+                if (!in.arr[s.arr[k]])
+                    return fail(ctx, GF_EINVAL, "instance %d step %d: null array in slot %d", idx, i, s.arr[k]);
+            const int64_t n = in.ip[s.np];
+            if (n < 0)
+                return fail(ctx, GF_EINVAL, "instance %d step %d: negative size", idx, i);
+            if ((s.kind == GF_R_JACOBI2D || s.kind == GF_R_JACOBI3D) && n > (1 << 20))
+                return fail(ctx, GF_EINVAL, "instance %d step %d: grid side too large", idx, i);
+            if (s.kind == GF_R_OWNER && n > INT32_MAX)
+                return fail(ctx, GF_EINVAL, "instance %d step %d: owner map larger than int32", idx, i);
+            if (s.red_op != GF_OP_NONE && region_items(s, n, t) > ctx->scr.partials_cap)
+                return fail(ctx, GF_EINVAL, "instance %d step %d: %lld reduction tiles exceed the partials capacity",
+                            idx, i, (long long)region_items(s, n, t));
+        } else if (s.kind == GF_S_SWAP || s.kind == GF_S_RECORD) {
+            if (!in.arr[s.arr[0]] || (s.kind == GF_S_SWAP && !in.arr[s.arr[1]]))
+                return fail(ctx, GF_EINVAL, "instance %d step %d: null array slot", idx, i);
+        }
+    }
+    return GF_OK;
+}
+
+int64_t max_items(const DProg &p, const gf_instance &in, const Tiling &t)
+{
+    int64_t m = 1;
+    for (int i = 0; i < p.n_steps; ++i)
+        if (is_region(p.steps[i].kind))
+            m = std::max<int64_t>(m, region_items(p.steps[i], in.ip[p.steps[i].np], t));
+    return m;
+}
+
+// Grid of a per-region launch: one workgroup per work item up to 16 per CU.
+int region_grid(const gf_ctx *ctx, const DStep &s, int64_t items, const Tiling &t)
+{
+    if (s.kind == GF_R_OWNER)
+        return std::max(1, ctx->num_cu);
+    const int64_t cap = (int64_t)ctx->num_cu * 16;
+    return (int)std::max<int64_t>(1, std::min<int64_t>(items, cap));
+}
+
+// Walk the flattened step sequence of one instance, enqueueing one launch per
+// region; the serial steps that follow a region ride along as its glue (run
+// by its last workgroup); SWAPs are applied to the host's binding table.
+gf_status enqueue_per_region(gf_ctx *ctx, const DProg &p, const gf_instance &in, int inst_idx, const Tiling &t,
+                             const gf_launch *l, hipStream_t stream, gf_run_stats *stats)
+{
+    void *arr[GF_MAX_ARRAYS];
+    std::memcpy(arr, in.arr, sizeof arr);
+    const RpcRing rpc = ring_of(ctx);
+    RegionLaunch cur;
+    bool pending = false;
+    int launches = 0, regions = 0, max_grid = 0;
+
+    auto flush = [&]() -> gf_status {
+        if (!pending)
+            return GF_OK;
+        int grid = 1;
+        if (is_region(cur.step.kind)) {
+            grid = region_grid(ctx, cur.step, cur.n_items, t);
+            if (l && l->num_wg > 0)
+                grid = l->num_wg;
+        }
+        hipError_t e = launch_region(cur, t, grid, ctx->scr, rpc, stream);
+        if (e != hipSuccess)
+            return hipfail(ctx, e, "region launch");
+        ++launches;
+        max_grid = std::max(max_grid, grid);
+        pending = false;
+        return GF_OK;
+    };
+    auto start_serial_only = [&]() {
+        std::memset(&cur, 0, sizeof cur);
+        cur.step.kind = 0;
+        cur.step.red_op = GF_OP_NONE;
+        for (int k = 0; k < 5; ++k)
+            cur.step.arr[k] = -1;
+        cur.scal = in.scal;
+        cur.inst = inst_idx;
+        pending = true;
+    };
+
+    const int64_t total = (int64_t)p.n_pro + (int64_t)p.iters * p.n_body;
+    for (int64_t si = 0; si < total; ++si) {
+        int sidx;
+        int32_t iter;
+        if (si < p.n_pro) {
+            sidx = (int)si;
+            iter = -1;
+        } else {
+            const int64_t k = si - p.n_pro;
+            sidx = p.n_pro + (int)(k % p.n_body);
+            iter = (int32_t)(k / p.n_body);
+        }
+        const DStep &s = p.steps[sidx];
+        if (is_region(s.kind)) {
+            gf_status st = flush();
+            if (st != GF_OK)
+                return st;
+            std::memset(&cur, 0, sizeof cur);
+            cur.step = s;
+            for (int k = 0; k < 5; ++k)
+                cur.arr[k] = s.arr[k] >= 0 ? arr[s.arr[k]] : nullptr;
+            cur.scal = in.scal;
+            cur.n = in.ip[s.np];
+            cur.n_items = (int32_t)region_items(s, cur.n, t);
+            cur.inst = inst_idx;
+            pending = true;
+            ++regions;
+        } else if (s.kind == GF_S_SWAP) {
+            std::swap(arr[s.arr[0]], arr[s.arr[1]]);
+        } else {
+            if (!pending || cur.n_glue == kMaxGlue) {
+                gf_status st = flush();
+                if (st != GF_OK)
+                    return st;
+                start_serial_only();
+            }
+            Glue &g = cur.glue[cur.n_glue++];
+            std::memset(&g, 0, sizeof g);
+            g.kind = s.kind;
+            for (int k = 0; k < 3; ++k)
+                g.sc[k] = s.sc[k];
+            g.every = s.every;
+            g.fmt_id = s.fmt_id;
+            g.nargs = s.nargs;
+            g.iter = iter;
+            g.flags = s.flags;
+            g.c = s.c;
+            g.rec = s.kind == GF_S_RECORD ? (double *)arr[s.arr[0]] : nullptr;
+        }
+    }
+    gf_status st = flush();
+    if (st != GF_OK)
+        return st;
+    if (stats) {
+        stats->regions += regions;
+        stats->launches += launches;
+        stats->num_wg = std::max(stats->num_wg, max_grid);
+        stats->wg_size = t.wg_size;
+    }
+    return GF_OK;
+}
+
+std::string graph_key(const DProg &p, const gf_instance *inst, int n_inst, const Tiling &t, const gf_launch *l,
+                      hipStream_t s)
+{
+    std::string k;
+    k.append((const char *)&p, sizeof p);
+    k.append((const char *)inst, sizeof(gf_instance) * (size_t)n_inst);
+    k.append((const char *)&t, sizeof t);
+    const int32_t nwg = l ? l->num_wg : 0;
+    k.append((const char *)&nwg, sizeof nwg);
+    k.append((const char *)&s, sizeof s);
+    return k;
+}
+
+}  // namespace
+
+extern "C" {
+
+int32_t gf_persistent_capacity(gf_ctx *ctx, const gf_program *prog, int32_t wg_size)
+{
+    if (!ctx)
+        return 0;
+    DProg p;
+    if (build_program(ctx, prog, &p) != GF_OK)
+        return 0;
+    gf_launch l{};
+    l.wg_size = wg_size;
+    Tiling t = choose_tiling(p, wg_size > 0 ? &l : nullptr);
+    if (check_tiling(ctx, t) != GF_OK)
+        return 0;
+    hipSetDevice(ctx->device);
+    return persistent_capacity(p, t, ctx->num_cu);
+}
+
+gf_status gf_region_run(gf_ctx *ctx, const gf_program *prog, const gf_instance *inst, int32_t n_inst, int32_t mode,
+                        const gf_launch *launch, gf_run_stats *stats, void *hip_stream)
+{
+    if (!ctx)
+        return GF_EINVAL;
+    if (!inst || n_inst < 1 || n_inst > GF_MAX_INSTANCES)
+        return fail(ctx, GF_EINVAL, "need 1..%d instances", GF_MAX_INSTANCES);
+    if (mode != GF_EXEC_PER_REGION && mode != GF_EXEC_PERSISTENT && mode != GF_EXEC_PER_REGION_GRAPH)
+        return fail(ctx, GF_EINVAL, "unknown execution mode %d", mode);
+    DProg p;
+    gf_status st = build_program(ctx, prog, &p);
+    if (st != GF_OK)
+        return st;
+    Tiling t = choose_tiling(p, launch);
+    if ((st = check_tiling(ctx, t)) != GF_OK)
+        return st;
+    for (int i = 0; i < n_inst; ++i)
+        if ((st = check_instance(ctx, p, inst[i], t, i)) != GF_OK)
+            return st;
+    hipSetDevice(ctx->device);
+    hipStream_t stream = (hipStream_t)hip_stream;
+    if (stats)
+        std::memset(stats, 0, sizeof *stats);
+
+    if (mode == GF_EXEC_PERSISTENT) {
+        const int cap = persistent_capacity(p, t, ctx->num_cu);
+        if (cap <= 0)
+            return fail(ctx, GF_EHIP, "occupancy query failed");
+        for (int i = 0; i < n_inst; ++i) {
+            int grid = (int)std::min<int64_t>(cap, max_items(p, inst[i], t));
+            if (launch && launch->num_wg > 0) {
+                if (launch->num_wg > cap)
+                    return fail(ctx, GF_EINVAL, "num_wg %d exceeds the co-resident capacity %d", launch->num_wg, cap);
+                grid = launch->num_wg;
+            }
+            DInst di;
+            std::memcpy(di.arr, inst[i].arr, sizeof di.arr);
+            di.scal = inst[i].scal;
+            std::memcpy(di.ip, inst[i].ip, sizeof di.ip);
+            hipError_t e = launch_persistent(p, di, t, grid, ctx->scr, ring_of(ctx), stream);
+            if (e != hipSuccess)
+                return hipfail(ctx, e, "persistent launch");
+            if (stats) {
+                stats->launches += 1;
+                stats->num_wg = std::max(stats->num_wg, grid);
+                stats->wg_size = t.wg_size;
+                int nreg = 0;
+                for (int k = 0; k < p.n_pro; ++k)
+                    nreg += is_region(p.steps[k].kind);
+                int nbody = 0;
+                for (int k = p.n_pro; k < p.n_steps; ++k)
+                    nbody += is_region(p.steps[k].kind);
+                stats->regions += nreg + nbody * p.iters;
+                stats->barriers = nreg + nbody * p.iters;
+            }
+        }
+        return GF_OK;
+    }
+
+    if (mode == GF_EXEC_PER_REGION) {
+        for (int i = 0; i < n_inst; ++i)
+            if ((st = enqueue_per_region(ctx, p, inst[i], i, t, launch, stream, stats)) != GF_OK)
+                return st;
+        return GF_OK;
+    }
+
+    // GF_EXEC_PER_REGION_GRAPH: capture the per-region launch sequence once
+    // per (program, bindings, tiling, stream) and replay it.
+    const std::string key = graph_key(p, inst, n_inst, t, launch, stream);
+    auto it = ctx->graphs.find(key);
+    if (it == ctx->graphs.end()) {
+        hipStream_t cs = ctx->capture_stream;
+        if (!cs)
+            return fail(ctx, GF_EHIP, "no capture stream");
+        hipError_t e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
+        if (e != hipSuccess)
+            return hipfail(ctx, e, "begin capture");
+        gf_run_stats tmp{};
+        for (int i = 0; i < n_inst && st == GF_OK; ++i)
+            st = enqueue_per_region(ctx, p, inst[i], i, t, launch, cs, &tmp);
+        hipGraph_t g = nullptr;
+        e = hipStreamEndCapture(cs, &g);
+        if (st != GF_OK) {
+            if (g)
+                hipGraphDestroy(g);
+            return st;
+        }
+        if (e != hipSuccess)
+            return hipfail(ctx, e, "end capture");
+        GraphEntry ge;
+        ge.graph = g;
+        ge.stats = tmp;
+        e = hipGraphInstantiate(&ge.exec, g, nullptr, nullptr, 0);
+        if (e != hipSuccess) {
+            hipGraphDestroy(g);
+            return hipfail(ctx, e, "graph instantiate");
+        }
+        it = ctx->graphs.emplace(key, ge).first;
+    }
+    if (stats)
+        *stats = it->second.stats;
+    hipError_t e = hipGraphLaunch(it->second.exec, stream);
+    if (e != hipSuccess)
+        return hipfail(ctx, e, "graph launch");
+    return GF_OK;
+}
+
+gf_status gf_reduce(gf_ctx *ctx, int32_t op, int32_t dt, const void *d_in, int64_t n, void *d_out, void *hip_stream)
+{
+    if (!ctx)
+        return GF_EINVAL;
+    if (op != GF_OP_SUM && op != GF_OP_MAX)
+        return fail(ctx, GF_EINVAL, "unknown reduction op %d", op);
+    if (dt < GF_F64 || dt > GF_I64)
+        return fail(ctx, GF_EINVAL, "unknown dtype %d", dt);
+    if (n < 0 || (n > 0 && !d_in) || !d_out)
+        return fail(ctx, GF_EINVAL, "bad reduction arguments");
+    hipSetDevice(ctx->device);
+    hipError_t e = launch_reduce(op, dt, d_in, n, d_out, ctx->scr, ctx->num_cu, (hipStream_t)hip_stream);
+    if (e != hipSuccess)
+        return hipfail(ctx, e, "reduce launch");
+    return GF_OK;
+}
+
+gf_status gf_copy(gf_ctx *ctx, void *d_dst, const void *d_src, int64_t nbytes, int32_t num_wg, void *hip_stream)
+{
+    if (!ctx)
+        return GF_EINVAL;
+    if (!d_dst || !d_src || nbytes < 0 || (nbytes % 16))
+        return fail(ctx, GF_EINVAL, "copy needs non-null buffers and a multiple of 16 bytes");
+    if (num_wg <= 0)
+        num_wg = ctx->num_cu * 8;
+    hipSetDevice(ctx->device);
+    hipError_t e = launch_copy(d_dst, d_src, nbytes, num_wg, (hipStream_t)hip_stream);
+    if (e != hipSuccess)
+        return hipfail(ctx, e, "copy launch");
+    return GF_OK;
+}
+
+gf_status gf_sync(gf_ctx *ctx, void *hip_stream, gf_run_stats *stats)
+{
+    if (!ctx)
+        return GF_EINVAL;
+    hipSetDevice(ctx->device);
+    hipError_t e = hipStreamSynchronize((hipStream_t)hip_stream);
+    {
+        std::lock_guard<std::mutex> g(ctx->rpc_mu);
+        while (poll_locked(ctx, 1 << 20, 0) > 0) {
+        }
+    }
+    if (stats)
+        stats->rpc_posted = (int32_t)ctx->serviced.load();
+    if (e != hipSuccess)
+        return hipfail(ctx, e, "stream synchronize");
+    int32_t code = 0;
+    if ((e = hipMemcpy(&code, ctx->scr.error, sizeof code, hipMemcpyDeviceToHost)) != hipSuccess)
+        return hipfail(ctx, e, "error word read");
+    if (code != kErrNone) {
+        const int32_t zero = 0;
+        hipMemcpy(ctx->scr.error, &zero, sizeof zero, hipMemcpyHostToDevice);
+        if (code == kErrBarrierTimeout)
+            return fail(ctx, GF_ETIMEOUT, "device: grid barrier watchdog expired");
+        if (code == kErrRpcTimeout)
+            return fail(ctx, GF_ETIMEOUT, "device: RPC wait watchdog expired (is a server polling?)");
+        return fail(ctx, GF_EDEVICE, "device error code %d", code);
+    }
+    return GF_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,233 @@
+// gf_device.h -- device building blocks: wavefront/workgroup reductions,
+// the cross-workgroup barrier, the static worksharing formula and the RPC
+// client. Included only by gf_kernels.hip.
+#pragma once
+
+#include <math.h>
+
+#include "gf_internal.h"
+
+namespace gf {
+
+// ---------------------------------------------------------------------------
+// Reductions. The paper leaves reduction clauses unrewritten (Section 4.3);
+// they follow OpenMP: identity-initialised private copies, combined with the
+// original value. A butterfly over the wavefront gives every lane the same
+// bits (each level adds the same two partials, commutatively), so the tree
+// is deterministic for a fixed workgroup size.
+// ---------------------------------------------------------------------------
+
+template <int OP>
+struct RedOp;
+template <>
+struct RedOp<GF_OP_SUM> {
+    static __device__ __forceinline__ double identity() { return 0.0; }
+    static __device__ __forceinline__ double apply(double a, double b) { return a + b; }
+};
+template <>
+struct RedOp<GF_OP_MAX> {
+    static __device__ __forceinline__ double identity() { return -INFINITY; }
+    static __device__ __forceinline__ double apply(double a, double b) { return a > b ? a : b; }
+};
+
+__device__ __forceinline__ double red_identity(int op) { return op == GF_OP_MAX ? -INFINITY : 0.0; }
+__device__ __forceinline__ double red_apply(int op, double a, double b)
+{
+    return op == GF_OP_MAX ? (a > b ? a : b) : a + b;
+}
+
+template <int OP>
+__device__ __forceinline__ double wave_reduce(double v)
+{
+#pragma unroll
+    for (int off = kWave / 2; off > 0; off >>= 1)
+        v = RedOp<OP>::apply(v, __shfl_xor(v, off, kWave));
+    return v;
+}
+
+// Workgroup reduction; the result is valid in thread 0. `lds` holds at least
+// blockDim.x / 64 doubles. Every thread of the workgroup must call it.
+template <int OP>
+__device__ __forceinline__ double block_reduce(double v, double *lds)
+{
+    v = wave_reduce<OP>(v);
+    const int lane = threadIdx.x & (kWave - 1);
+    const int wid = threadIdx.x / kWave;
+    const int nw = blockDim.x / kWave;
+    if (lane == 0)
+        lds[wid] = v;
+    __syncthreads();
+    if (wid == 0) {
+        v = lane < nw ? lds[lane] : RedOp<OP>::identity();
+        v = wave_reduce<OP>(v);
+    }
+    __syncthreads();
+    return v;
+}
+
+__device__ __forceinline__ double block_reduce_rt(int op, double v, double *lds)
+{
+    return op == GF_OP_MAX ? block_reduce<GF_OP_MAX>(v, lds) : block_reduce<GF_OP_SUM>(v, lds);
+}
+
+// Reduce p[0..n) in a fixed order (strided per thread, then the workgroup
+// tree). Every workgroup that calls this on the same data with the same
+// blockDim gets the same bits; the result is valid in thread 0.
+__device__ __forceinline__ double reduce_partials(int op, const double *p, int64_t n, double *lds)
+{
+    double acc = red_identity(op);
+    for (int64_t i = threadIdx.x; i < n; i += blockDim.x)
+        acc = red_apply(op, acc, p[i]);
+    return block_reduce_rt(op, acc, lds);
+}
+
+// ---------------------------------------------------------------------------
+// Sticky error word and time.
+// ---------------------------------------------------------------------------
+
+__device__ __forceinline__ void set_error(int32_t *err, int32_t code)
+{
+    int32_t expected = kErrNone;
+    __hip_atomic_compare_exchange_strong(err, &expected, code, __ATOMIC_RELAXED, __ATOMIC_RELAXED,
+                                         __HIP_MEMORY_SCOPE_AGENT);
+}
+
+__device__ __forceinline__ int32_t read_error(const int32_t *err)
+{
+    return __hip_atomic_load(err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+__device__ __forceinline__ uint64_t now_ticks() { return __builtin_amdgcn_s_memrealtime(); }
+
+// ---------------------------------------------------------------------------
+// Cross-workgroup barrier (paper, Section 3.3: an `omp barrier` inside a
+// multi-team region becomes a barrier over all teams built on global atomic
+// counters). Generation-counting barrier on one 128-byte line: word 0 counts
+// arrivals, word 1 is the generation. Each wavefront first publishes its own
+// stores at agent scope (a plain __syncthreads does not wait for stores);
+// thread 0 arrives, the last arrival resets the count and bumps the
+// generation, the others spin with relaxed agent-scope loads and s_sleep,
+// then acquire. A watchdog turns a stuck barrier into a sticky error and a
+// clean exit instead of a hang. Returns false if the kernel must stop.
+// ---------------------------------------------------------------------------
+
+struct BarrierState {
+    uint32_t gen;
+    int32_t ok;
+};
+
+__device__ __forceinline__ bool group_barrier(uint32_t *line, uint32_t nblocks, BarrierState *bs,
+                                              int32_t *err, int64_t timeout_ticks)
+{
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        const uint32_t g = bs->gen;
+        int32_t ok = 1;
+        const uint32_t arrived = __hip_atomic_fetch_add(&line[0], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        if (arrived == nblocks - 1) {
+            __hip_atomic_store(&line[0], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            __hip_atomic_store(&line[1], g + 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+        } else {
+            const uint64_t t0 = now_ticks();
+            uint32_t spins = 0;
+            while (__hip_atomic_load(&line[1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == g) {
+                __builtin_amdgcn_s_sleep(1);
+                if ((++spins & 63u) == 0) {
+                    if (read_error(err) != kErrNone) {
+                        ok = 0;
+                        break;
+                    }
+                    if ((int64_t)(now_ticks() - t0) > timeout_ticks) {
+                        set_error(err, kErrBarrierTimeout);
+                        ok = 0;
+                        break;
+                    }
+                }
+            }
+        }
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+        bs->gen = g + 1u;
+        bs->ok = ok;
+    }
+    __syncthreads();
+    return bs->ok != 0;
+}
+
+// Logical worker id of workgroup `wg` among `nwg`: workgroups are dispatched
+// round-robin over the 8 XCDs (each with its own L2), so with remapping the
+// workers of one XCD get consecutive ids and hence neighbouring tiles.
+__device__ __forceinline__ int64_t worker_id(int64_t wg, int64_t nwg, int remap)
+{
+    if (!remap || nwg < kNumXcd)
+        return wg;
+    const int64_t per = nwg / kNumXcd;
+    const int64_t full = per * kNumXcd;
+    if (wg >= full)
+        return wg;
+    return (wg % kNumXcd) * per + wg / kNumXcd;
+}
+
+// ---------------------------------------------------------------------------
+// Static worksharing with continuous global thread ids (Section 3.3): thread
+// t of T owns [t*q + min(t,r), (t+1)*q + min(t+1,r)) with q = n / T,
+// r = n % T for schedule(static), or chunks c, c+T*c, ... for
+// schedule(static, c).
+// ---------------------------------------------------------------------------
+
+__device__ __forceinline__ void static_range(int64_t n, int64_t T, int64_t t, int64_t *lo, int64_t *hi)
+{
+    const int64_t q = n / T, r = n % T;
+    *lo = t * q + (t < r ? t : r);
+    *hi = (t + 1) * q + (t + 1 < r ? t + 1 : r);
+}
+
+// ---------------------------------------------------------------------------
+// RPC client (Section 2.3 / 3.2). A ticket from a device-memory counter
+// selects a slot; the client waits until the slot's previous use is done,
+// fills the request and publishes it with a system-scope release store.
+// Posted calls return at once; blocking calls wait for `done` (the paper's
+// completion flag in shared memory) and return the host's value.
+// ---------------------------------------------------------------------------
+
+__device__ __forceinline__ bool rpc_wait_done(const RpcSlot *slot, uint64_t want, const RpcRing &rpc, int32_t *err)
+{
+    const uint64_t t0 = now_ticks();
+    uint32_t spins = 0;
+    while (__hip_atomic_load(&slot->done, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM) < want) {
+        __builtin_amdgcn_s_sleep(2);
+        if ((++spins & 15u) == 0 && (int64_t)(now_ticks() - t0) > rpc.timeout_ticks) {
+            set_error(err, kErrRpcTimeout);
+            return false;
+        }
+    }
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "");
+    return true;
+}
+
+// Called by a single thread. Returns false on timeout (error word set).
+__device__ __forceinline__ bool rpc_call(const RpcRing &rpc, uint32_t callee, uint32_t fmt_id, uint32_t nargs,
+                                         const uint64_t *args, uint32_t flags, int64_t *ret, int32_t *err)
+{
+    const uint64_t t = __hip_atomic_fetch_add(rpc.ticket, (uint64_t)1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    RpcSlot *slot = rpc.slots + (t & rpc.mask);
+    const uint64_t nslots = (uint64_t)rpc.mask + 1;
+    if (t >= nslots && !rpc_wait_done(slot, t - nslots + 1, rpc, err))
+        return false;
+    slot->callee = callee;
+    slot->fmt_id = fmt_id;
+    slot->nargs = nargs;
+    slot->flags = flags;
+    for (uint32_t i = 0; i < nargs && i < 8; ++i)
+        slot->args[i] = args[i];
+    __hip_atomic_store(&slot->seq, t + 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
+    if (flags & GF_STEP_BLOCKING) {
+        if (!rpc_wait_done(slot, t + 1, rpc, err))
+            return false;
+        if (ret)
+            *ret = __hip_atomic_load(&slot->ret, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+    }
+    return true;
+}
+
+}  // namespace gf

@@ -1,0 +1,150 @@
+// gf_internal.h -- device-side program representation, scratch layout and
+// the RPC slot format shared by the libgf translation units (not public).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "gf.h"
+
+namespace gf {
+
+// Persistent kernels receive the whole program by value as a kernel
+// argument (copied by the runtime at enqueue time, so the caller's structs
+// are free on return). 24 steps keep the argument block under 4 KiB.
+constexpr int kMaxDevSteps = 24;
+constexpr int kMaxGlue = 8;
+constexpr int kWave = 64;
+constexpr int kNumXcd = 8;
+
+struct DStep {
+    int32_t kind;
+    int32_t arr[5];
+    int32_t sc[3];
+    int32_t red_op;
+    int32_t np;
+    int32_t every;
+    int32_t fmt_id;
+    int32_t nargs;
+    uint32_t flags;
+    uint32_t mask;
+    int64_t chunk;
+    double c;
+};
+
+struct DProg {
+    int32_t n_pro;
+    int32_t n_body;
+    int32_t iters;
+    int32_t n_steps;  // n_pro + n_body
+    DStep steps[kMaxDevSteps];
+};
+
+struct DInst {
+    void *arr[GF_MAX_ARRAYS];
+    double *scal;
+    int64_t ip[GF_MAX_IPARAMS];
+};
+
+// Tiling chosen on the host; identical in every workgroup of a launch.
+struct Tiling {
+    int32_t wg_size;
+    int32_t tile_y;
+    int32_t tile_z;
+    int32_t items;
+    int32_t xcd_remap;
+    int32_t pad_;
+};
+
+// One RPC request slot in pinned, coherent host memory (cf. the paper's
+// RPCInfo / RPCArgInfo records, Section 3.2): the device fills the body,
+// then publishes `seq` = ticket + 1 with a system-scope release store; the
+// host runs the landing pad, writes `ret` and publishes `done` = ticket + 1.
+struct alignas(128) RpcSlot {
+    uint64_t seq;
+    uint32_t callee;
+    uint32_t fmt_id;
+    uint32_t nargs;
+    uint32_t flags;
+    uint64_t args[8];
+    int64_t ret;
+    uint64_t done;
+};
+static_assert(sizeof(RpcSlot) == 128, "RPC slot is one 128-byte line");
+
+enum : uint32_t { kCalleePrintf = 1 };
+
+// Device error word codes (sticky; first writer wins).
+enum : int32_t {
+    kErrNone = 0,
+    kErrBarrierTimeout = 1,
+    kErrRpcTimeout = 2,
+    kErrBadStep = 3,
+};
+
+struct RpcRing {
+    RpcSlot *slots;      // host pinned (device-visible)
+    uint64_t *ticket;    // device memory
+    uint32_t mask;       // nslots - 1
+    uint32_t pad_;
+    int64_t timeout_ticks;  // s_memrealtime ticks (100 MHz)
+};
+
+// Device scratch owned by a context. Each counter sits on its own 128-byte
+// line so spinning workgroups do not share lines with unrelated atomics.
+struct Scratch {
+    double *partials;        // reduction partials, two halves (double buffer)
+    int64_t partials_cap;    // doubles per half
+    uint32_t *lines;         // counters: line i = lines + 32*i
+    int32_t *error;          // sticky device error word
+    int64_t barrier_timeout_ticks;
+};
+
+constexpr int kLineWords = 32;  // uint32 words per 128-byte line
+// line 0: global grid barrier {count, gen}; lines 1..: per-instance group
+// barrier; lines kFinalizeLine0 + i: per-region last-workgroup counters.
+constexpr int kFinalizeLine0 = 1 + GF_MAX_INSTANCES;
+constexpr int kNumLines = kFinalizeLine0 + GF_MAX_INSTANCES;
+
+// A serial step attached to a per-region launch, with its array operand
+// resolved on the host (SWAPs are applied by the host while it walks the
+// step list).
+struct Glue {
+    int32_t kind;
+    int32_t sc[3];
+    int32_t every;
+    int32_t fmt_id;
+    int32_t nargs;
+    int32_t iter;
+    uint32_t flags;
+    uint32_t pad_;
+    double c;
+    double *rec;  // GF_S_RECORD destination array
+};
+
+struct RegionLaunch {
+    DStep step;
+    void *arr[5];          // resolved operands
+    double *scal;          // the instance's scalar variables (device)
+    int64_t n;             // size
+    int32_t n_items;
+    int32_t n_glue;
+    int32_t inst;          // instance index (finalize counter line)
+    int32_t pad_;
+    Glue glue[kMaxGlue];
+};
+
+// Host-side launch helpers implemented in gf_kernels.hip.
+hipError_t launch_persistent(const DProg &prog, const DInst &inst, const Tiling &t, int num_wg,
+                             const Scratch &scr, const RpcRing &rpc, hipStream_t s);
+int persistent_capacity(const DProg &prog, const Tiling &t, int num_cu);
+hipError_t launch_region(const RegionLaunch &rl, const Tiling &t, int num_wg, const Scratch &scr,
+                         const RpcRing &rpc, hipStream_t s);
+hipError_t launch_reduce(int op, int dt, const void *in, int64_t n, void *out, const Scratch &scr,
+                         int num_cu, hipStream_t s);
+hipError_t launch_copy(void *dst, const void *src, int64_t nbytes, int num_wg, hipStream_t s);
+
+// Number of work items (tiles / chunks) a region splits into under tiling t.
+int64_t region_items(const DStep &st, int64_t n, const Tiling &t);
+
+}  // namespace gf

@@ -1,0 +1,800 @@
+// gf_kernels.hip -- region bodies, the persistent program kernel, the
+// per-region kernel with in-kernel reduction finalize, gf_reduce and the
+// bandwidth probe. gfx950 only; built with -ffp-contract=off so every
+// elementwise value is rounded exactly as the legacy loop writes it.
+#include "gf_device.h"
+
+namespace gf {
+
+constexpr int kMaxWg = 256;         // workgroup size limit of every kernel here
+constexpr int kLdsRed = kMaxWg / kWave;
+
+// ---------------------------------------------------------------------------
+// Work decomposition shared by host and device.
+// ---------------------------------------------------------------------------
+
+__host__ __device__ inline int64_t cdiv(int64_t a, int64_t b) { return (a + b - 1) / b; }
+
+struct StencilGeom {
+    int64_t nxc, nyt, nzs;  // x chunks, y tiles, z segments
+};
+
+__host__ __device__ inline StencilGeom j3_geom(int64_t n, const Tiling &t)
+{
+    StencilGeom g;
+    const int64_t interior = n > 2 ? n - 2 : 0;
+    g.nxc = cdiv(n, t.wg_size);
+    g.nyt = cdiv(interior, t.tile_y);
+    g.nzs = cdiv(interior, t.tile_z);
+    return g;
+}
+
+__host__ __device__ inline StencilGeom j2_geom(int64_t n, const Tiling &t)
+{
+    StencilGeom g;
+    const int64_t interior = n > 2 ? n - 2 : 0;
+    g.nxc = cdiv(n, t.wg_size);
+    g.nyt = cdiv(interior, t.tile_y);
+    g.nzs = 1;
+    return g;
+}
+
+__host__ __device__ inline int64_t chunk_elems(const Tiling &t) { return (int64_t)t.wg_size * t.items; }
+
+int64_t region_items(const DStep &st, int64_t n, const Tiling &t)
+{
+    switch (st.kind) {
+    case GF_R_JACOBI3D: {
+        StencilGeom g = j3_geom(n, t);
+        return g.nxc * g.nyt * g.nzs;
+    }
+    case GF_R_JACOBI2D: {
+        StencilGeom g = j2_geom(n, t);
+        return g.nxc * g.nyt;
+    }
+    case GF_R_SPMV:
+        return cdiv(n, t.wg_size);
+    case GF_R_DOT:
+    case GF_R_AXPBY:
+    case GF_R_HIST:
+        return cdiv(n, chunk_elems(t));
+    case GF_R_OWNER:
+        return 0;  // thread-level static schedule, no tiles
+    default:
+        return 0;
+    }
+}
+
+__device__ inline int64_t region_items_dev(const DStep &st, int64_t n, const Tiling &t)
+{
+    switch (st.kind) {
+    case GF_R_JACOBI3D: {
+        StencilGeom g = j3_geom(n, t);
+        return g.nxc * g.nyt * g.nzs;
+    }
+    case GF_R_JACOBI2D: {
+        StencilGeom g = j2_geom(n, t);
+        return g.nxc * g.nyt;
+    }
+    case GF_R_SPMV:
+        return cdiv(n, t.wg_size);
+    case GF_R_DOT:
+    case GF_R_AXPBY:
+    case GF_R_HIST:
+        return cdiv(n, chunk_elems(t));
+    default:
+        return 0;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Region bodies. Each processes one work item with the whole workgroup and
+// returns the thread's private reduction value (identity if none).
+// ---------------------------------------------------------------------------
+
+// 3D 7-point Jacobi, 2.5-D blocking: the workgroup owns a (row chunk of
+// wg_size x) x (TY rows) column of the grid and marches along z over one
+// segment. Each thread keeps its column of planes z-1, z, z+1 in registers,
+// so every value of u is fetched from memory once per tile plus the two
+// y-halo rows and two z-halo planes; x neighbours are re-read from L1.
+template <int TY>
+__device__ __forceinline__ double j3_item(const double *__restrict__ u, double *__restrict__ w, int64_t n,
+                                          int64_t item, const Tiling &t, bool want_red)
+{
+    const StencilGeom g = j3_geom(n, t);
+    const int64_t xc = item % g.nxc;
+    const int64_t rest = item / g.nxc;
+    const int64_t yt = rest % g.nyt;
+    const int64_t zs = rest / g.nyt;
+    const int64_t x = xc * blockDim.x + threadIdx.x;
+    const int64_t y0 = 1 + yt * TY;
+    const int ny = (int)(n - 1 - y0 < TY ? n - 1 - y0 : TY);
+    const int64_t z0 = 1 + zs * t.tile_z;
+    const int64_t z1 = (z0 + t.tile_z < n - 1) ? z0 + t.tile_z : n - 1;
+    const bool xload = x < n;
+    const bool xin = x >= 1 && x <= n - 2;
+    const int64_t SY = n, SZ = n * n;
+    const double c6 = 1.0 / 6.0;
+    double mx = -INFINITY;
+    double pm[TY], pc[TY + 2], pn[TY + 2];
+#pragma unroll
+    for (int r = 0; r < TY; ++r)
+        pm[r] = 0.0;
+#pragma unroll
+    for (int r = 0; r < TY + 2; ++r)
+        pc[r] = pn[r] = 0.0;
+    if (xload) {
+        const double *b = u + (z0 - 1) * SZ + y0 * SY + x;
+#pragma unroll
+        for (int r = 0; r < TY; ++r)
+            if (r < ny)
+                pm[r] = b[r * SY];
+        b = u + z0 * SZ + (y0 - 1) * SY + x;
+#pragma unroll
+        for (int r = 0; r < TY + 2; ++r)
+            if (r < ny + 2)
+                pc[r] = b[r * SY];
+    }
+    for (int64_t z = z0; z < z1; ++z) {
+        if (xload) {
+            const double *b = u + (z + 1) * SZ + (y0 - 1) * SY + x;
+#pragma unroll
+            for (int r = 0; r < TY + 2; ++r)
+                if (r < ny + 2)
+                    pn[r] = b[r * SY];
+        }
+        if (xin) {
+            const double *row = u + z * SZ + y0 * SY + x;
+            double *out = w + z * SZ + y0 * SY + x;
+#pragma unroll
+            for (int r = 0; r < TY; ++r) {
+                if (r < ny) {
+                    const double xl = row[r * SY - 1];
+                    const double xr = row[r * SY + 1];
+                    const double v = (((xl + xr) + (pc[r] + pc[r + 2])) + (pm[r] + pn[r + 1])) * c6;
+                    __builtin_nontemporal_store(v, out + r * SY);
+                    if (want_red) {
+                        const double d = fabs(v - pc[r + 1]);
+                        mx = d > mx ? d : mx;
+                    }
+                }
+            }
+        }
+#pragma unroll
+        for (int r = 0; r < TY; ++r)
+            pm[r] = pc[r + 1];
+#pragma unroll
+        for (int r = 0; r < TY + 2; ++r)
+            pc[r] = pn[r];
+    }
+    return mx;
+}
+
+// 2D 5-point Jacobi: the workgroup owns (row chunk) x (TY rows); each thread
+// holds its column of TY+2 rows in registers.
+template <int TY>
+__device__ __forceinline__ double j2_item(const double *__restrict__ u, double *__restrict__ w, int64_t n,
+                                          int64_t item, const Tiling &t, bool want_red)
+{
+    const StencilGeom g = j2_geom(n, t);
+    const int64_t xc = item % g.nxc;
+    const int64_t yt = item / g.nxc;
+    const int64_t x = xc * blockDim.x + threadIdx.x;
+    const int64_t y0 = 1 + yt * TY;
+    const int ny = (int)(n - 1 - y0 < TY ? n - 1 - y0 : TY);
+    double acc = 0.0;
+    if (x >= 1 && x <= n - 2) {
+        double col[TY + 2];
+        const double *b = u + (y0 - 1) * n + x;
+#pragma unroll
+        for (int r = 0; r < TY + 2; ++r)
+            col[r] = (r < ny + 2) ? b[r * n] : 0.0;
+        double *out = w + y0 * n + x;
+#pragma unroll
+        for (int r = 0; r < TY; ++r) {
+            if (r < ny) {
+                const double xl = b[(r + 1) * n - 1];
+                const double xr = b[(r + 1) * n + 1];
+                const double v = ((xl + xr) + (col[r] + col[r + 2])) * 0.25;
+                out[r * n] = v;
+                if (want_red) {
+                    const double d = v - col[r + 1];
+                    acc = acc + d * d;
+                }
+            }
+        }
+    }
+    return acc;
+}
+
+// CSR SpMV, one thread per row; the row is summed serially in stored column
+// order, as the legacy loop does.
+__device__ __forceinline__ void spmv_item(const int32_t *__restrict__ rowptr, const int32_t *__restrict__ col,
+                                          const double *__restrict__ val, const double *__restrict__ x,
+                                          double *__restrict__ y, int64_t n, int64_t item)
+{
+    const int64_t row = item * blockDim.x + threadIdx.x;
+    if (row < n) {
+        double acc = 0.0;
+        const int32_t e = rowptr[row + 1];
+        for (int32_t k = rowptr[row]; k < e; ++k)
+            acc = acc + val[k] * x[col[k]];
+        y[row] = acc;
+    }
+}
+
+__device__ __forceinline__ double dot_item(const double *__restrict__ a, const double *__restrict__ b, int64_t n,
+                                           int64_t item, const Tiling &t)
+{
+    const int64_t base = item * chunk_elems(t);
+    double acc = 0.0;
+    for (int k = 0; k < t.items; ++k) {
+        const int64_t i = base + (int64_t)k * blockDim.x + threadIdx.x;
+        if (i < n)
+            acc = acc + a[i] * b[i];
+    }
+    return acc;
+}
+
+__device__ __forceinline__ void axpby_item(double *out, const double *x, double s, const double *y, int64_t n,
+                                           int64_t item, const Tiling &t)
+{
+    const int64_t base = item * chunk_elems(t);
+    for (int k = 0; k < t.items; ++k) {
+        const int64_t i = base + (int64_t)k * blockDim.x + threadIdx.x;
+        if (i < n)
+            out[i] = x[i] + s * y[i];
+    }
+}
+
+__device__ __forceinline__ void hist_item(const uint32_t *__restrict__ keys, uint32_t *bins, uint32_t mask,
+                                          int64_t n, int64_t item, const Tiling &t)
+{
+    const int64_t base = item * chunk_elems(t);
+    for (int k = 0; k < t.items; ++k) {
+        const int64_t i = base + (int64_t)k * blockDim.x + threadIdx.x;
+        if (i < n)
+            atomicAdd(&bins[keys[i] & mask], 1u);
+    }
+}
+
+// GF_R_OWNER: the static schedule executed literally over all T threads.
+__device__ __forceinline__ void owner_region(int32_t *owner, int64_t n, int64_t chunk, int64_t T, int64_t tid)
+{
+    if (chunk <= 0) {
+        int64_t lo, hi;
+        static_range(n, T, tid, &lo, &hi);
+        for (int64_t i = lo; i < hi; ++i)
+            owner[i] = (int32_t)tid;
+    } else {
+        for (int64_t c0 = tid * chunk; c0 < n; c0 += T * chunk)
+            for (int64_t i = c0; i < c0 + chunk && i < n; ++i)
+                owner[i] = (int32_t)tid;
+    }
+}
+
+// Executes one work item of a region; returns the thread's reduction value.
+// op[i] is the region's i-th array operand (slot st.arr[i] resolved by the
+// caller); s is the AXPBY coefficient scal[st.sc[1]] * st.c.
+template <unsigned KMASK, int TY>
+__device__ __forceinline__ double region_item(const DStep &st, void *const *op, double s, int64_t n, int64_t item,
+                                              const Tiling &t)
+{
+    const bool red = st.red_op != GF_OP_NONE;
+    switch (st.kind) {
+    case GF_R_JACOBI3D:
+        if constexpr ((KMASK >> GF_R_JACOBI3D) & 1u)
+            return j3_item<TY>((const double *)op[0], (double *)op[1], n, item, t, red);
+        break;
+    case GF_R_JACOBI2D:
+        if constexpr ((KMASK >> GF_R_JACOBI2D) & 1u)
+            return j2_item<TY>((const double *)op[0], (double *)op[1], n, item, t, red);
+        break;
+    case GF_R_SPMV:
+        if constexpr ((KMASK >> GF_R_SPMV) & 1u) {
+            spmv_item((const int32_t *)op[0], (const int32_t *)op[1], (const double *)op[2], (const double *)op[3],
+                      (double *)op[4], n, item);
+            return 0.0;
+        }
+        break;
+    case GF_R_DOT:
+        if constexpr ((KMASK >> GF_R_DOT) & 1u)
+            return dot_item((const double *)op[0], (const double *)op[1], n, item, t);
+        break;
+    case GF_R_AXPBY:
+        if constexpr ((KMASK >> GF_R_AXPBY) & 1u) {
+            axpby_item((double *)op[0], (const double *)op[1], s, (const double *)op[2], n, item, t);
+            return 0.0;
+        }
+        break;
+    case GF_R_HIST:
+        if constexpr ((KMASK >> GF_R_HIST) & 1u) {
+            hist_item((const uint32_t *)op[0], (uint32_t *)op[1], st.mask, n, item, t);
+            return 0.0;
+        }
+        break;
+    default:
+        break;
+    }
+    return red_identity(st.red_op);
+}
+
+// ---------------------------------------------------------------------------
+// Serial steps of the initial thread (called by one thread).
+// ---------------------------------------------------------------------------
+
+__device__ inline void serial_scalar(int kind, const int32_t *sc, double c, double *scal)
+{
+    switch (kind) {
+    case GF_S_SET:
+        scal[sc[0]] = c;
+        break;
+    case GF_S_COPY:
+        scal[sc[0]] = scal[sc[1]];
+        break;
+    case GF_S_DIV:
+        scal[sc[0]] = scal[sc[1]] / scal[sc[2]];
+        break;
+    case GF_S_SQRT:
+        scal[sc[0]] = sqrt(scal[sc[1]]);
+        break;
+    default:
+        break;
+    }
+}
+
+__device__ inline void serial_printf(const RpcRing &rpc, int32_t fmt_id, int32_t nargs, uint32_t flags,
+                                     const int32_t *sc, int32_t iter, const double *scal, int32_t *err)
+{
+    uint64_t args[8];
+    args[0] = (uint64_t)(int64_t)(iter + 1);
+    for (int k = 1; k < nargs && k < 4; ++k)
+        args[k] = __double_as_longlong(scal[sc[k - 1]]);
+    rpc_call(rpc, kCalleePrintf, (uint32_t)fmt_id, (uint32_t)nargs, args, flags, nullptr, err);
+}
+
+// ---------------------------------------------------------------------------
+// Persistent program kernel (the whole main loop in one cooperative launch;
+// Section 3.3 with the kernel split replaced by in-kernel grid barriers).
+// Every workgroup walks the step list. Region work items are dealt
+// round-robin over workers; after each region a grid barrier stands for the
+// implicit barrier of `parallel for`. Serial steps are executed redundantly by
+// every workgroup on its own LDS copy of the scalar variables, which stay
+// identical because every workgroup reduces the same partials in the same
+// order; only workgroup 0 performs side effects (records, RPC, write-back).
+// ---------------------------------------------------------------------------
+
+template <unsigned KMASK, int TY>
+__global__ void __launch_bounds__(kMaxWg) k_persistent(DProg prog, DInst inst, Tiling t, Scratch scr, RpcRing rpc)
+{
+    __shared__ double s_scal[GF_MAX_SCALARS];
+    __shared__ void *s_arr[GF_MAX_ARRAYS];
+    __shared__ double s_red[kLdsRed];
+    __shared__ BarrierState s_bar;
+
+    const int64_t G = gridDim.x;
+    const int64_t worker = worker_id(blockIdx.x, G, t.xcd_remap);
+    uint32_t *line = scr.lines;  // line 0: the grid barrier
+    if (threadIdx.x < GF_MAX_SCALARS)
+        s_scal[threadIdx.x] = inst.scal[threadIdx.x];
+    if (threadIdx.x < GF_MAX_ARRAYS)
+        s_arr[threadIdx.x] = inst.arr[threadIdx.x];
+    if (threadIdx.x == 0) {
+        s_bar.gen = __hip_atomic_load(&line[1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        s_bar.ok = 1;
+    }
+    __syncthreads();
+
+    int parity = 0;
+    const int64_t total = (int64_t)prog.n_pro + (int64_t)prog.iters * prog.n_body;
+    for (int64_t si = 0; si < total; ++si) {
+        int sidx;
+        int32_t iter;
+        if (si < prog.n_pro) {
+            sidx = (int)si;
+            iter = -1;
+        } else {
+            const int64_t k = si - prog.n_pro;
+            sidx = prog.n_pro + (int)(k % prog.n_body);
+            iter = (int32_t)(k / prog.n_body);
+        }
+        const DStep &st = prog.steps[sidx];
+        if (st.kind < 32) {
+            const int64_t n = inst.ip[st.np];
+            const bool red = st.red_op != GF_OP_NONE;
+            double *part = scr.partials + (parity ? scr.partials_cap : 0);
+            void *op[5];
+#pragma unroll
+            for (int k = 0; k < 5; ++k)
+                op[k] = st.arr[k] >= 0 ? s_arr[st.arr[k]] : nullptr;
+            const double coef = (st.kind == GF_R_AXPBY) ? s_scal[st.sc[1]] * st.c : 0.0;
+            if (st.kind == GF_R_OWNER) {
+                owner_region((int32_t *)op[0], n, st.chunk, G * blockDim.x,
+                             (int64_t)blockIdx.x * blockDim.x + threadIdx.x);
+            } else {
+                const int64_t nitems = region_items_dev(st, n, t);
+                for (int64_t it = worker; it < nitems; it += G) {
+                    double v = region_item<KMASK, TY>(st, op, coef, n, it, t);
+                    if (red) {
+                        v = block_reduce_rt(st.red_op, v, s_red);
+                        if (threadIdx.x == 0)
+                            part[it] = v;
+                    }
+                }
+                if (!group_barrier(line, (uint32_t)G, &s_bar, scr.error, scr.barrier_timeout_ticks))
+                    return;
+                if (red) {
+                    const double v = reduce_partials(st.red_op, part, nitems, s_red);
+                    if (threadIdx.x == 0)
+                        s_scal[st.sc[0]] = red_apply(st.red_op, s_scal[st.sc[0]], v);
+                    parity ^= 1;
+                }
+                __syncthreads();
+                continue;
+            }
+            if (!group_barrier(line, (uint32_t)G, &s_bar, scr.error, scr.barrier_timeout_ticks))
+                return;
+        } else if (threadIdx.x == 0) {
+            if (st.kind == GF_S_SWAP) {
+                void *tmp = s_arr[st.arr[0]];
+                s_arr[st.arr[0]] = s_arr[st.arr[1]];
+                s_arr[st.arr[1]] = tmp;
+            } else if (st.kind == GF_S_RECORD) {
+                if (blockIdx.x == 0 && iter >= 0)
+                    ((double *)s_arr[st.arr[0]])[iter] = s_scal[st.sc[0]];
+            } else if (st.kind == GF_S_PRINTF) {
+                if (blockIdx.x == 0 && iter >= 0 && st.every > 0 && (iter + 1) % st.every == 0)
+                    serial_printf(rpc, st.fmt_id, st.nargs, st.flags, st.sc, iter, s_scal, scr.error);
+            } else {
+                serial_scalar(st.kind, st.sc, st.c, s_scal);
+            }
+        }
+        __syncthreads();
+    }
+    if (blockIdx.x == 0 && threadIdx.x < GF_MAX_SCALARS)
+        inst.scal[threadIdx.x] = s_scal[threadIdx.x];
+}
+
+// ---------------------------------------------------------------------------
+// Per-region kernel: one launch per region. Work items are dealt over the
+// grid; with a reduction clause each item writes its partial and the last
+// workgroup to finish (arrival counter) reduces all partials in a fixed
+// order, combines the result into the scalar variable and runs the serial
+// glue that follows the region in the program.
+// ---------------------------------------------------------------------------
+
+__device__ inline void run_glue(const RegionLaunch &rl, const RpcRing &rpc, int32_t *err)
+{
+    for (int g = 0; g < rl.n_glue; ++g) {
+        const Glue &gl = rl.glue[g];
+        if (gl.kind == GF_S_RECORD) {
+            if (gl.iter >= 0)
+                gl.rec[gl.iter] = rl.scal[gl.sc[0]];
+        } else if (gl.kind == GF_S_PRINTF) {
+            if (gl.iter >= 0 && gl.every > 0 && (gl.iter + 1) % gl.every == 0)
+                serial_printf(rpc, gl.fmt_id, gl.nargs, gl.flags, gl.sc, gl.iter, rl.scal, err);
+        } else {
+            serial_scalar(gl.kind, gl.sc, gl.c, rl.scal);
+        }
+    }
+}
+
+template <unsigned KMASK, int TY>
+__global__ void __launch_bounds__(kMaxWg) k_region(RegionLaunch rl, Tiling t, Scratch scr, RpcRing rpc)
+{
+    __shared__ double s_red[kLdsRed];
+    __shared__ int s_last;
+    const DStep &st = rl.step;
+    const int64_t G = gridDim.x;
+    const bool red = st.red_op != GF_OP_NONE;
+    double *part = scr.partials;
+    if (st.kind == GF_R_OWNER) {
+        owner_region((int32_t *)rl.arr[0], rl.n, st.chunk, G * blockDim.x,
+                     (int64_t)blockIdx.x * blockDim.x + threadIdx.x);
+    } else if (st.kind < 32) {
+        const double coef = (st.kind == GF_R_AXPBY) ? rl.scal[st.sc[1]] * st.c : 0.0;
+        const int64_t worker = worker_id(blockIdx.x, G, t.xcd_remap);
+        for (int64_t it = worker; it < rl.n_items; it += G) {
+            double v = region_item<KMASK, TY>(st, rl.arr, coef, rl.n, it, t);
+            if (red) {
+                v = block_reduce_rt(st.red_op, v, s_red);
+                if (threadIdx.x == 0)
+                    part[it] = v;
+            }
+        }
+    }
+    if (!red && rl.n_glue == 0)
+        return;
+    // last-workgroup finalize
+    uint32_t *cnt = scr.lines + (int64_t)(kFinalizeLine0 + rl.inst) * kLineWords;
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        const uint32_t a = __hip_atomic_fetch_add(cnt, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
+        s_last = (a == (uint32_t)G - 1);
+    }
+    __syncthreads();
+    if (!s_last)
+        return;
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+    if (red) {
+        const double v = reduce_partials(st.red_op, part, rl.n_items, s_red);
+        if (threadIdx.x == 0)
+            rl.scal[st.sc[0]] = red_apply(st.red_op, rl.scal[st.sc[0]], v);
+    }
+    if (threadIdx.x == 0) {
+        run_glue(rl, rpc, scr.error);
+        __hip_atomic_store(cnt, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Kernel selection. Families: the bodies a program uses decide which
+// instantiation runs, so a program only pays the registers of its own bodies.
+// ---------------------------------------------------------------------------
+
+constexpr unsigned kFamJ3 = (1u << GF_R_JACOBI3D) | (1u << GF_R_OWNER);
+constexpr unsigned kFamJ2 = (1u << GF_R_JACOBI2D) | (1u << GF_R_OWNER);
+constexpr unsigned kFamVec = (1u << GF_R_SPMV) | (1u << GF_R_DOT) | (1u << GF_R_AXPBY) | (1u << GF_R_HIST) |
+                             (1u << GF_R_OWNER);
+constexpr unsigned kFamAll = kFamJ3 | kFamJ2 | kFamVec;
+
+static unsigned program_kinds(const DProg &p)
+{
+    unsigned m = 0;
+    for (int i = 0; i < p.n_steps; ++i)
+        if (p.steps[i].kind < 32)
+            m |= 1u << p.steps[i].kind;
+    return m;
+}
+
+static unsigned pick_family(unsigned kinds)
+{
+    if ((kinds & ~kFamJ3) == 0)
+        return kFamJ3;
+    if ((kinds & ~kFamJ2) == 0)
+        return kFamJ2;
+    if ((kinds & ~kFamVec) == 0)
+        return kFamVec;
+    return kFamAll;
+}
+
+typedef void (*PersistentFn)(DProg, DInst, Tiling, Scratch, RpcRing);
+typedef void (*RegionFn)(RegionLaunch, Tiling, Scratch, RpcRing);
+
+template <unsigned F>
+static PersistentFn persistent_for_ty(int ty)
+{
+    switch (ty) {
+    case 1: return k_persistent<F, 1>;
+    case 2: return k_persistent<F, 2>;
+    case 4: return k_persistent<F, 4>;
+    case 8: return k_persistent<F, 8>;
+    case 16: return k_persistent<F, 16>;
+    default: return nullptr;
+    }
+}
+
+template <unsigned F>
+static RegionFn region_for_ty(int ty)
+{
+    switch (ty) {
+    case 1: return k_region<F, 1>;
+    case 2: return k_region<F, 2>;
+    case 4: return k_region<F, 4>;
+    case 8: return k_region<F, 8>;
+    case 16: return k_region<F, 16>;
+    default: return nullptr;
+    }
+}
+
+static PersistentFn persistent_fn(unsigned fam, int ty)
+{
+    switch (fam) {
+    case kFamJ3: return persistent_for_ty<kFamJ3>(ty);
+    case kFamJ2: return persistent_for_ty<kFamJ2>(ty);
+    case kFamVec: return persistent_for_ty<kFamVec>(1);
+    default: return persistent_for_ty<kFamAll>(ty);
+    }
+}
+
+static RegionFn region_fn(int kind, int ty)
+{
+    switch (kind) {
+    case GF_R_JACOBI3D: return region_for_ty<kFamJ3>(ty);
+    case GF_R_JACOBI2D: return region_for_ty<kFamJ2>(ty);
+    default: return region_for_ty<kFamVec>(1);
+    }
+}
+
+int persistent_capacity(const DProg &prog, const Tiling &t, int num_cu)
+{
+    PersistentFn fn = persistent_fn(pick_family(program_kinds(prog)), t.tile_y);
+    if (!fn)
+        return 0;
+    int per_cu = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, reinterpret_cast<const void *>(fn), t.wg_size, 0) !=
+        hipSuccess)
+        return 0;
+    return per_cu * num_cu;
+}
+
+hipError_t launch_persistent(const DProg &prog, const DInst &inst, const Tiling &t, int num_wg, const Scratch &scr,
+                             const RpcRing &rpc, hipStream_t s)
+{
+    PersistentFn fn = persistent_fn(pick_family(program_kinds(prog)), t.tile_y);
+    if (!fn)
+        return hipErrorInvalidValue;
+    DProg p = prog;
+    DInst i = inst;
+    Tiling tt = t;
+    Scratch sc = scr;
+    RpcRing r = rpc;
+    void *args[] = {&p, &i, &tt, &sc, &r};
+    return hipLaunchCooperativeKernel(reinterpret_cast<const void *>(fn), dim3(num_wg), dim3(t.wg_size), args, 0, s);
+}
+
+hipError_t launch_region(const RegionLaunch &rl, const Tiling &t, int num_wg, const Scratch &scr,
+                         const RpcRing &rpc, hipStream_t s)
+{
+    RegionFn fn = region_fn(rl.step.kind, t.tile_y);
+    if (!fn)
+        return hipErrorInvalidValue;
+    hipLaunchKernelGGL(fn, dim3(num_wg), dim3(t.wg_size), 0, s, rl, t, scr, rpc);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// gf_reduce: a stand-alone reduction region over a device array. Fixed
+// two-level tree: each workgroup reduces a contiguous block (strided per
+// thread), the last workgroup reduces the per-block partials in order.
+// ---------------------------------------------------------------------------
+
+template <typename T, int OP>
+struct TRed;
+template <typename T>
+struct TRed<T, GF_OP_SUM> {
+    static __device__ T id() { return (T)0; }
+    static __device__ T ap(T a, T b) { return a + b; }
+};
+template <typename T>
+struct TRed<T, GF_OP_MAX> {
+    static __device__ T id();
+    static __device__ T ap(T a, T b) { return a > b ? a : b; }
+};
+template <>
+__device__ double TRed<double, GF_OP_MAX>::id() { return -INFINITY; }
+template <>
+__device__ uint64_t TRed<uint64_t, GF_OP_MAX>::id() { return 0; }
+template <>
+__device__ int64_t TRed<int64_t, GF_OP_MAX>::id() { return INT64_MIN; }
+
+template <typename T>
+__device__ __forceinline__ T shfl_xor_t(T v, int off)
+{
+    if constexpr (sizeof(T) == 8) {
+        int64_t b;
+        __builtin_memcpy(&b, &v, 8);
+        b = __shfl_xor((long long)b, off, kWave);
+        __builtin_memcpy(&v, &b, 8);
+        return v;
+    } else {
+        return __shfl_xor(v, off, kWave);
+    }
+}
+
+template <typename T, int OP>
+__device__ __forceinline__ T block_reduce_t(T v, T *lds)
+{
+#pragma unroll
+    for (int off = kWave / 2; off > 0; off >>= 1)
+        v = TRed<T, OP>::ap(v, shfl_xor_t(v, off));
+    const int lane = threadIdx.x & (kWave - 1), wid = threadIdx.x / kWave, nw = blockDim.x / kWave;
+    if (lane == 0)
+        lds[wid] = v;
+    __syncthreads();
+    if (wid == 0) {
+        v = lane < nw ? lds[lane] : TRed<T, OP>::id();
+#pragma unroll
+        for (int off = kWave / 2; off > 0; off >>= 1)
+            v = TRed<T, OP>::ap(v, shfl_xor_t(v, off));
+    }
+    __syncthreads();
+    return v;
+}
+
+// In: element type TI; accumulation/output type T (u32 sums widen to u64).
+template <typename TI, typename T, int OP>
+__global__ void __launch_bounds__(kMaxWg) k_reduce(const TI *__restrict__ in, int64_t n, T *out, T *partials,
+                                                    uint32_t *cnt)
+{
+    __shared__ T s_red[kLdsRed];
+    __shared__ int s_last;
+    const int64_t G = gridDim.x;
+    const int64_t per = cdiv(n, G);
+    const int64_t lo = blockIdx.x * per;
+    const int64_t hi = lo + per < n ? lo + per : n;
+    T acc = TRed<T, OP>::id();
+    for (int64_t i = lo + threadIdx.x; i < hi; i += blockDim.x)
+        acc = TRed<T, OP>::ap(acc, (T)in[i]);
+    acc = block_reduce_t<T, OP>(acc, s_red);
+    if (threadIdx.x == 0)
+        partials[blockIdx.x] = acc;
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        const uint32_t a = __hip_atomic_fetch_add(cnt, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
+        s_last = (a == (uint32_t)G - 1);
+    }
+    __syncthreads();
+    if (!s_last)
+        return;
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+    T v = TRed<T, OP>::id();
+    for (int64_t i = threadIdx.x; i < G; i += blockDim.x)
+        v = TRed<T, OP>::ap(v, partials[i]);
+    v = block_reduce_t<T, OP>(v, s_red);
+    if (threadIdx.x == 0) {
+        out[0] = v;
+        __hip_atomic_store(cnt, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+}
+
+hipError_t launch_reduce(int op, int dt, const void *in, int64_t n, void *out, const Scratch &scr, int num_cu,
+                         hipStream_t s)
+{
+    // Enough workgroups to stream at full bandwidth, each with >= 4K elements.
+    int64_t g = cdiv(n, 4096);
+    const int64_t gmax = (int64_t)num_cu * 4;
+    if (g > gmax)
+        g = gmax;
+    if (g < 1)
+        g = 1;
+    uint32_t *cnt = scr.lines + (int64_t)(kFinalizeLine0 + GF_MAX_INSTANCES - 1) * kLineWords;
+    void *part = scr.partials;
+    const dim3 grid((unsigned)g), blk(kMaxWg);
+#define GF_RED(TI, T, OP) \
+    hipLaunchKernelGGL((k_reduce<TI, T, OP>), grid, blk, 0, s, (const TI *)in, n, (T *)out, (T *)part, cnt)
+    if (op == GF_OP_SUM) {
+        switch (dt) {
+        case GF_F64: GF_RED(double, double, GF_OP_SUM); break;
+        case GF_U32: GF_RED(uint32_t, uint64_t, GF_OP_SUM); break;
+        case GF_U64: GF_RED(uint64_t, uint64_t, GF_OP_SUM); break;
+        case GF_I64: GF_RED(int64_t, int64_t, GF_OP_SUM); break;
+        default: return hipErrorInvalidValue;
+        }
+    } else {
+        switch (dt) {
+        case GF_F64: GF_RED(double, double, GF_OP_MAX); break;
+        case GF_U32: GF_RED(uint32_t, uint64_t, GF_OP_MAX); break;
+        case GF_U64: GF_RED(uint64_t, uint64_t, GF_OP_MAX); break;
+        case GF_I64: GF_RED(int64_t, int64_t, GF_OP_MAX); break;
+        default: return hipErrorInvalidValue;
+        }
+    }
+#undef GF_RED
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Copy kernel: the achievable HBM ceiling (16-byte loads and nontemporal
+// stores, grid-stride).
+// ---------------------------------------------------------------------------
+
+__global__ void __launch_bounds__(kMaxWg) k_copy(const double2 *__restrict__ src, double2 *__restrict__ dst, int64_t n)
+{
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
+        const double2 v = src[i];
+        __builtin_nontemporal_store(v.x, &dst[i].x);
+        __builtin_nontemporal_store(v.y, &dst[i].y);
+    }
+}
+
+hipError_t launch_copy(void *dst, const void *src, int64_t nbytes, int num_wg, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_copy, dim3(num_wg), dim3(kMaxWg), 0, s, (const double2 *)src, (double2 *)dst, nbytes / 16);
+    return hipGetLastError();
+}
+
+}  // namespace gf

@@ -18,3 +18,15 @@ def oracle_lib():
     import oracle
     oracle.build(force=False)
     return oracle
+
+
+@pytest.fixture(scope="session")
+def gfx():
+    """A libgf context on cuda:0 with captured RPC output (GPU tests only)."""
+    torch = pytest.importorskip("torch")
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU visible")
+    import paper_2306_11686_amd as gf
+    ctx = gf.Context(0, rpc_capture=True)
+    yield ctx
+    ctx.close()

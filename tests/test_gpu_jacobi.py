@@ -1,0 +1,169 @@
+"""GPU parity of the stencil programs against the serial oracle.
+
+Grids are compared bit for bit (both sides evaluate the same parenthesised
+expression without contraction). The 3D residual is a max and must match
+exactly; the 2D residual is a sum whose order differs, so it must lie within
+1e-12 (relative, all terms are >= 0) of the oracle's compensated value.
+"""
+import numpy as np
+import pytest
+
+import gf_inputs as gi
+from tests.gpu_helpers import run_jacobi2d, run_jacobi3d
+
+pytestmark = pytest.mark.gpu
+
+MODES = ["persistent", "per_region", "graph"]
+
+
+def _mode(gf, name):
+    return {"persistent": gf.GF_EXEC_PERSISTENT, "per_region": gf.GF_EXEC_PER_REGION,
+            "graph": gf.GF_EXEC_PER_REGION_GRAPH}[name]
+
+
+@pytest.mark.parametrize("mode", MODES)
+@pytest.mark.parametrize("n,sweeps", [(3, 2), (5, 3), (13, 4), (37, 5), (66, 3)])
+def test_jacobi3d_small_odd_shapes(gfx, oracle_lib, mode, n, sweeps):
+    import paper_2306_11686_amd as gf
+    print(f"jacobi3d n={n} sweeps={sweeps} mode={mode}", flush=True)
+    u0 = gi.grid3d(n, seed=1)
+    g_ref, r_ref = oracle_lib.jacobi3d(u0, sweeps)
+    g, r, _ = run_jacobi3d(gfx, u0, sweeps, _mode(gf, mode))
+    assert np.array_equal(g, g_ref)
+    assert np.array_equal(r, r_ref)
+
+
+@pytest.mark.parametrize("ty,tz,wg,remap", [(1, 1, 64, 0), (2, 7, 128, 1), (4, 16, 192, 0), (8, 64, 256, 1),
+                                            (16, 5, 256, 1), (8, 300, 64, 1)])
+@pytest.mark.parametrize("mode", ["persistent", "per_region"])
+def test_jacobi3d_tilings(gfx, oracle_lib, ty, tz, wg, remap, mode):
+    import paper_2306_11686_amd as gf
+    n = 41
+    print(f"jacobi3d tiling ty={ty} tz={tz} wg={wg} remap={remap} mode={mode}", flush=True)
+    u0 = gi.grid3d(n, seed=2)
+    g_ref, r_ref = oracle_lib.jacobi3d(u0, 3)
+    launch = gf.Launch.make(wg_size=wg, tile_y=ty, tile_z=tz, xcd_remap=remap)
+    g, r, _ = run_jacobi3d(gfx, u0, 3, _mode(gf, mode), launch=launch)
+    assert np.array_equal(g, g_ref)
+    assert np.array_equal(r, r_ref)
+
+
+def test_jacobi3d_persistent_small_grid_count(gfx, oracle_lib):
+    import paper_2306_11686_amd as gf
+    u0 = gi.grid3d(30, seed=3)
+    g_ref, r_ref = oracle_lib.jacobi3d(u0, 6)
+    for nwg in (1, 3, 8, 37):
+        print(f"jacobi3d persistent num_wg={nwg}", flush=True)
+        g, r, st = run_jacobi3d(gfx, u0, 6, gf.GF_EXEC_PERSISTENT, launch=gf.Launch.make(num_wg=nwg))
+        assert st["num_wg"] == nwg and st["launches"] == 1
+        assert np.array_equal(g, g_ref) and np.array_equal(r, r_ref)
+
+
+def test_jacobi3d_eigenmode_and_determinism(gfx, oracle_lib):
+    import paper_2306_11686_amd as gf
+    n, k = 48, 10
+    u0 = gi.eigenmode3d(n, 1, 2, 3)
+    g_ref, r_ref = oracle_lib.jacobi3d(u0, k)
+    g1, r1, _ = run_jacobi3d(gfx, u0, k, gf.GF_EXEC_PERSISTENT)
+    g2, r2, _ = run_jacobi3d(gfx, u0, k, gf.GF_EXEC_PERSISTENT)
+    g3, r3, _ = run_jacobi3d(gfx, u0, k, gf.GF_EXEC_PER_REGION)
+    assert np.array_equal(g1, g_ref) and np.array_equal(g1, g2) and np.array_equal(g1, g3)
+    assert np.array_equal(r1, r_ref) and np.array_equal(r1, r2) and np.array_equal(r1, r3)
+
+
+@pytest.mark.parametrize("mode", MODES)
+@pytest.mark.parametrize("n,sweeps", [(3, 1), (4, 2), (9, 5), (130, 7), (257, 3)])
+def test_jacobi2d_small_shapes(gfx, oracle_lib, mode, n, sweeps):
+    import paper_2306_11686_amd as gf
+    print(f"jacobi2d n={n} sweeps={sweeps} mode={mode}", flush=True)
+    u0 = gi.grid2d(n, seed=1)
+    g_ref, r_naive, r_comp, _ = oracle_lib.jacobi2d(u0, sweeps)
+    g, r, _ = run_jacobi2d(gfx, u0, sweeps, _mode(gf, mode))
+    assert np.array_equal(g, g_ref)
+    assert np.all(np.abs(r - r_comp) <= 1e-12 * r_comp + 1e-300)
+
+
+@pytest.mark.parametrize("ty", [1, 2, 4, 8, 16])
+def test_jacobi2d_tilings(gfx, oracle_lib, ty):
+    import paper_2306_11686_amd as gf
+    u0 = gi.grid2d(75, seed=4)
+    g_ref, _, r_comp, _ = oracle_lib.jacobi2d(u0, 4)
+    for mode in (gf.GF_EXEC_PERSISTENT, gf.GF_EXEC_PER_REGION):
+        g, r, _ = run_jacobi2d(gfx, u0, 4, mode, launch=gf.Launch.make(tile_y=ty, wg_size=64))
+        assert np.array_equal(g, g_ref)
+        assert np.all(np.abs(r - r_comp) <= 1e-12 * r_comp)
+
+
+@pytest.mark.parametrize("mode", MODES)
+def test_jacobi2d_256_with_printf_rpc(gfx, oracle_lib, mode):
+    """The 2D program at its full size: 256^2, 100 sweeps, printf every 10
+    sweeps forwarded to the host by RPC."""
+    import paper_2306_11686_amd as gf
+    from paper_2306_11686_amd import programs
+    print(f"jacobi2d 256 printf mode={mode}", flush=True)
+    fmt = gfx.register_format(programs.JACOBI2D_FORMAT, "id")
+    gfx.take_output()
+    u0 = gi.grid2d(256, seed=1)
+    g_ref, _, r_comp, text_ref = oracle_lib.jacobi2d(u0, 100, print_every=10)
+    g, r, st = run_jacobi2d(gfx, u0, 100, _mode(gf, mode), fmt_id=fmt, print_every=10)
+    text = gfx.take_output()
+    assert np.array_equal(g, g_ref)
+    assert np.all(np.abs(r - r_comp) <= 1e-12 * r_comp)
+    lines = text.splitlines()
+    assert len(lines) == 10
+    # the text is the host's own formatting of the doubles the device sent
+    assert lines == [programs.JACOBI2D_FORMAT.strip() % (s, r[s - 1]) for s in range(10, 101, 10)]
+    ref_lines = text_ref.splitlines()
+    for a, b in zip(lines, ref_lines):
+        assert a.split()[1] == b.split()[1]
+        assert abs(float(a.split()[3]) - float(b.split()[3])) <= 1e-9 * abs(float(b.split()[3]))
+
+
+def test_jacobi2d_blocking_printf_with_server_thread(oracle_lib):
+    import torch
+    import paper_2306_11686_amd as gf
+    from paper_2306_11686_amd import programs
+    with gf.Context(0, rpc_capture=True, rpc_thread=True, rpc_slots=8) as ctx:
+        fmt = ctx.register_format(programs.JACOBI2D_FORMAT, "id")
+        u0 = gi.grid2d(64, seed=2)
+        _, r_naive, r_comp, _ = oracle_lib.jacobi2d(u0, 40, print_every=2)
+        g, r, _ = run_jacobi2d(ctx, u0, 40, gf.GF_EXEC_PERSISTENT, fmt_id=fmt, print_every=2, blocking=True)
+        text = ctx.take_output()
+        assert len(text.splitlines()) == 20
+        assert np.all(np.abs(r - r_comp) <= 1e-12 * r_comp)
+        torch.cuda.synchronize()
+
+
+def test_rpc_ring_wraps_with_server_thread():
+    """More posted printf calls than ring slots: the device waits for freed
+    slots while the library's server thread drains them, in FIFO order."""
+    import paper_2306_11686_amd as gf
+    from paper_2306_11686_amd import programs
+    with gf.Context(0, rpc_capture=True, rpc_thread=True, rpc_slots=8) as ctx:
+        fmt = ctx.register_format(programs.JACOBI2D_FORMAT, "id")
+        u0 = gi.grid2d(32, seed=3)
+        _, r, _ = run_jacobi2d(ctx, u0, 50, gf.GF_EXEC_PER_REGION, fmt_id=fmt, print_every=1)
+        lines = ctx.take_output().splitlines()
+        assert [int(l.split()[1]) for l in lines] == list(range(1, 51))
+        assert lines == [programs.JACOBI2D_FORMAT.strip() % (s, r[s - 1]) for s in range(1, 51)]
+
+
+def test_rpc_blocking_without_server_times_out_cleanly():
+    """A blocking RPC with nobody polling ends in the device watchdog and a
+    GF_ETIMEOUT from gf_sync, not a hang."""
+    import paper_2306_11686_amd as gf
+    from paper_2306_11686_amd import programs
+    with gf.Context(0, rpc_capture=True, rpc_timeout_us=20000) as ctx:
+        fmt = ctx.register_format(programs.JACOBI2D_FORMAT, "id")
+        u0 = gi.grid2d(16, seed=1)
+        prog = programs.jacobi2d(3, fmt_id=fmt, print_every=1, blocking=True)
+        import torch
+        u = torch.from_numpy(u0).cuda(); w = u.clone()
+        res = torch.zeros(3, dtype=torch.float64, device="cuda")
+        sc = torch.zeros(16, dtype=torch.float64, device="cuda")
+        inst = gf.Instance.make({0: u, 1: w, 2: res}, sc, ip=(16,))
+        ctx.run(prog, inst, mode=gf.GF_EXEC_PER_REGION)
+        torch.cuda.synchronize()
+        with pytest.raises(gf.GfError) as ei:
+            ctx.sync()
+        assert ei.value.status == gf.binding.GF_ETIMEOUT

@@ -1,0 +1,92 @@
+"""GPU parity of gf_reduce (reduction regions) and of the static worksharing
+schedule with continuous global thread ids."""
+import math
+
+import numpy as np
+import pytest
+
+import gf_inputs as gi
+from tests.gpu_helpers import dev, host
+
+pytestmark = pytest.mark.gpu
+
+SIZES = [0, 1, 63, 64, 65, 1000, 4097, 1 << 20, (1 << 22) + 17]
+
+
+def _reduce(ctx, op, dt, a):
+    import torch
+    import paper_2306_11686_amd as gf
+    x = dev(a)
+    out_dt = torch.float64 if dt == gf.GF_F64 else torch.int64
+    out = torch.zeros(1, dtype=out_dt, device="cuda")
+    ctx.reduce(op, dt, x, a.shape[0], out)
+    v = host(out)[0]
+    if dt in (gf.GF_U32, gf.GF_U64):
+        v = int(np.uint64(np.int64(v)))
+    return v
+
+
+@pytest.mark.parametrize("n", SIZES)
+def test_reduce_f64_sum_and_max(gfx, oracle_lib, n):
+    import paper_2306_11686_amd as gf
+    print(f"reduce f64 n={n}", flush=True)
+    a = gi.um11(1, 11, np.arange(n, dtype=np.uint64))
+    s = _reduce(gfx, gf.GF_OP_SUM, gf.GF_F64, a)
+    ref = oracle_lib.reduce("sum", a, compensated=True)
+    assert abs(s - ref) <= 1e-12 * float(np.sum(np.abs(a))) or (n == 0 and s == 0.0)
+    m = _reduce(gfx, gf.GF_OP_MAX, gf.GF_F64, a)
+    assert m == oracle_lib.reduce("max", a) if n else m == -math.inf
+    # integer-valued doubles: exact in any order
+    b = (np.arange(n) % 1024).astype(np.float64)
+    assert _reduce(gfx, gf.GF_OP_SUM, gf.GF_F64, b) == oracle_lib.reduce("sum", b)
+
+
+@pytest.mark.parametrize("n", SIZES)
+def test_reduce_integers_exact(gfx, oracle_lib, n):
+    import paper_2306_11686_amd as gf
+    h = gi.hash_u64(2, 12, np.arange(n, dtype=np.uint64))
+    u32 = (h >> np.uint64(32)).astype(np.uint32)
+    assert _reduce(gfx, gf.GF_OP_SUM, gf.GF_U32, u32) == oracle_lib.reduce("sum", u32)
+    assert _reduce(gfx, gf.GF_OP_MAX, gf.GF_U32, u32) == (oracle_lib.reduce("max", u32) if n else 0)
+    assert _reduce(gfx, gf.GF_OP_SUM, gf.GF_U64, h) == oracle_lib.reduce("sum", h)
+    assert _reduce(gfx, gf.GF_OP_MAX, gf.GF_U64, h) == (oracle_lib.reduce("max", h) if n else 0)
+    i64 = h.view(np.int64)
+    assert _reduce(gfx, gf.GF_OP_SUM, gf.GF_I64, i64) == oracle_lib.reduce("sum", i64)
+    if n:
+        assert _reduce(gfx, gf.GF_OP_MAX, gf.GF_I64, i64) == oracle_lib.reduce("max", i64)
+
+
+def test_reduce_is_deterministic(gfx):
+    import paper_2306_11686_amd as gf
+    a = gi.um11(3, 11, np.arange(3 << 20, dtype=np.uint64))
+    vals = {_reduce(gfx, gf.GF_OP_SUM, gf.GF_F64, a) for _ in range(4)}
+    assert len(vals) == 1
+
+
+@pytest.mark.parametrize("mode_name", ["persistent", "per_region"])
+@pytest.mark.parametrize("n,chunk,nwg,wg", [(1000, 0, 3, 64), (100003, 0, 37, 256), (5, 0, 2, 128),
+                                             (99991, 7, 11, 192), (4096, 1, 4, 64), (0, 0, 2, 64)])
+def test_static_schedule_owner_map(gfx, oracle_lib, mode_name, n, chunk, nwg, wg):
+    """Every iteration is executed by the thread the static-schedule formula
+    names, with ids continuous across workgroups (bit-exact)."""
+    import torch
+    import paper_2306_11686_amd as gf
+    from paper_2306_11686_amd import programs
+    mode = gf.GF_EXEC_PERSISTENT if mode_name == "persistent" else gf.GF_EXEC_PER_REGION
+    owner = torch.full((max(1, n),), -1, dtype=torch.int32, device="cuda")
+    sc = torch.zeros(16, dtype=torch.float64, device="cuda")
+    inst = gf.Instance.make({0: owner}, sc, ip=(n,))
+    gfx.run(programs.owner_map(chunk), inst, mode=mode, launch=gf.Launch.make(wg_size=wg, num_wg=nwg))
+    gfx.sync()
+    got = host(owner)[:n]
+    ref = oracle_lib.static_owner(n, nwg * wg, chunk)
+    assert np.array_equal(got, ref)
+
+
+def test_copy_kernel(gfx):
+    import torch
+    a = torch.arange(1 << 20, dtype=torch.float64, device="cuda")
+    b = torch.zeros_like(a)
+    gfx.copy(b, a, a.numel() * 8)
+    torch.cuda.synchronize()
+    assert torch.equal(a, b)

@@ -1,0 +1,60 @@
+"""CPU checks of the native library: it is built, loads, and exports every
+entry point include/gf.h declares (no compute calls without a GPU)."""
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def declared_functions():
+    names = set()
+    for fn in os.listdir(os.path.join(ROOT, "include")):
+        if fn.endswith(".h"):
+            text = open(os.path.join(ROOT, "include", fn)).read()
+            text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+            names |= set(re.findall(r"\b(gf_[a-z0-9_]+)\s*\(", text))
+    return sorted(names)
+
+
+def test_header_declares_the_boundary():
+    names = declared_functions()
+    for required in ("gf_region_run", "gf_reduce", "gf_rpc_poll", "gf_ctx_create", "gf_ctx_destroy",
+                     "gf_last_error", "gf_sync"):
+        assert required in names
+
+
+def test_library_loads_and_exports_every_declared_symbol():
+    import paper_2306_11686_amd as gf
+    lib = gf.load_library()
+    for name in declared_functions():
+        assert hasattr(lib, name), name
+    assert set(gf.exported_symbols()) == set(declared_functions())
+
+
+def test_binding_struct_layouts_match_header(tmp_path):
+    import subprocess
+    import paper_2306_11686_amd as gf
+    from paper_2306_11686_amd import binding
+    src = tmp_path / "sz.c"
+    src.write_text('#include <stdio.h>\n#include <stddef.h>\n#include "gf.h"\n'
+                   'int main(void){printf("%zu %zu %zu %zu %zu %zu %zu\\n", sizeof(gf_step), sizeof(gf_instance),'
+                   ' sizeof(gf_launch), sizeof(gf_ctx_opts), sizeof(gf_run_stats), sizeof(gf_program),'
+                   ' offsetof(gf_step, chunk)); return 0;}\n')
+    exe = tmp_path / "sz"
+    subprocess.check_call(["gcc", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)])
+    got = [int(v) for v in subprocess.check_output([str(exe)]).split()]
+    assert got == [ctypes.sizeof(gf.Step), ctypes.sizeof(gf.Instance), ctypes.sizeof(gf.Launch),
+                   ctypes.sizeof(binding.CtxOpts), ctypes.sizeof(binding.RunStats), ctypes.sizeof(gf.Program),
+                   gf.Step.chunk.offset]
+
+
+def test_programs_are_well_formed():
+    from paper_2306_11686_amd import programs
+    p = programs.cg(500)
+    assert p.n_prologue == 2 and p.n_body == 12 and p.iters == 500
+    p3 = programs.jacobi3d(200)
+    kinds = [p3.body[i].kind for i in range(p3.n_body)]
+    assert kinds == [32, 2, 37, 36]
