@@ -246,7 +246,9 @@ gf_status gf_sync(gf_ctx *ctx, void *hip_stream, gf_run_stats *stats);
 int32_t gf_persistent_capacity(gf_ctx *ctx, const gf_program *prog, int32_t wg_size);
 
 /* Device copy kernel (bandwidth probe for the HBM ceiling): d_dst = d_src,
- * nbytes a multiple of 16. */
+ * nbytes a multiple of 16. num_wg > 0: a grid-stride loop over num_wg
+ * workgroups; num_wg <= 0: one 4 x 16-byte tile per thread over the whole
+ * array. */
 gf_status gf_copy(gf_ctx *ctx, void *d_dst, const void *d_src, int64_t nbytes, int32_t num_wg,
                   void *hip_stream);
 

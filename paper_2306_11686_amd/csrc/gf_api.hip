@@ -776,7 +776,8 @@ gf_status gf_region_run(gf_ctx *ctx, const gf_program *prog, const gf_instance *
         std::memset(stats, 0, sizeof *stats);
 
     if (mode == GF_EXEC_PERSISTENT) {
-        const int cap = persistent_capacity(p, t, ctx->num_cu);
+        // the barrier tree is sized for at most 4096 workgroups
+        const int cap = std::min(4096, persistent_capacity(p, t, ctx->num_cu));
         if (cap <= 0)
             return fail(ctx, GF_EHIP, "occupancy query failed");
         for (int i = 0; i < n_inst; ++i) {
@@ -881,8 +882,6 @@ gf_status gf_copy(gf_ctx *ctx, void *d_dst, const void *d_src, int64_t nbytes, i
         return GF_EINVAL;
     if (!d_dst || !d_src || nbytes < 0 || (nbytes % 16))
         return fail(ctx, GF_EINVAL, "copy needs non-null buffers and a multiple of 16 bytes");
-    if (num_wg <= 0)
-        num_wg = ctx->num_cu * 8;
     hipSetDevice(ctx->device);
     hipError_t e = launch_copy(d_dst, d_src, nbytes, num_wg, (hipStream_t)hip_stream);
     if (e != hipSuccess)

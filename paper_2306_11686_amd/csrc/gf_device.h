@@ -97,18 +97,49 @@ __device__ __forceinline__ int32_t read_error(const int32_t *err)
     return __hip_atomic_load(err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
+// Region operands may arrive as generic pointers (the persistent kernel
+// reads them from LDS); casting them to the global address space lets the
+// compiler emit global loads with scalar bases instead of flat loads with
+// 64-bit per-lane addresses.
+#define GF_GLOBAL __attribute__((address_space(1)))
+template <typename T>
+__device__ __forceinline__ GF_GLOBAL T *gptr(T *p)
+{
+    return (GF_GLOBAL T *)p;
+}
+
+// Values every lane agrees on (read from LDS, say) moved to scalar registers.
+__device__ __forceinline__ void *uniform_ptr(void *p)
+{
+    const uint64_t v = (uint64_t)p;
+    const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)v);
+    const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(v >> 32));
+    return (void *)(((uint64_t)hi << 32) | lo);
+}
+
+__device__ __forceinline__ double uniform_f64(double d)
+{
+    const int lo = __builtin_amdgcn_readfirstlane(__double2loint(d));
+    const int hi = __builtin_amdgcn_readfirstlane(__double2hiint(d));
+    return __hiloint2double(hi, lo);
+}
+
 __device__ __forceinline__ uint64_t now_ticks() { return __builtin_amdgcn_s_memrealtime(); }
 
 // ---------------------------------------------------------------------------
 // Cross-workgroup barrier (paper, Section 3.3: an `omp barrier` inside a
 // multi-team region becomes a barrier over all teams built on global atomic
-// counters). Generation-counting barrier on one 128-byte line: word 0 counts
-// arrivals, word 1 is the generation. Each wavefront first publishes its own
-// stores at agent scope (a plain __syncthreads does not wait for stores);
-// thread 0 arrives, the last arrival resets the count and bumps the
-// generation, the others spin with relaxed agent-scope loads and s_sleep,
-// then acquire. A watchdog turns a stuck barrier into a sticky error and a
-// clean exit instead of a hang. Returns false if the kernel must stop.
+// counters). Arrivals climb a tree of counters with fan-in 16, one 128-byte
+// line each, so no line takes more than 16 atomics per barrier; the last
+// arrival at the root bumps a generation word on which every workgroup
+// waits. Each wavefront first publishes its own stores at agent scope (a
+// plain __syncthreads does not wait for stores); the last arrival of every
+// counter acquires before climbing, so the release of the generation orders
+// every workgroup's writes before every waiter's acquire. A counter is reset
+// by its last arrival before it climbs, hence before the generation moves
+// and before anyone can arrive again. A watchdog turns a stuck barrier into
+// a sticky error and a clean exit instead of a hang. Returns false if the
+// kernel must stop.
 // ---------------------------------------------------------------------------
 
 struct BarrierState {
@@ -116,36 +147,55 @@ struct BarrierState {
     int32_t ok;
 };
 
-__device__ __forceinline__ bool group_barrier(uint32_t *line, uint32_t nblocks, BarrierState *bs,
-                                              int32_t *err, int64_t timeout_ticks)
+__device__ __forceinline__ bool barrier_wait(uint32_t *genw, uint32_t g, int32_t *err, int64_t timeout_ticks)
+{
+    const uint64_t t0 = now_ticks();
+    uint32_t spins = 0;
+    while (__hip_atomic_load(genw, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == g) {
+        __builtin_amdgcn_s_sleep(1);
+        if ((++spins & 63u) == 0) {
+            if (read_error(err) != kErrNone)
+                return false;
+            if ((int64_t)(now_ticks() - t0) > timeout_ticks) {
+                set_error(err, kErrBarrierTimeout);
+                return false;
+            }
+        }
+    }
+    return true;
+}
+
+// member: this workgroup's index in the barrier's group of nmembers.
+// genw: the generation word; tree: first counter line of this barrier.
+__device__ __forceinline__ bool tree_barrier(uint32_t *genw, uint32_t *tree, uint32_t member, uint32_t nmembers,
+                                             BarrierState *bs, int32_t *err, int64_t timeout_ticks)
 {
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
     __syncthreads();
     if (threadIdx.x == 0) {
         const uint32_t g = bs->gen;
-        int32_t ok = 1;
-        const uint32_t arrived = __hip_atomic_fetch_add(&line[0], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        if (arrived == nblocks - 1) {
-            __hip_atomic_store(&line[0], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            __hip_atomic_store(&line[1], g + 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
-        } else {
-            const uint64_t t0 = now_ticks();
-            uint32_t spins = 0;
-            while (__hip_atomic_load(&line[1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == g) {
-                __builtin_amdgcn_s_sleep(1);
-                if ((++spins & 63u) == 0) {
-                    if (read_error(err) != kErrNone) {
-                        ok = 0;
-                        break;
-                    }
-                    if ((int64_t)(now_ticks() - t0) > timeout_ticks) {
-                        set_error(err, kErrBarrierTimeout);
-                        ok = 0;
-                        break;
-                    }
-                }
+        uint32_t idx = member, n = nmembers, base = 0;
+        bool top = true;
+        while (n > 1) {
+            const uint32_t grp = idx / kTreeFanIn;
+            const uint32_t size = (n - grp * kTreeFanIn) < (uint32_t)kTreeFanIn ? n - grp * kTreeFanIn : kTreeFanIn;
+            uint32_t *c = tree + (base + grp) * kLineWords;
+            const uint32_t a = __hip_atomic_fetch_add(c, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            if (a != size - 1) {
+                top = false;
+                break;
             }
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+            __hip_atomic_store(c, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            base += (n + kTreeFanIn - 1) / kTreeFanIn;
+            n = (n + kTreeFanIn - 1) / kTreeFanIn;
+            idx = grp;
         }
+        int32_t ok = 1;
+        if (top)
+            __hip_atomic_store(genw, g + 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+        else
+            ok = barrier_wait(genw, g, err, timeout_ticks) ? 1 : 0;
         __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
         bs->gen = g + 1u;
         bs->ok = ok;

@@ -101,9 +101,15 @@ struct Scratch {
 };
 
 constexpr int kLineWords = 32;  // uint32 words per 128-byte line
-// line 0: global grid barrier {count, gen}; lines 1..: per-instance group
-// barrier; lines kFinalizeLine0 + i: per-region last-workgroup counters.
-constexpr int kFinalizeLine0 = 1 + GF_MAX_INSTANCES;
+// line 0: generation word of the grid barrier; lines kTreeLine0..: the
+// arrival counters of the barrier's fan-in tree; lines kGroupLine0 + i:
+// per-instance group barriers {count, gen}; lines kFinalizeLine0 + i:
+// per-region last-workgroup counters.
+constexpr int kTreeFanIn = 16;
+constexpr int kTreeLine0 = 1;
+constexpr int kTreeLines = 512;  // >= 4096/16 + 4096/256 + 1
+constexpr int kGroupLine0 = kTreeLine0 + kTreeLines;
+constexpr int kFinalizeLine0 = kGroupLine0 + GF_MAX_INSTANCES;
 constexpr int kNumLines = kFinalizeLine0 + GF_MAX_INSTANCES;
 
 // A serial step attached to a per-region launch, with its array operand

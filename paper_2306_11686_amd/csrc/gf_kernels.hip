@@ -29,6 +29,15 @@ __host__ __device__ inline StencilGeom j3_geom(int64_t n, const Tiling &t)
     return g;
 }
 
+typedef double gf_d2 __attribute__((ext_vector_type(2)));
+
+__host__ __device__ inline StencilGeom j3v2_geom(int64_t n, const Tiling &t)
+{
+    StencilGeom g = j3_geom(n, t);
+    g.nxc = cdiv(n, 2 * (int64_t)t.wg_size);
+    return g;
+}
+
 __host__ __device__ inline StencilGeom j2_geom(int64_t n, const Tiling &t)
 {
     StencilGeom g;
@@ -45,7 +54,7 @@ int64_t region_items(const DStep &st, int64_t n, const Tiling &t)
 {
     switch (st.kind) {
     case GF_R_JACOBI3D: {
-        StencilGeom g = j3_geom(n, t);
+        StencilGeom g = (n & 1) ? j3_geom(n, t) : j3v2_geom(n, t);
         return g.nxc * g.nyt * g.nzs;
     }
     case GF_R_JACOBI2D: {
@@ -69,7 +78,7 @@ __device__ inline int64_t region_items_dev(const DStep &st, int64_t n, const Til
 {
     switch (st.kind) {
     case GF_R_JACOBI3D: {
-        StencilGeom g = j3_geom(n, t);
+        StencilGeom g = (n & 1) ? j3_geom(n, t) : j3v2_geom(n, t);
         return g.nxc * g.nyt * g.nzs;
     }
     case GF_R_JACOBI2D: {
@@ -98,9 +107,11 @@ __device__ inline int64_t region_items_dev(const DStep &st, int64_t n, const Til
 // so every value of u is fetched from memory once per tile plus the two
 // y-halo rows and two z-halo planes; x neighbours are re-read from L1.
 template <int TY>
-__device__ __forceinline__ double j3_item(const double *__restrict__ u, double *__restrict__ w, int64_t n,
-                                          int64_t item, const Tiling &t, bool want_red)
+__device__ __forceinline__ double j3_item(const double *u_, double *w_, int64_t n, int64_t item, const Tiling &t,
+                                          bool want_red)
 {
+    GF_GLOBAL const double *__restrict__ u = gptr(u_);
+    GF_GLOBAL double *__restrict__ w = gptr(w_);
     const StencilGeom g = j3_geom(n, t);
     const int64_t xc = item % g.nxc;
     const int64_t rest = item / g.nxc;
@@ -124,7 +135,7 @@ __device__ __forceinline__ double j3_item(const double *__restrict__ u, double *
     for (int r = 0; r < TY + 2; ++r)
         pc[r] = pn[r] = 0.0;
     if (xload) {
-        const double *b = u + (z0 - 1) * SZ + y0 * SY + x;
+        GF_GLOBAL const double *b = u + (z0 - 1) * SZ + y0 * SY + x;
 #pragma unroll
         for (int r = 0; r < TY; ++r)
             if (r < ny)
@@ -137,15 +148,15 @@ __device__ __forceinline__ double j3_item(const double *__restrict__ u, double *
     }
     for (int64_t z = z0; z < z1; ++z) {
         if (xload) {
-            const double *b = u + (z + 1) * SZ + (y0 - 1) * SY + x;
+            GF_GLOBAL const double *b = u + (z + 1) * SZ + (y0 - 1) * SY + x;
 #pragma unroll
             for (int r = 0; r < TY + 2; ++r)
                 if (r < ny + 2)
                     pn[r] = b[r * SY];
         }
         if (xin) {
-            const double *row = u + z * SZ + y0 * SY + x;
-            double *out = w + z * SZ + y0 * SY + x;
+            GF_GLOBAL const double *row = u + z * SZ + y0 * SY + x;
+            GF_GLOBAL double *out = w + z * SZ + y0 * SY + x;
 #pragma unroll
             for (int r = 0; r < TY; ++r) {
                 if (r < ny) {
@@ -170,12 +181,177 @@ __device__ __forceinline__ double j3_item(const double *__restrict__ u, double *
     return mx;
 }
 
+// Lane shifts across the whole wavefront (DPP wave_shr:1 / wave_shl:1):
+// lane i receives lane i-1's (shr) or lane i+1's (shl) value; the lane at
+// the wavefront edge receives 0 and is fixed up by the caller.
+__device__ __forceinline__ double wave_shr1(double v)
+{
+    const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), 0x138, 0xf, 0xf, false);
+    const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), 0x138, 0xf, 0xf, false);
+    return __hiloint2double(hi, lo);
+}
+__device__ __forceinline__ double wave_shl1(double v)
+{
+    const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), 0x130, 0xf, 0xf, false);
+    const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), 0x130, 0xf, 0xf, false);
+    return __hiloint2double(hi, lo);
+}
+
+// 3D 7-point Jacobi for even n: each thread owns an x-pair (one 16-byte load
+// per row), a column of TY rows, and marches z. x-neighbours come from the
+// adjacent lanes by DPP shifts; the edge lanes of each wavefront swap their
+// values through LDS once per plane (which also keeps the workgroup's
+// wavefronts in step), and only the workgroup's outermost lanes re-read a
+// neighbour from cache when the row spans several workgroups. y-neighbours
+// come from the thread's own rows plus two halo rows, z-neighbours from the
+// register planes. Plane z+2 is requested before plane z is computed.
+// Rows that no neighbouring tile reads again (the tile's inner rows) are
+// loaded with the streaming hint so they do not evict the halo rows that the
+// adjacent tile is about to read. FULL tiles (all TY rows present) run
+// without per-row guards; lanes past the row end load a clamped in-bounds
+// address and store nothing.
+template <int TY>
+__device__ __forceinline__ gf_d2 ld_row(GF_GLOBAL const double *p, int r)
+{
+    // r indexes rows y0-1 .. y0+TY; rows y0-1, y0, y0+TY-1, y0+TY are shared
+    if (r >= 2 && r <= TY - 1)
+        return __builtin_nontemporal_load((GF_GLOBAL const gf_d2 *)p);
+    return *(GF_GLOBAL const gf_d2 *)p;
+}
+
+template <int TY, bool FULL>
+__device__ __forceinline__ double j3v2_tile(GF_GLOBAL const double *__restrict__ u, GF_GLOBAL double *__restrict__ w,
+                                            int64_t n, int64_t x, int64_t y0, int ny, int64_t z0, int64_t z1,
+                                            bool want_red)
+{
+    __shared__ double s_edge[2][kMaxWg / kWave][TY][2];
+    const int lane = threadIdx.x & (kWave - 1);
+    const int wv = threadIdx.x / kWave;
+    const int nw = blockDim.x / kWave;
+    const bool xload = x < n;
+    const int64_t xs = xload ? x : n - 2;          // clamped load column (even, in bounds)
+    const bool in0 = xload && x >= 1;              // column x is interior (x <= n-2 as x is even)
+    const bool in1 = xload && x + 1 <= n - 2;      // column x+1 is interior
+    const bool gather_l = wv == 0 && lane == 0 && xs >= 1;
+    const bool gather_r = wv == nw - 1 && lane == kWave - 1 && xs + 2 <= n - 1;
+    const int64_t SY = n, SZ = n * n;
+    const double c6 = 1.0 / 6.0;
+    double mx = -INFINITY;
+    gf_d2 pm[TY], pc[TY + 2], pn[TY + 2], pf[TY + 2];
+    const gf_d2 zero2 = {0.0, 0.0};
+    GF_GLOBAL const double *col = u + (y0 - 1) * SY + xs;  // row y0-1 of plane 0
+#pragma unroll
+    for (int r = 0; r < TY; ++r)
+        pm[r] = (FULL || r < ny) ? ld_row<TY>(col + (z0 - 1) * SZ + (r + 1) * SY, r + 1) : zero2;
+#pragma unroll
+    for (int r = 0; r < TY + 2; ++r) {
+        pc[r] = (FULL || r < ny + 2) ? ld_row<TY>(col + z0 * SZ + r * SY, r) : zero2;
+        pn[r] = (FULL || r < ny + 2) ? ld_row<TY>(col + (z0 + 1) * SZ + r * SY, r) : zero2;
+        pf[r] = zero2;
+    }
+    for (int64_t z = z0; z < z1; ++z) {
+        if (z + 2 <= z1) {
+#pragma unroll
+            for (int r = 0; r < TY + 2; ++r)
+                if (FULL || r < ny + 2)
+                    pf[r] = ld_row<TY>(col + (z + 2) * SZ + r * SY, r);
+        }
+        const int par = (int)(z & 1);
+        if (lane == 0) {
+#pragma unroll
+            for (int r = 0; r < TY; ++r)
+                s_edge[par][wv][r][0] = pc[r + 1].x;
+        }
+        if (lane == kWave - 1) {
+#pragma unroll
+            for (int r = 0; r < TY; ++r)
+                s_edge[par][wv][r][1] = pc[r + 1].y;
+        }
+        GF_GLOBAL const double *frow = u + z * SZ + y0 * SY + xs;
+        double gl[TY], gr[TY];
+#pragma unroll
+        for (int r = 0; r < TY; ++r) {
+            gl[r] = 0.0;
+            gr[r] = 0.0;
+        }
+        if (gather_l || gather_r) {
+#pragma unroll
+            for (int r = 0; r < TY; ++r)
+                if (FULL || r < ny) {
+                    const double g = frow[r * SY + (gather_l ? -1 : 2)];
+                    gl[r] = g;
+                    gr[r] = g;
+                }
+        }
+        __syncthreads();
+        GF_GLOBAL double *out = w + z * SZ + y0 * SY + xs;
+#pragma unroll
+        for (int r = 0; r < TY; ++r) {
+            if (FULL || r < ny) {
+                const gf_d2 c = pc[r + 1];
+                const double sl = wave_shr1(c.y);
+                const double sr = wave_shl1(c.x);
+                const double el = wv > 0 ? s_edge[par][wv - 1][r][1] : gl[r];
+                const double er = wv < nw - 1 ? s_edge[par][wv + 1][r][0] : gr[r];
+                const double xl = lane == 0 ? el : sl;
+                const double xr = lane == kWave - 1 ? er : sr;
+                gf_d2 v;
+                v.x = (((xl + c.y) + (pc[r].x + pc[r + 2].x)) + (pm[r].x + pn[r + 1].x)) * c6;
+                v.y = (((c.x + xr) + (pc[r].y + pc[r + 2].y)) + (pm[r].y + pn[r + 1].y)) * c6;
+                if (in0 && in1) {
+                    __builtin_nontemporal_store(v, (GF_GLOBAL gf_d2 *)(out + r * SY));
+                } else if (in0) {
+                    out[r * SY] = v.x;
+                } else if (in1) {
+                    out[r * SY + 1] = v.y;
+                }
+                if (want_red) {
+                    const double d0 = in0 ? fabs(v.x - c.x) : -INFINITY;
+                    const double d1 = in1 ? fabs(v.y - c.y) : -INFINITY;
+                    const double d = d0 > d1 ? d0 : d1;
+                    mx = d > mx ? d : mx;
+                }
+            }
+        }
+#pragma unroll
+        for (int r = 0; r < TY; ++r)
+            pm[r] = pc[r + 1];
+#pragma unroll
+        for (int r = 0; r < TY + 2; ++r) {
+            pc[r] = pn[r];
+            pn[r] = pf[r];
+        }
+    }
+    return mx;
+}
+
+template <int TY>
+__device__ __forceinline__ double j3v2_item(const double *u_, double *w_, int64_t n, int64_t item, const Tiling &t,
+                                            bool want_red)
+{
+    const StencilGeom g = j3v2_geom(n, t);
+    const int64_t xc = item % g.nxc;
+    const int64_t rest = item / g.nxc;
+    const int64_t yt = rest % g.nyt;
+    const int64_t zs = rest / g.nyt;
+    const int64_t x = (xc * blockDim.x + threadIdx.x) * 2;
+    const int64_t y0 = 1 + yt * TY;
+    const int ny = (int)(n - 1 - y0 < TY ? n - 1 - y0 : TY);
+    const int64_t z0 = 1 + zs * t.tile_z;
+    const int64_t z1 = (z0 + t.tile_z < n - 1) ? z0 + t.tile_z : n - 1;
+    if (ny == TY)
+        return j3v2_tile<TY, true>(gptr(u_), gptr(w_), n, x, y0, ny, z0, z1, want_red);
+    return j3v2_tile<TY, false>(gptr(u_), gptr(w_), n, x, y0, ny, z0, z1, want_red);
+}
+
 // 2D 5-point Jacobi: the workgroup owns (row chunk) x (TY rows); each thread
 // holds its column of TY+2 rows in registers.
 template <int TY>
-__device__ __forceinline__ double j2_item(const double *__restrict__ u, double *__restrict__ w, int64_t n,
-                                          int64_t item, const Tiling &t, bool want_red)
+__device__ __forceinline__ double j2_item(const double *u_, double *w_, int64_t n, int64_t item, const Tiling &t,
+                                          bool want_red)
 {
+    GF_GLOBAL const double *__restrict__ u = gptr(u_);
+    GF_GLOBAL double *__restrict__ w = gptr(w_);
     const StencilGeom g = j2_geom(n, t);
     const int64_t xc = item % g.nxc;
     const int64_t yt = item / g.nxc;
@@ -185,11 +361,11 @@ __device__ __forceinline__ double j2_item(const double *__restrict__ u, double *
     double acc = 0.0;
     if (x >= 1 && x <= n - 2) {
         double col[TY + 2];
-        const double *b = u + (y0 - 1) * n + x;
+        GF_GLOBAL const double *b = u + (y0 - 1) * n + x;
 #pragma unroll
         for (int r = 0; r < TY + 2; ++r)
             col[r] = (r < ny + 2) ? b[r * n] : 0.0;
-        double *out = w + y0 * n + x;
+        GF_GLOBAL double *out = w + y0 * n + x;
 #pragma unroll
         for (int r = 0; r < TY; ++r) {
             if (r < ny) {
@@ -209,10 +385,14 @@ __device__ __forceinline__ double j2_item(const double *__restrict__ u, double *
 
 // CSR SpMV, one thread per row; the row is summed serially in stored column
 // order, as the legacy loop does.
-__device__ __forceinline__ void spmv_item(const int32_t *__restrict__ rowptr, const int32_t *__restrict__ col,
-                                          const double *__restrict__ val, const double *__restrict__ x,
-                                          double *__restrict__ y, int64_t n, int64_t item)
+__device__ __forceinline__ void spmv_item(const int32_t *rowptr_, const int32_t *col_, const double *val_,
+                                          const double *x_, double *y_, int64_t n, int64_t item)
 {
+    GF_GLOBAL const int32_t *__restrict__ rowptr = gptr(rowptr_);
+    GF_GLOBAL const int32_t *__restrict__ col = gptr(col_);
+    GF_GLOBAL const double *__restrict__ val = gptr(val_);
+    GF_GLOBAL const double *__restrict__ x = gptr(x_);
+    GF_GLOBAL double *__restrict__ y = gptr(y_);
     const int64_t row = item * blockDim.x + threadIdx.x;
     if (row < n) {
         double acc = 0.0;
@@ -223,9 +403,11 @@ __device__ __forceinline__ void spmv_item(const int32_t *__restrict__ rowptr, co
     }
 }
 
-__device__ __forceinline__ double dot_item(const double *__restrict__ a, const double *__restrict__ b, int64_t n,
-                                           int64_t item, const Tiling &t)
+__device__ __forceinline__ double dot_item(const double *a_, const double *b_, int64_t n, int64_t item,
+                                           const Tiling &t)
 {
+    GF_GLOBAL const double *__restrict__ a = gptr(a_);
+    GF_GLOBAL const double *__restrict__ b = gptr(b_);
     const int64_t base = item * chunk_elems(t);
     double acc = 0.0;
     for (int k = 0; k < t.items; ++k) {
@@ -236,9 +418,12 @@ __device__ __forceinline__ double dot_item(const double *__restrict__ a, const d
     return acc;
 }
 
-__device__ __forceinline__ void axpby_item(double *out, const double *x, double s, const double *y, int64_t n,
+__device__ __forceinline__ void axpby_item(double *out_, const double *x_, double s, const double *y_, int64_t n,
                                            int64_t item, const Tiling &t)
 {
+    GF_GLOBAL double *out = gptr(out_);
+    GF_GLOBAL const double *x = gptr(x_);
+    GF_GLOBAL const double *y = gptr(y_);
     const int64_t base = item * chunk_elems(t);
     for (int k = 0; k < t.items; ++k) {
         const int64_t i = base + (int64_t)k * blockDim.x + threadIdx.x;
@@ -247,14 +432,16 @@ __device__ __forceinline__ void axpby_item(double *out, const double *x, double 
     }
 }
 
-__device__ __forceinline__ void hist_item(const uint32_t *__restrict__ keys, uint32_t *bins, uint32_t mask,
-                                          int64_t n, int64_t item, const Tiling &t)
+__device__ __forceinline__ void hist_item(const uint32_t *keys_, uint32_t *bins_, uint32_t mask, int64_t n,
+                                          int64_t item, const Tiling &t)
 {
+    GF_GLOBAL const uint32_t *__restrict__ keys = gptr(keys_);
+    GF_GLOBAL uint32_t *bins = gptr(bins_);
     const int64_t base = item * chunk_elems(t);
     for (int k = 0; k < t.items; ++k) {
         const int64_t i = base + (int64_t)k * blockDim.x + threadIdx.x;
         if (i < n)
-            atomicAdd(&bins[keys[i] & mask], 1u);
+            __hip_atomic_fetch_add(&bins[keys[i] & mask], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     }
 }
 
@@ -283,8 +470,11 @@ __device__ __forceinline__ double region_item(const DStep &st, void *const *op, 
     const bool red = st.red_op != GF_OP_NONE;
     switch (st.kind) {
     case GF_R_JACOBI3D:
-        if constexpr ((KMASK >> GF_R_JACOBI3D) & 1u)
+        if constexpr ((KMASK >> GF_R_JACOBI3D) & 1u) {
+            if ((n & 1) == 0)
+                return j3v2_item<TY>((const double *)op[0], (double *)op[1], n, item, t, red);
             return j3_item<TY>((const double *)op[0], (double *)op[1], n, item, t, red);
+        }
         break;
     case GF_R_JACOBI2D:
         if constexpr ((KMASK >> GF_R_JACOBI2D) & 1u)
@@ -374,13 +564,14 @@ __global__ void __launch_bounds__(kMaxWg) k_persistent(DProg prog, DInst inst, T
 
     const int64_t G = gridDim.x;
     const int64_t worker = worker_id(blockIdx.x, G, t.xcd_remap);
-    uint32_t *line = scr.lines;  // line 0: the grid barrier
+    uint32_t *genw = scr.lines + 1;  // line 0, word 1: the grid barrier's generation
+    uint32_t *tree = scr.lines + kTreeLine0 * kLineWords;
     if (threadIdx.x < GF_MAX_SCALARS)
         s_scal[threadIdx.x] = inst.scal[threadIdx.x];
     if (threadIdx.x < GF_MAX_ARRAYS)
         s_arr[threadIdx.x] = inst.arr[threadIdx.x];
     if (threadIdx.x == 0) {
-        s_bar.gen = __hip_atomic_load(&line[1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        s_bar.gen = __hip_atomic_load(genw, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         s_bar.ok = 1;
     }
     __syncthreads();
@@ -406,8 +597,8 @@ __global__ void __launch_bounds__(kMaxWg) k_persistent(DProg prog, DInst inst, T
             void *op[5];
 #pragma unroll
             for (int k = 0; k < 5; ++k)
-                op[k] = st.arr[k] >= 0 ? s_arr[st.arr[k]] : nullptr;
-            const double coef = (st.kind == GF_R_AXPBY) ? s_scal[st.sc[1]] * st.c : 0.0;
+                op[k] = uniform_ptr(st.arr[k] >= 0 ? s_arr[st.arr[k]] : nullptr);
+            const double coef = uniform_f64((st.kind == GF_R_AXPBY) ? s_scal[st.sc[1]] * st.c : 0.0);
             if (st.kind == GF_R_OWNER) {
                 owner_region((int32_t *)op[0], n, st.chunk, G * blockDim.x,
                              (int64_t)blockIdx.x * blockDim.x + threadIdx.x);
@@ -421,7 +612,7 @@ __global__ void __launch_bounds__(kMaxWg) k_persistent(DProg prog, DInst inst, T
                             part[it] = v;
                     }
                 }
-                if (!group_barrier(line, (uint32_t)G, &s_bar, scr.error, scr.barrier_timeout_ticks))
+                if (!tree_barrier(genw, tree, blockIdx.x, (uint32_t)G, &s_bar, scr.error, scr.barrier_timeout_ticks))
                     return;
                 if (red) {
                     const double v = reduce_partials(st.red_op, part, nitems, s_red);
@@ -432,7 +623,7 @@ __global__ void __launch_bounds__(kMaxWg) k_persistent(DProg prog, DInst inst, T
                 __syncthreads();
                 continue;
             }
-            if (!group_barrier(line, (uint32_t)G, &s_bar, scr.error, scr.barrier_timeout_ticks))
+            if (!tree_barrier(genw, tree, blockIdx.x, (uint32_t)G, &s_bar, scr.error, scr.barrier_timeout_ticks))
                 return;
         } else if (threadIdx.x == 0) {
             if (st.kind == GF_S_SWAP) {
@@ -783,17 +974,57 @@ hipError_t launch_reduce(int op, int dt, const void *in, int64_t n, void *out, c
 
 __global__ void __launch_bounds__(kMaxWg) k_copy(const double2 *__restrict__ src, double2 *__restrict__ dst, int64_t n)
 {
+    // four 16-byte loads in flight per thread per trip
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    for (; i + 3 * stride < n; i += 4 * stride) {
+        double2 v[4];
+#pragma unroll
+        for (int k = 0; k < 4; ++k)
+            v[k] = src[i + k * stride];
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            __builtin_nontemporal_store(v[k].x, &dst[i + k * stride].x);
+            __builtin_nontemporal_store(v[k].y, &dst[i + k * stride].y);
+        }
+    }
+    for (; i < n; i += stride) {
         const double2 v = src[i];
         __builtin_nontemporal_store(v.x, &dst[i].x);
         __builtin_nontemporal_store(v.y, &dst[i].y);
     }
 }
 
+// One tile of 4 x 16 bytes per thread, no grid-stride loop: the whole array
+// is covered by the grid (STREAM-style).
+__global__ void __launch_bounds__(kMaxWg) k_copy_tiles(const double2 *__restrict__ src, double2 *__restrict__ dst,
+                                                      int64_t n)
+{
+    const int64_t base = (int64_t)blockIdx.x * blockDim.x * 4 + threadIdx.x;
+    double2 v[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k)
+        if (base + k * blockDim.x < n)
+            v[k] = src[base + k * blockDim.x];
+#pragma unroll
+    for (int k = 0; k < 4; ++k)
+        if (base + k * blockDim.x < n) {
+            __builtin_nontemporal_store(v[k].x, &dst[base + k * blockDim.x].x);
+            __builtin_nontemporal_store(v[k].y, &dst[base + k * blockDim.x].y);
+        }
+}
+
 hipError_t launch_copy(void *dst, const void *src, int64_t nbytes, int num_wg, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_copy, dim3(num_wg), dim3(kMaxWg), 0, s, (const double2 *)src, (double2 *)dst, nbytes / 16);
+    const int64_t n = nbytes / 16;
+    if (num_wg <= 0) {
+        const int64_t g = cdiv(n, (int64_t)kMaxWg * 4);
+        if (g > 0)
+            hipLaunchKernelGGL(k_copy_tiles, dim3((unsigned)g), dim3(kMaxWg), 0, s, (const double2 *)src,
+                               (double2 *)dst, n);
+        return hipGetLastError();
+    }
+    hipLaunchKernelGGL(k_copy, dim3(num_wg), dim3(kMaxWg), 0, s, (const double2 *)src, (double2 *)dst, n);
     return hipGetLastError();
 }
 

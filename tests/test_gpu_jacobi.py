@@ -36,10 +36,14 @@ def test_jacobi3d_small_odd_shapes(gfx, oracle_lib, mode, n, sweeps):
 @pytest.mark.parametrize("ty,tz,wg,remap", [(1, 1, 64, 0), (2, 7, 128, 1), (4, 16, 192, 0), (8, 64, 256, 1),
                                             (16, 5, 256, 1), (8, 300, 64, 1)])
 @pytest.mark.parametrize("mode", ["persistent", "per_region"])
-def test_jacobi3d_tilings(gfx, oracle_lib, ty, tz, wg, remap, mode):
+@pytest.mark.parametrize("n", [41, 64, 300])
+def test_jacobi3d_tilings(gfx, oracle_lib, ty, tz, wg, remap, mode, n):
+    """Odd n runs the one-value-per-thread tile, even n the x-pair tile with
+    lane shifts (n = 300 spans several row chunks for small workgroups)."""
     import paper_2306_11686_amd as gf
-    n = 41
-    print(f"jacobi3d tiling ty={ty} tz={tz} wg={wg} remap={remap} mode={mode}", flush=True)
+    if n == 300 and wg != 64:
+        pytest.skip("one configuration per large grid keeps the suite short")
+    print(f"jacobi3d tiling n={n} ty={ty} tz={tz} wg={wg} remap={remap} mode={mode}", flush=True)
     u0 = gi.grid3d(n, seed=2)
     g_ref, r_ref = oracle_lib.jacobi3d(u0, 3)
     launch = gf.Launch.make(wg_size=wg, tile_y=ty, tile_z=tz, xcd_remap=remap)
@@ -167,3 +171,56 @@ def test_rpc_blocking_without_server_times_out_cleanly():
         with pytest.raises(gf.GfError) as ei:
             ctx.sync()
         assert ei.value.status == gf.binding.GF_ETIMEOUT
+
+
+def _bench_launch(gf):
+    import bench
+    tuned = bench.load_tuned("jacobi3d_512") or {}
+    return gf.Launch.make(wg_size=tuned.get("wg_size", 0), num_wg=tuned.get("num_wg", 0),
+                          tile_y=tuned.get("tile_y", 0), tile_z=tuned.get("tile_z", 0),
+                          xcd_remap=tuned.get("xcd_remap", 1))
+
+
+@pytest.mark.parametrize("mode", ["persistent", "per_region"])
+def test_jacobi3d_512_full_size_first_sweeps(gfx, oracle_lib, mode):
+    """512^3 in the launch configuration the benchmark times: the first two
+    sweeps compared element by element with the oracle."""
+    import paper_2306_11686_amd as gf
+    print(f"jacobi3d 512 full mode={mode}", flush=True)
+    u0 = gi.grid3d(512, seed=1)
+    g_ref, r_ref = oracle_lib.jacobi3d(u0, 2)
+    g, r, _ = run_jacobi3d(gfx, u0, 2, _mode(gf, mode), launch=_bench_launch(gf))
+    assert np.array_equal(r, r_ref)
+    assert np.array_equal(g, g_ref)
+
+
+def test_jacobi3d_512_lockstep_after_200_sweeps(gfx, oracle_lib):
+    """After the benchmark's 200 persistent sweeps, one more GPU sweep must
+    equal one oracle sweep from the GPU's own state (grid bit-exact, max
+    residual exact); the residual history must decay monotonically."""
+    import torch
+    import paper_2306_11686_amd as gf
+    from paper_2306_11686_amd import programs
+    from tests.gpu_helpers import host, scalars
+    print("jacobi3d 512 lockstep", flush=True)
+    n = 512
+    u0 = gi.grid3d(n, seed=1)
+    u = torch.from_numpy(u0).cuda()
+    w = u.clone()
+    res = torch.zeros(200, dtype=torch.float64, device="cuda")
+    sc = scalars()
+    inst = gf.Instance.make({0: u, 1: w, 2: res}, sc, ip=(n,))
+    gfx.run(programs.jacobi3d(200), inst, mode=gf.GF_EXEC_PERSISTENT, launch=_bench_launch(gf))
+    gfx.sync()
+    r200 = host(res)
+    assert np.all(np.diff(r200) <= 0.0)
+    state = host(u)
+    del u0
+    res1 = torch.zeros(1, dtype=torch.float64, device="cuda")
+    inst1 = gf.Instance.make({0: u, 1: w, 2: res1}, sc, ip=(n,))
+    gfx.run(programs.jacobi3d(1), inst1, mode=gf.GF_EXEC_PERSISTENT, launch=_bench_launch(gf))
+    gfx.sync()
+    g_gpu = host(w)
+    g_ref, r_ref = oracle_lib.jacobi3d(state, 1)
+    assert host(res1)[0] == r_ref[0]
+    assert np.array_equal(g_gpu, g_ref)
