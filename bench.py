@@ -90,7 +90,7 @@ def time_mode(ctx, gf, torch, prog, inst, mode, launch, steps, warmup):
     return (t1 - t0) * 1e3 / steps, sum(ev_ms) / len(ev_ms), stats
 
 
-def cpu_baseline(u0, n, budget_s=15.0, max_sweeps=40):
+def cpu_baseline(u0, n, budget_s=15.0, max_sweeps=200):
     """The serial oracle on this host's cores (one thread) for a bounded
     number of sweeps of the same 512^3 workload."""
     import numpy as np
