@@ -47,7 +47,8 @@ def build(force: bool = True) -> str:
 def _fill_lib():
     global _fill
     if _fill is None:
-        if not os.path.exists(_FILL_SO):
+        src = os.path.join(_HERE, "fill.c")
+        if not os.path.exists(_FILL_SO) or os.path.getmtime(src) > os.path.getmtime(_FILL_SO):
             try:
                 build(force=True)
             except (OSError, subprocess.CalledProcessError):
@@ -57,6 +58,7 @@ def _fill_lib():
         lib.gfi_u01.argtypes = [U64, U64, U64, I64, P]
         lib.gfi_grid3d.argtypes = [I64, U64, U64, P]
         lib.gfi_keys_u32.argtypes = [U64, U64, U64, I64, P]
+        lib.gfi_keys_zipf.argtypes = [U64, U64, U64, I64, P, I64, P]
         _fill = lib
     return _fill
 
@@ -258,9 +260,15 @@ def zipf_cdf(ranks: int = 65536, s: float = 1.1) -> np.ndarray:
 
 
 def hist_keys_zipf(n: int, seed: int = 1, ranks: int = 65536, s: float = 1.1,
-                   chunk: int = 1 << 22) -> np.ndarray:
+                   chunk: int = 1 << 22, fast: bool = True) -> np.ndarray:
     """key = (rank-1) | (high 16 random bits << 16): bin (key mod 65536) = rank-1."""
     cdf = zipf_cdf(ranks, s)
+    lib = _fill_lib() if fast else None
+    if lib is not None:
+        keys = np.empty(n, dtype=np.uint32)
+        lib.gfi_keys_zipf(seed, STREAM_ZIPF, STREAM_HIST, n, cdf.ctypes.data_as(ctypes.c_void_p), ranks,
+                          keys.ctypes.data_as(ctypes.c_void_p))
+        return keys
     keys = np.empty(n, dtype=np.uint32)
     for st in range(0, n, chunk):
         e = min(n, st + chunk)

@@ -48,3 +48,26 @@ void gfi_keys_u32(uint64_t seed, uint64_t stream, uint64_t start, int64_t count,
     for (int64_t i = 0; i < count; ++i)
         keys[i] = (uint32_t)(mix64(b + (start + (uint64_t)i + 1) * GAMMA) >> 32);
 }
+
+/* Zipf keys: rank index = smallest r with cdf[r] >= U01(seed, zstream, i)
+ * (clamped to ranks-1), high 16 bits from H(seed, hstream, i) >> 48. */
+void gfi_keys_zipf(uint64_t seed, uint64_t zstream, uint64_t hstream, int64_t count, const double *cdf,
+                   int64_t ranks, uint32_t *keys)
+{
+    const uint64_t bz = base_of(seed, zstream), bh = base_of(seed, hstream);
+    for (int64_t i = 0; i < count; ++i) {
+        const double u = (double)(mix64(bz + ((uint64_t)i + 1) * GAMMA) >> 11) * 0x1.0p-53;
+        int64_t lo = 0, hi = ranks; /* first index in [lo, hi) with cdf >= u */
+        while (lo < hi) {
+            const int64_t mid = lo + (hi - lo) / 2;
+            if (cdf[mid] < u)
+                lo = mid + 1;
+            else
+                hi = mid;
+        }
+        if (lo > ranks - 1)
+            lo = ranks - 1;
+        const uint32_t hi16 = (uint32_t)(mix64(bh + ((uint64_t)i + 1) * GAMMA) >> 48);
+        keys[i] = (uint32_t)lo | (hi16 << 16);
+    }
+}

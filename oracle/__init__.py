@@ -28,7 +28,7 @@ _lib = None
 
 def build(force: bool = True) -> str:
     """Compile liboracle.so with gcc (no contraction, IEEE double)."""
-    if force or not os.path.exists(_SO):
+    if force or not os.path.exists(_SO) or os.path.getmtime(_SRC) > os.path.getmtime(_SO):
         tmp = _SO + ".tmp"
         subprocess.check_call(["gcc", "-O2", "-ffp-contract=off", "-fno-fast-math", "-std=c11",
                                "-Wall", "-Wextra", "-shared", "-fPIC", "-o", tmp, _SRC, "-lm"])
@@ -40,7 +40,7 @@ def _load():
     global _lib
     if _lib is not None:
         return _lib
-    if not os.path.exists(_SO):
+    if not os.path.exists(_SO) or os.path.getmtime(_SRC) > os.path.getmtime(_SO):
         build(force=True)
     lib = ctypes.CDLL(_SO)
     P = ctypes.c_void_p

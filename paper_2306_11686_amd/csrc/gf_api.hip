@@ -238,7 +238,8 @@ gf_status gf_ctx_create(int32_t hip_device, const gf_ctx_opts *opts, gf_ctx **ou
     const int64_t cap = 1 << 20;
     const size_t part_bytes = 2 * cap * sizeof(double);
     const size_t line_bytes = (size_t)kNumLines * 128;
-    const size_t total = part_bytes + line_bytes + 256;
+    const size_t hist_bytes = (size_t)kHistRowsMax * 32768 * sizeof(uint32_t);
+    const size_t total = part_bytes + line_bytes + 256 + hist_bytes;
     char *base = nullptr;
     if ((e = hipMalloc((void **)&base, total)) != hipSuccess) {
         delete ctx;
@@ -254,6 +255,7 @@ gf_status gf_ctx_create(int32_t hip_device, const gf_ctx_opts *opts, gf_ctx **ou
     ctx->scr.partials_cap = cap;
     ctx->scr.lines = (uint32_t *)(base + part_bytes);
     ctx->scr.error = (int32_t *)(base + part_bytes + line_bytes);
+    ctx->scr.hist_rows = (uint32_t *)(base + part_bytes + line_bytes + 256);
     const int64_t btus = o.barrier_timeout_us > 0 ? o.barrier_timeout_us : 10 * 1000 * 1000;
     ctx->scr.barrier_timeout_ticks = btus * 100;
 
@@ -416,8 +418,8 @@ gf_status check_step(gf_ctx *ctx, const gf_step &s, int idx)
             return fail(ctx, GF_EINVAL, "step %d: reduction target out of range", idx);
         if (s.kind == GF_R_AXPBY && !sc_ok(s.sc[1]))
             return fail(ctx, GF_EINVAL, "step %d: AXPBY coefficient slot out of range", idx);
-        if (s.kind == GF_R_HIST && (s.mask & (s.mask + 1u)) != 0)
-            return fail(ctx, GF_EINVAL, "step %d: histogram mask must be 2^k - 1", idx);
+        if (s.kind == GF_R_HIST && ((s.mask & (s.mask + 1u)) != 0 || s.mask >= (1u << 20)))
+            return fail(ctx, GF_EINVAL, "step %d: histogram mask must be 2^k - 1 with at most 2^20 bins", idx);
         if (s.kind == GF_R_OWNER && s.chunk < 0)
             return fail(ctx, GF_EINVAL, "step %d: negative chunk", idx);
         return GF_OK;
@@ -509,7 +511,7 @@ Tiling choose_tiling(const DProg &p, const gf_launch *l)
     Tiling t;
     std::memset(&t, 0, sizeof t);
     const unsigned m = program_region_mask(p);
-    t.wg_size = 256;
+    t.wg_size = program_is_hist_family(p) ? 1024 : 256;
     t.tile_y = (m & (1u << GF_R_JACOBI3D)) ? 8 : ((m & (1u << GF_R_JACOBI2D)) ? 1 : 1);
     t.tile_z = 64;
     t.items = 4;
@@ -528,10 +530,11 @@ Tiling choose_tiling(const DProg &p, const gf_launch *l)
     return t;
 }
 
-gf_status check_tiling(gf_ctx *ctx, const Tiling &t)
+gf_status check_tiling(gf_ctx *ctx, const DProg &p, const Tiling &t)
 {
-    if (t.wg_size < 64 || t.wg_size > 256 || (t.wg_size % 64))
-        return fail(ctx, GF_EINVAL, "wg_size must be 64, 128, 192 or 256");
+    const int maxwg = program_is_hist_family(p) ? 1024 : 256;
+    if (t.wg_size < 64 || t.wg_size > maxwg || (t.wg_size % 64))
+        return fail(ctx, GF_EINVAL, "wg_size must be a multiple of 64 in [64, %d]", maxwg);
     if (!(t.tile_y == 1 || t.tile_y == 2 || t.tile_y == 4 || t.tile_y == 8 || t.tile_y == 16))
         return fail(ctx, GF_EINVAL, "tile_y must be 1, 2, 4, 8 or 16");
     if (t.tile_z < 1 || t.tile_z > 1 << 20)
@@ -566,6 +569,8 @@ gf_status build_program(gf_ctx *ctx, const gf_program *prog, DProg *out)
             return st;
         out->steps[i] = to_dev(s);
     }
+    if (program_mixes_hist(*out))
+        return fail(ctx, GF_EUNSUPPORTED, "a histogram region can only share a program with schedule regions");
     return GF_OK;
 }
 
@@ -584,6 +589,8 @@ gf_status check_instance(gf_ctx *ctx, const DProg &p, const gf_instance &in, con
                 return fail(ctx, GF_EINVAL, "instance %d step %d: negative size", idx, i);
             if ((s.kind == GF_R_JACOBI2D || s.kind == GF_R_JACOBI3D) && n > (1 << 20))
                 return fail(ctx, GF_EINVAL, "instance %d step %d: grid side too large", idx, i);
+            if (s.kind == GF_R_HIST && ((uintptr_t)in.arr[s.arr[0]] % 16) != 0)
+                return fail(ctx, GF_EINVAL, "instance %d step %d: histogram keys must be 16-byte aligned", idx, i);
             if (s.kind == GF_R_OWNER && n > INT32_MAX)
                 return fail(ctx, GF_EINVAL, "instance %d step %d: owner map larger than int32", idx, i);
             if (s.red_op != GF_OP_NONE && region_items(s, n, t) > ctx->scr.partials_cap)
@@ -607,10 +614,21 @@ int64_t max_items(const DProg &p, const gf_instance &in, const Tiling &t)
 }
 
 // Grid of a per-region launch: one workgroup per work item up to 16 per CU.
+// Histogram grid: a multiple of the bin-part count, at most kHistRowsMax.
+int hist_grid(int64_t want, uint32_t mask)
+{
+    const int64_t parts = hist_parts(mask);
+    int64_t g = std::min<int64_t>(want, kHistRowsMax);
+    g -= g % parts;
+    return (int)std::max<int64_t>(g, parts);
+}
+
 int region_grid(const gf_ctx *ctx, const DStep &s, int64_t items, const Tiling &t)
 {
     if (s.kind == GF_R_OWNER)
         return std::max(1, ctx->num_cu);
+    if (s.kind == GF_R_HIST)
+        return hist_grid(std::min<int64_t>(std::max<int64_t>(items, 1), (int64_t)ctx->num_cu * 2), s.mask);
     const int64_t cap = (int64_t)ctx->num_cu * 16;
     return (int)std::max<int64_t>(1, std::min<int64_t>(items, cap));
 }
@@ -635,7 +653,20 @@ gf_status enqueue_per_region(gf_ctx *ctx, const DProg &p, const gf_instance &in,
         if (is_region(cur.step.kind)) {
             grid = region_grid(ctx, cur.step, cur.n_items, t);
             if (l && l->num_wg > 0)
-                grid = l->num_wg;
+                grid = cur.step.kind == GF_R_HIST ? hist_grid(l->num_wg, cur.step.mask) : l->num_wg;
+        }
+        if (cur.step.kind == GF_R_HIST) {
+            RegionLaunch p1 = cur;
+            p1.n_glue = 0;
+            hipError_t e = launch_region(p1, t, grid, ctx->scr, rpc, stream);
+            if (e == hipSuccess)
+                e = launch_hist_merge(cur, grid, ctx->scr, rpc, ctx->num_cu, stream);
+            if (e != hipSuccess)
+                return hipfail(ctx, e, "histogram launch");
+            launches += 2;
+            max_grid = std::max(max_grid, grid);
+            pending = false;
+            return GF_OK;
         }
         hipError_t e = launch_region(cur, t, grid, ctx->scr, rpc, stream);
         if (e != hipSuccess)
@@ -745,7 +776,7 @@ int32_t gf_persistent_capacity(gf_ctx *ctx, const gf_program *prog, int32_t wg_s
     gf_launch l{};
     l.wg_size = wg_size;
     Tiling t = choose_tiling(p, wg_size > 0 ? &l : nullptr);
-    if (check_tiling(ctx, t) != GF_OK)
+    if (check_tiling(ctx, p, t) != GF_OK)
         return 0;
     hipSetDevice(ctx->device);
     return persistent_capacity(p, t, ctx->num_cu);
@@ -765,7 +796,7 @@ gf_status gf_region_run(gf_ctx *ctx, const gf_program *prog, const gf_instance *
     if (st != GF_OK)
         return st;
     Tiling t = choose_tiling(p, launch);
-    if ((st = check_tiling(ctx, t)) != GF_OK)
+    if ((st = check_tiling(ctx, p, t)) != GF_OK)
         return st;
     for (int i = 0; i < n_inst; ++i)
         if ((st = check_instance(ctx, p, inst[i], t, i)) != GF_OK)
@@ -786,6 +817,16 @@ gf_status gf_region_run(gf_ctx *ctx, const gf_program *prog, const gf_instance *
                 if (launch->num_wg > cap)
                     return fail(ctx, GF_EINVAL, "num_wg %d exceeds the co-resident capacity %d", launch->num_wg, cap);
                 grid = launch->num_wg;
+            }
+            if (program_is_hist_family(p)) {
+                uint32_t mask = 0;
+                for (int k = 0; k < p.n_steps; ++k)
+                    if (p.steps[k].kind == GF_R_HIST)
+                        mask = std::max(mask, p.steps[k].mask);
+                const int want = (launch && launch->num_wg > 0) ? launch->num_wg : cap;
+                grid = hist_grid(want, mask);
+                if (grid > cap)
+                    return fail(ctx, GF_EINVAL, "histogram needs %d co-resident workgroups, capacity %d", grid, cap);
             }
             DInst di;
             std::memcpy(di.arr, inst[i].arr, sizeof di.arr);

@@ -98,7 +98,10 @@ struct Scratch {
     uint32_t *lines;         // counters: line i = lines + 32*i
     int32_t *error;          // sticky device error word
     int64_t barrier_timeout_ticks;
+    uint32_t *hist_rows;     // histogram partial rows (kHistRowsMax rows of 32768 u32)
 };
+
+constexpr int kHistRowsMax = 512;
 
 constexpr int kLineWords = 32;  // uint32 words per 128-byte line
 // line 0: generation word of the grid barrier; lines kTreeLine0..: the
@@ -152,5 +155,13 @@ hipError_t launch_copy(void *dst, const void *src, int64_t nbytes, int num_wg, h
 
 // Number of work items (tiles / chunks) a region splits into under tiling t.
 int64_t region_items(const DStep &st, int64_t n, const Tiling &t);
+
+// Histogram support: the histogram runs in its own kernel family (1024-thread
+// workgroups, 128 KiB LDS); phase 1 writes one partial row per workgroup.
+bool program_is_hist_family(const DProg &prog);
+bool program_mixes_hist(const DProg &prog);
+int64_t hist_parts(uint32_t mask);
+hipError_t launch_hist_merge(const RegionLaunch &rl, int64_t rows_used, const Scratch &scr, const RpcRing &rpc,
+                             int num_cu, hipStream_t s);
 
 }  // namespace gf

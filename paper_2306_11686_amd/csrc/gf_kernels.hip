@@ -6,8 +6,10 @@
 
 namespace gf {
 
-constexpr int kMaxWg = 256;         // workgroup size limit of every kernel here
-constexpr int kLdsRed = kMaxWg / kWave;
+constexpr int kMaxWg = 256;         // workgroup size limit of the region kernels
+constexpr int kMaxWgHist = 1024;    // histogram kernels (one 128 KiB workgroup per CU)
+constexpr int kLdsRed = kMaxWgHist / kWave;
+constexpr int kHistPart = 32768;    // bins counted per workgroup pass (128 KiB of u32 in LDS)
 
 // ---------------------------------------------------------------------------
 // Work decomposition shared by host and device.
@@ -50,6 +52,24 @@ __host__ __device__ inline StencilGeom j2_geom(int64_t n, const Tiling &t)
 
 __host__ __device__ inline int64_t chunk_elems(const Tiling &t) { return (int64_t)t.wg_size * t.items; }
 
+// Histogram work: chunks of wg_size * items * 4 keys (each thread reads
+// `items` 16-byte groups of four keys); every chunk is counted once per part
+// of kHistPart bins, and item = chunk * parts + part.
+struct HistGeom {
+    int64_t nbins, parts, chunk_keys, nchunks, nitems;
+};
+
+__host__ __device__ inline HistGeom hist_geom(int64_t n, uint32_t mask, const Tiling &t)
+{
+    HistGeom g;
+    g.nbins = (int64_t)mask + 1;
+    g.parts = cdiv(g.nbins, kHistPart);
+    g.chunk_keys = (int64_t)t.wg_size * t.items * 4;
+    g.nchunks = cdiv(n, g.chunk_keys);
+    g.nitems = g.nchunks * g.parts;
+    return g;
+}
+
 int64_t region_items(const DStep &st, int64_t n, const Tiling &t)
 {
     switch (st.kind) {
@@ -65,8 +85,9 @@ int64_t region_items(const DStep &st, int64_t n, const Tiling &t)
         return cdiv(n, t.wg_size);
     case GF_R_DOT:
     case GF_R_AXPBY:
-    case GF_R_HIST:
         return cdiv(n, chunk_elems(t));
+    case GF_R_HIST:
+        return hist_geom(n, st.mask, t).nitems;
     case GF_R_OWNER:
         return 0;  // thread-level static schedule, no tiles
     default:
@@ -89,8 +110,9 @@ __device__ inline int64_t region_items_dev(const DStep &st, int64_t n, const Til
         return cdiv(n, t.wg_size);
     case GF_R_DOT:
     case GF_R_AXPBY:
-    case GF_R_HIST:
         return cdiv(n, chunk_elems(t));
+    case GF_R_HIST:
+        return hist_geom(n, st.mask, t).nitems;
     default:
         return 0;
     }
@@ -383,18 +405,41 @@ __device__ __forceinline__ double j2_item(const double *u_, double *w_, int64_t 
     return acc;
 }
 
-// CSR SpMV, one thread per row; the row is summed serially in stored column
-// order, as the legacy loop does.
+// CSR SpMV over a block of blockDim rows (CSR-stream): the block's products
+// val[k] * x[col[k]] are formed by a coalesced pass over its nonzeros into
+// LDS, then each thread sums its own row serially in stored column order,
+// exactly as the legacy loop does (same products, same order, no
+// contraction). Blocks with more nonzeros than the LDS tile fall back to one
+// thread per row reading global memory.
+constexpr int kSpmvLds = 4096;  // doubles (32 KiB)
+
 __device__ __forceinline__ void spmv_item(const int32_t *rowptr_, const int32_t *col_, const double *val_,
                                           const double *x_, double *y_, int64_t n, int64_t item)
 {
+    __shared__ double s_prod[kSpmvLds];
     GF_GLOBAL const int32_t *__restrict__ rowptr = gptr(rowptr_);
     GF_GLOBAL const int32_t *__restrict__ col = gptr(col_);
     GF_GLOBAL const double *__restrict__ val = gptr(val_);
     GF_GLOBAL const double *__restrict__ x = gptr(x_);
     GF_GLOBAL double *__restrict__ y = gptr(y_);
-    const int64_t row = item * blockDim.x + threadIdx.x;
-    if (row < n) {
+    const int64_t r0 = item * blockDim.x;
+    const int64_t r1 = r0 + blockDim.x < n ? r0 + blockDim.x : n;
+    const int64_t row = r0 + threadIdx.x;
+    const int32_t k0 = rowptr[r0];
+    const int32_t k1 = rowptr[r1];
+    if (k1 - k0 <= kSpmvLds) {
+        for (int32_t k = k0 + (int32_t)threadIdx.x; k < k1; k += (int32_t)blockDim.x)
+            s_prod[k - k0] = val[k] * x[col[k]];
+        __syncthreads();
+        if (row < n) {
+            const int32_t b = rowptr[row] - k0, e = rowptr[row + 1] - k0;
+            double acc = 0.0;
+            for (int32_t k = b; k < e; ++k)
+                acc = acc + s_prod[k];
+            y[row] = acc;
+        }
+        __syncthreads();
+    } else if (row < n) {
         double acc = 0.0;
         const int32_t e = rowptr[row + 1];
         for (int32_t k = rowptr[row]; k < e; ++k)
@@ -432,16 +477,68 @@ __device__ __forceinline__ void axpby_item(double *out_, const double *x_, doubl
     }
 }
 
-__device__ __forceinline__ void hist_item(const uint32_t *keys_, uint32_t *bins_, uint32_t mask, int64_t n,
-                                          int64_t item, const Tiling &t)
+// Histogram, phase 1: this worker counts the keys of its chunks whose bin
+// falls in its part (all of a worker's items share one part because the
+// worker stride is a multiple of the part count) into 32-bit LDS counters,
+// then writes them as its partial row. Integer counts are exact in any order.
+__device__ __forceinline__ void hist_phase1(const uint32_t *keys_, uint32_t *rows_, uint32_t mask, int64_t n,
+                                            int64_t worker, int64_t G, const Tiling &t)
 {
+    __shared__ uint32_t s_h[kHistPart];
     GF_GLOBAL const uint32_t *__restrict__ keys = gptr(keys_);
+    const HistGeom g = hist_geom(n, mask, t);
+    const int64_t part = worker % g.parts;
+    const uint32_t lo = (uint32_t)(part * kHistPart);
+    const int64_t span64 = g.nbins - (int64_t)lo < kHistPart ? g.nbins - (int64_t)lo : kHistPart;
+    const uint32_t span = (uint32_t)span64;
+    for (int i = threadIdx.x; i < kHistPart; i += blockDim.x)
+        s_h[i] = 0u;
+    __syncthreads();
+    for (int64_t it = worker; it < g.nitems; it += G) {
+        const int64_t base = (it / g.parts) * g.chunk_keys;
+        for (int k = 0; k < t.items; ++k) {
+            const int64_t i4 = base + ((int64_t)k * blockDim.x + threadIdx.x) * 4;
+            if (i4 + 3 < n) {
+                typedef uint32_t gf_u4 __attribute__((ext_vector_type(4)));
+                const gf_u4 v = *(GF_GLOBAL const gf_u4 *)(keys + i4);
+                const uint32_t kk[4] = {v.x, v.y, v.z, v.w};
+#pragma unroll
+                for (int j = 0; j < 4; ++j) {
+                    const uint32_t b = (kk[j] & mask) - lo;
+                    if (b < span)
+                        atomicAdd(&s_h[b], 1u);
+                }
+            } else {
+                for (int64_t i = i4; i < n && i < i4 + 4; ++i) {
+                    const uint32_t b = (keys[i] & mask) - lo;
+                    if (b < span)
+                        atomicAdd(&s_h[b], 1u);
+                }
+            }
+        }
+    }
+    __syncthreads();
+    GF_GLOBAL uint32_t *row = gptr(rows_) + worker * kHistPart;
+    for (uint32_t i = threadIdx.x; i < span; i += blockDim.x)
+        row[i] = s_h[i];
+}
+
+// Histogram, phase 2: bins[b] += sum over the workers of b's part of their
+// partial rows, in ascending worker order. Bins [b0, b1) by stride.
+__device__ __forceinline__ void hist_merge(uint32_t *bins_, const uint32_t *rows_, uint32_t mask, int64_t G,
+                                           int64_t first, int64_t stride)
+{
     GF_GLOBAL uint32_t *bins = gptr(bins_);
-    const int64_t base = item * chunk_elems(t);
-    for (int k = 0; k < t.items; ++k) {
-        const int64_t i = base + (int64_t)k * blockDim.x + threadIdx.x;
-        if (i < n)
-            __hip_atomic_fetch_add(&bins[keys[i] & mask], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    GF_GLOBAL const uint32_t *rows = gptr(rows_);
+    const int64_t nbins = (int64_t)mask + 1;
+    const int64_t parts = cdiv(nbins, kHistPart);
+    for (int64_t b = first; b < nbins; b += stride) {
+        const int64_t part = b / kHistPart;
+        const int64_t off = b - part * kHistPart;
+        uint32_t sum = 0;
+        for (int64_t w = part; w < G; w += parts)
+            sum += rows[w * kHistPart + off];
+        bins[b] += sum;
     }
 }
 
@@ -497,12 +594,6 @@ __device__ __forceinline__ double region_item(const DStep &st, void *const *op, 
             return 0.0;
         }
         break;
-    case GF_R_HIST:
-        if constexpr ((KMASK >> GF_R_HIST) & 1u) {
-            hist_item((const uint32_t *)op[0], (uint32_t *)op[1], st.mask, n, item, t);
-            return 0.0;
-        }
-        break;
     default:
         break;
     }
@@ -554,8 +645,17 @@ __device__ inline void serial_printf(const RpcRing &rpc, int32_t fmt_id, int32_t
 // order; only workgroup 0 performs side effects (records, RPC, write-back).
 // ---------------------------------------------------------------------------
 
+constexpr unsigned kFamHist = (1u << GF_R_HIST) | (1u << GF_R_OWNER);
+
+template <unsigned KMASK>
+constexpr int family_max_threads()
+{
+    return KMASK == kFamHist ? kMaxWgHist : kMaxWg;
+}
+
 template <unsigned KMASK, int TY>
-__global__ void __launch_bounds__(kMaxWg) k_persistent(DProg prog, DInst inst, Tiling t, Scratch scr, RpcRing rpc)
+__global__ void __launch_bounds__(family_max_threads<KMASK>())
+    k_persistent(DProg prog, DInst inst, Tiling t, Scratch scr, RpcRing rpc)
 {
     __shared__ double s_scal[GF_MAX_SCALARS];
     __shared__ void *s_arr[GF_MAX_ARRAYS];
@@ -602,6 +702,15 @@ __global__ void __launch_bounds__(kMaxWg) k_persistent(DProg prog, DInst inst, T
             if (st.kind == GF_R_OWNER) {
                 owner_region((int32_t *)op[0], n, st.chunk, G * blockDim.x,
                              (int64_t)blockIdx.x * blockDim.x + threadIdx.x);
+            } else if (st.kind == GF_R_HIST) {
+                if constexpr ((KMASK >> GF_R_HIST) & 1u) {
+                    hist_phase1((const uint32_t *)op[0], scr.hist_rows, st.mask, n, worker, G, t);
+                    if (!tree_barrier(genw, tree, blockIdx.x, (uint32_t)G, &s_bar, scr.error,
+                                      scr.barrier_timeout_ticks))
+                        return;
+                    hist_merge((uint32_t *)op[1], scr.hist_rows, st.mask, G, worker * blockDim.x + threadIdx.x,
+                               G * blockDim.x);
+                }
             } else {
                 const int64_t nitems = region_items_dev(st, n, t);
                 for (int64_t it = worker; it < nitems; it += G) {
@@ -671,7 +780,8 @@ __device__ inline void run_glue(const RegionLaunch &rl, const RpcRing &rpc, int3
 }
 
 template <unsigned KMASK, int TY>
-__global__ void __launch_bounds__(kMaxWg) k_region(RegionLaunch rl, Tiling t, Scratch scr, RpcRing rpc)
+__global__ void __launch_bounds__(family_max_threads<KMASK>()) k_region(RegionLaunch rl, Tiling t, Scratch scr,
+                                                                         RpcRing rpc)
 {
     __shared__ double s_red[kLdsRed];
     __shared__ int s_last;
@@ -682,6 +792,12 @@ __global__ void __launch_bounds__(kMaxWg) k_region(RegionLaunch rl, Tiling t, Sc
     if (st.kind == GF_R_OWNER) {
         owner_region((int32_t *)rl.arr[0], rl.n, st.chunk, G * blockDim.x,
                      (int64_t)blockIdx.x * blockDim.x + threadIdx.x);
+    } else if (st.kind == GF_R_HIST) {
+        // phase 1 only; k_hist_merge finishes the region and runs the glue
+        if constexpr ((KMASK >> GF_R_HIST) & 1u)
+            hist_phase1((const uint32_t *)rl.arr[0], scr.hist_rows, st.mask, rl.n,
+                        worker_id(blockIdx.x, G, t.xcd_remap), G, t);
+        return;
     } else if (st.kind < 32) {
         const double coef = (st.kind == GF_R_AXPBY) ? rl.scal[st.sc[1]] * st.c : 0.0;
         const int64_t worker = worker_id(blockIdx.x, G, t.xcd_remap);
@@ -719,6 +835,33 @@ __global__ void __launch_bounds__(kMaxWg) k_region(RegionLaunch rl, Tiling t, Sc
     }
 }
 
+// Histogram phase 2 of the per-region mode: merge the `rows_used` partial
+// rows of phase 1 into the bins; the last workgroup runs the glue.
+__global__ void __launch_bounds__(kMaxWg) k_hist_merge(RegionLaunch rl, int64_t rows_used, Scratch scr, RpcRing rpc)
+{
+    __shared__ int s_last;
+    const int64_t G = gridDim.x;
+    hist_merge((uint32_t *)rl.arr[1], scr.hist_rows, rl.step.mask, rows_used,
+               (int64_t)blockIdx.x * blockDim.x + threadIdx.x, G * blockDim.x);
+    if (rl.n_glue == 0)
+        return;
+    uint32_t *cnt = scr.lines + (int64_t)(kFinalizeLine0 + rl.inst) * kLineWords;
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        const uint32_t a = __hip_atomic_fetch_add(cnt, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
+        s_last = (a == (uint32_t)G - 1);
+    }
+    __syncthreads();
+    if (!s_last)
+        return;
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+    if (threadIdx.x == 0) {
+        run_glue(rl, rpc, scr.error);
+        __hip_atomic_store(cnt, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+}
+
 // ---------------------------------------------------------------------------
 // Kernel selection. Families: the bodies a program uses decide which
 // instantiation runs, so a program only pays the registers of its own bodies.
@@ -726,9 +869,8 @@ __global__ void __launch_bounds__(kMaxWg) k_region(RegionLaunch rl, Tiling t, Sc
 
 constexpr unsigned kFamJ3 = (1u << GF_R_JACOBI3D) | (1u << GF_R_OWNER);
 constexpr unsigned kFamJ2 = (1u << GF_R_JACOBI2D) | (1u << GF_R_OWNER);
-constexpr unsigned kFamVec = (1u << GF_R_SPMV) | (1u << GF_R_DOT) | (1u << GF_R_AXPBY) | (1u << GF_R_HIST) |
-                             (1u << GF_R_OWNER);
-constexpr unsigned kFamAll = kFamJ3 | kFamJ2 | kFamVec;
+constexpr unsigned kFamVec = (1u << GF_R_SPMV) | (1u << GF_R_DOT) | (1u << GF_R_AXPBY) | (1u << GF_R_OWNER);
+constexpr unsigned kFamAll = kFamJ3 | kFamJ2 | kFamVec;  // the histogram runs only in its own family
 
 static unsigned program_kinds(const DProg &p)
 {
@@ -741,6 +883,8 @@ static unsigned program_kinds(const DProg &p)
 
 static unsigned pick_family(unsigned kinds)
 {
+    if ((kinds & ~kFamHist) == 0 && (kinds & (1u << GF_R_HIST)))
+        return kFamHist;
     if ((kinds & ~kFamJ3) == 0)
         return kFamJ3;
     if ((kinds & ~kFamJ2) == 0)
@@ -756,6 +900,8 @@ typedef void (*RegionFn)(RegionLaunch, Tiling, Scratch, RpcRing);
 template <unsigned F>
 static PersistentFn persistent_for_ty(int ty)
 {
+    if constexpr (F == kFamVec || F == kFamHist)
+        return ty >= 1 ? k_persistent<F, 1> : nullptr;
     switch (ty) {
     case 1: return k_persistent<F, 1>;
     case 2: return k_persistent<F, 2>;
@@ -769,6 +915,8 @@ static PersistentFn persistent_for_ty(int ty)
 template <unsigned F>
 static RegionFn region_for_ty(int ty)
 {
+    if constexpr (F == kFamVec || F == kFamHist)
+        return ty >= 1 ? k_region<F, 1> : nullptr;
     switch (ty) {
     case 1: return k_region<F, 1>;
     case 2: return k_region<F, 2>;
@@ -785,6 +933,7 @@ static PersistentFn persistent_fn(unsigned fam, int ty)
     case kFamJ3: return persistent_for_ty<kFamJ3>(ty);
     case kFamJ2: return persistent_for_ty<kFamJ2>(ty);
     case kFamVec: return persistent_for_ty<kFamVec>(1);
+    case kFamHist: return persistent_for_ty<kFamHist>(1);
     default: return persistent_for_ty<kFamAll>(ty);
     }
 }
@@ -794,8 +943,32 @@ static RegionFn region_fn(int kind, int ty)
     switch (kind) {
     case GF_R_JACOBI3D: return region_for_ty<kFamJ3>(ty);
     case GF_R_JACOBI2D: return region_for_ty<kFamJ2>(ty);
+    case GF_R_HIST: return region_for_ty<kFamHist>(1);
     default: return region_for_ty<kFamVec>(1);
     }
+}
+
+bool program_is_hist_family(const DProg &prog) { return pick_family(program_kinds(prog)) == kFamHist; }
+
+bool program_mixes_hist(const DProg &prog)
+{
+    const unsigned k = program_kinds(prog);
+    return (k & (1u << GF_R_HIST)) && (k & ~kFamHist);
+}
+
+int64_t hist_row_words() { return kHistPart; }
+
+int64_t hist_parts(uint32_t mask) { return cdiv((int64_t)mask + 1, kHistPart); }
+
+hipError_t launch_hist_merge(const RegionLaunch &rl, int64_t rows_used, const Scratch &scr, const RpcRing &rpc,
+                             int num_cu, hipStream_t s)
+{
+    const int64_t nbins = (int64_t)rl.step.mask + 1;
+    int64_t g = cdiv(nbins, kMaxWg);
+    if (g > (int64_t)num_cu * 4)
+        g = (int64_t)num_cu * 4;
+    hipLaunchKernelGGL(k_hist_merge, dim3((unsigned)g), dim3(kMaxWg), 0, s, rl, rows_used, scr, rpc);
+    return hipGetLastError();
 }
 
 int persistent_capacity(const DProg &prog, const Tiling &t, int num_cu)

@@ -60,7 +60,11 @@ def cg(iters: int) -> Program:
         Step.make(GF_S_SET, sc=(CG_S_RHO,), c=0.0),
         Step.make(GF_R_DOT, arr=(CG_R, CG_R), sc=(CG_S_RHO,), red_op=GF_OP_SUM, np=0),
     ]
-    body = [
+    return Program.make(pro, list(_cg_body()), iters)
+
+
+def _cg_body():
+    return [
         Step.make(GF_R_SPMV, arr=(CG_ROWPTR, CG_COL, CG_VAL, CG_P, CG_Q), np=0),
         Step.make(GF_S_SET, sc=(CG_S_PQ,), c=0.0),
         Step.make(GF_R_DOT, arr=(CG_P, CG_Q), sc=(CG_S_PQ,), red_op=GF_OP_SUM, np=0),
@@ -74,7 +78,12 @@ def cg(iters: int) -> Program:
         Step.make(GF_R_AXPBY, arr=(CG_P, CG_R, CG_P), sc=(-1, CG_S_BETA), c=1.0, np=0),
         Step.make(GF_S_RECORD, arr=(CG_RHO,), sc=(CG_S_RHO,)),
     ]
-    return Program.make(pro, body, iters)
+
+
+def cg_iterations_only(iters: int) -> Program:
+    """The CG body without its prologue: continues from the state (x, r, p) and
+    the scalar rho already held by the instance."""
+    return Program.make([], list(_cg_body()), iters)
 
 
 def histogram(nbins: int = 65536) -> Program:

@@ -1,0 +1,246 @@
+"""GPU parity of the legacy-loop mix: CG on the 27-point matrix (SpMV, dot and
+axpy each a separate region) and the u32 histogram.
+
+SpMV and axpy are elementwise-exact (same products, same order, no
+contraction); dots are sums whose order differs, held to 1e-12 of the sum of
+|terms| around the oracle's compensated value. CG trajectories are checked by
+lock-step replay: one GPU iteration from a snapshot of the GPU's own state is
+compared region by region with the oracle, the axpys bit-exact given the
+GPU's alpha and beta. Histograms are bit-exact.
+"""
+import math
+
+import numpy as np
+import pytest
+
+import gf_inputs as gi
+from tests.gpu_helpers import dev, host, scalars
+
+pytestmark = pytest.mark.gpu
+
+
+def _mode(gf, name):
+    return {"persistent": gf.GF_EXEC_PERSISTENT, "per_region": gf.GF_EXEC_PER_REGION,
+            "graph": gf.GF_EXEC_PER_REGION_GRAPH}[name]
+
+
+_MATS = {}
+
+
+def _matrix(m):
+    if m not in _MATS:
+        _MATS[m] = gi.poisson27_csr(m)
+    return _MATS[m]
+
+
+def _cg_instance(gf, programs, m, b, x=None, r=None, p=None, rho_hist_len=1):
+    import torch
+    rowptr, col, val = _matrix(m)
+    n = m ** 3
+    t = {programs.CG_ROWPTR: dev(rowptr), programs.CG_COL: dev(col), programs.CG_VAL: dev(val),
+         programs.CG_X: dev(np.zeros(n) if x is None else x), programs.CG_R: dev(b if r is None else r),
+         programs.CG_P: dev(b if p is None else p), programs.CG_Q: torch.zeros(n, dtype=torch.float64, device="cuda"),
+         programs.CG_RHO: torch.zeros(max(1, rho_hist_len), dtype=torch.float64, device="cuda")}
+    sc = scalars()
+    inst = gf.Instance.make(t, sc, ip=(n,))
+    return inst, t, sc
+
+
+@pytest.mark.parametrize("mode", ["persistent", "per_region"])
+@pytest.mark.parametrize("m", [3, 5, 8, 13])
+def test_spmv_region_bit_exact(gfx, oracle_lib, mode, m):
+    import paper_2306_11686_amd as gf
+    print(f"spmv m={m} mode={mode}", flush=True)
+    rowptr, col, val = _matrix(m)
+    n = m ** 3
+    x = gi.cg_rhs(n, seed=7)
+    y = np.zeros(n)
+    prog = gf.Program.make([gf.Step.make(gf.GF_R_SPMV, arr=(0, 1, 2, 3, 4), np=0)], [], 0)
+    ty = dev(y)
+    inst = gf.Instance.make({0: dev(rowptr), 1: dev(col), 2: dev(val), 3: dev(x), 4: ty}, scalars(), ip=(n,))
+    gfx.run(prog, inst, mode=_mode(gf, mode))
+    gfx.sync()
+    assert np.array_equal(host(ty), oracle_lib.spmv(rowptr, col, val, x))
+
+
+def test_spmv_fallback_path_for_dense_rows(gfx, oracle_lib):
+    """Rows too long for the LDS product tile take the one-thread-per-row
+    path; both paths are bit-exact."""
+    import paper_2306_11686_amd as gf
+    rng = np.random.default_rng(5)
+    n = 700
+    lens = np.where(np.arange(n) % 97 == 0, 3000, rng.integers(0, 40, n))
+    rowptr = np.zeros(n + 1, dtype=np.int32)
+    rowptr[1:] = np.cumsum(lens)
+    col = rng.integers(0, n, int(rowptr[-1])).astype(np.int32)
+    val = rng.standard_normal(int(rowptr[-1]))
+    x = rng.standard_normal(n)
+    ty = dev(np.zeros(n))
+    prog = gf.Program.make([gf.Step.make(gf.GF_R_SPMV, arr=(0, 1, 2, 3, 4), np=0)], [], 0)
+    inst = gf.Instance.make({0: dev(rowptr), 1: dev(col), 2: dev(val), 3: dev(x), 4: ty}, scalars(), ip=(n,))
+    for mode in (gf.GF_EXEC_PERSISTENT, gf.GF_EXEC_PER_REGION):
+        gfx.run(prog, inst, mode=mode)
+        gfx.sync()
+        assert np.array_equal(host(ty), oracle_lib.spmv(rowptr, col, val, x))
+
+
+@pytest.mark.parametrize("n", [1, 257, 100003, 2097152])
+@pytest.mark.parametrize("items", [1, 4, 16])
+def test_dot_and_axpby_regions(gfx, oracle_lib, n, items):
+    import paper_2306_11686_amd as gf
+    a = gi.cg_rhs(n, seed=3)
+    b = gi.cg_rhs(n, seed=4)
+    ta, tb, tout = dev(a), dev(b), dev(np.zeros(n))
+    sc = scalars({1: 0.0, 2: 0.8125})
+    prog = gf.Program.make([
+        gf.Step.make(gf.GF_R_DOT, arr=(0, 1), sc=(1,), red_op=gf.GF_OP_SUM, np=0),
+        gf.Step.make(gf.GF_R_AXPBY, arr=(2, 0, 1), sc=(-1, 2), c=-1.0, np=0),
+    ], [], 0)
+    inst = gf.Instance.make({0: ta, 1: tb, 2: tout}, sc, ip=(n,))
+    for mode in (gf.GF_EXEC_PERSISTENT, gf.GF_EXEC_PER_REGION):
+        sc[1] = 0.0
+        gfx.run(prog, inst, mode=mode, launch=gf.Launch.make(items=items))
+        gfx.sync()
+        d, s = oracle_lib.dot_compensated(a, b)
+        assert abs(host(sc)[1] - d) <= 1e-12 * s
+        assert np.array_equal(host(tout), oracle_lib.axpby(a, -0.8125, b))
+
+
+@pytest.mark.parametrize("mode", ["persistent", "per_region", "graph"])
+@pytest.mark.parametrize("m,iters", [(3, 20), (6, 40), (11, 30)])
+def test_cg_small_systems(gfx, oracle_lib, mode, m, iters):
+    """Whole CG runs on small systems: the GPU rho history stays within the
+    envelope set by the oracle's own naive-vs-compensated divergence."""
+    import paper_2306_11686_amd as gf
+    from paper_2306_11686_amd import programs
+    print(f"cg m={m} iters={iters} mode={mode}", flush=True)
+    rowptr, col, val = _matrix(m)
+    n = m ** 3
+    b = gi.cg_rhs(n, seed=1)
+    inst, t, sc = _cg_instance(gf, programs, m, b, rho_hist_len=iters)
+    gfx.run(programs.cg(iters), inst, mode=_mode(gf, mode))
+    gfx.sync()
+    x_n, rh_n, _, _, k_n = oracle_lib.cg(rowptr, col, val, b, iters)
+    x_c, rh_c, _, _, k_c = oracle_lib.cg(rowptr, col, val, b, iters, compensated=True)
+    rh = host(t[programs.CG_RHO])[:k_n]
+    # the envelope: how far two legitimate summation orders drift apart, with
+    # a floor at the rounding level of rho
+    env = np.maximum(np.abs(rh_n - rh_c), 1e-12 * np.abs(rh_c)) * 8 + 1e-13 * abs(rh_c[0])
+    assert np.all(np.abs(rh - rh_c[:len(rh)]) <= env[:len(rh)])
+    xg = host(t[programs.CG_X])
+    scale = max(1.0, float(np.max(np.abs(x_c))))
+    assert np.max(np.abs(xg - x_c)) <= max(8 * np.max(np.abs(x_n - x_c)), 1e-11 * scale)
+
+
+def test_cg_persistent_equals_per_region_bitwise(gfx):
+    import paper_2306_11686_amd as gf
+    from paper_2306_11686_amd import programs
+    m, iters = 9, 25
+    b = gi.cg_rhs(m ** 3, seed=2)
+    outs = []
+    for mode in (gf.GF_EXEC_PERSISTENT, gf.GF_EXEC_PER_REGION):
+        inst, t, sc = _cg_instance(gf, programs, m, b, rho_hist_len=iters)
+        gfx.run(programs.cg(iters), inst, mode=mode)
+        gfx.sync()
+        outs.append((host(t[programs.CG_X]), host(t[programs.CG_RHO])))
+    assert np.array_equal(outs[0][0], outs[1][0]) and np.array_equal(outs[0][1], outs[1][1])
+
+
+@pytest.mark.parametrize("k", [1, 10, 100, 499])
+def test_cg_128_lockstep_replay(gfx, oracle_lib, k):
+    """128^3 (2,097,152 rows, 55,742,968 nonzeros), the benchmark size: run k
+    GPU iterations, snapshot (x, r, p, rho), run one more GPU iteration and
+    replay it on the oracle region by region."""
+    import paper_2306_11686_amd as gf
+    from paper_2306_11686_amd import programs
+    print(f"cg 128 lockstep k={k}", flush=True)
+    m = 128
+    rowptr, col, val = _matrix(m)
+    n = m ** 3
+    assert col.size == 55742968
+    b = gi.cg_rhs(n, seed=1)
+    inst, t, sc = _cg_instance(gf, programs, m, b, rho_hist_len=k + 1)
+    gfx.run(programs.cg(k), inst, mode=gf.GF_EXEC_PERSISTENT)
+    gfx.sync()
+    x0, r0, p0 = host(t[programs.CG_X]), host(t[programs.CG_R]), host(t[programs.CG_P])
+    s0 = host(sc)
+    rho0 = s0[programs.CG_S_RHO]
+    gfx.run(programs.cg_iterations_only(1), inst, mode=gf.GF_EXEC_PERSISTENT)
+    gfx.sync()
+    s1 = host(sc)
+    q = host(t[programs.CG_Q])
+    assert np.array_equal(q, oracle_lib.spmv(rowptr, col, val, p0))
+    pq_ref, pq_abs = oracle_lib.dot_compensated(p0, q)
+    assert abs(s1[programs.CG_S_PQ] - pq_ref) <= 1e-12 * pq_abs
+    alpha = s1[programs.CG_S_ALPHA]
+    assert alpha == rho0 / s1[programs.CG_S_PQ]
+    x1 = host(t[programs.CG_X])
+    r1 = host(t[programs.CG_R])
+    assert np.array_equal(x1, oracle_lib.axpby(x0, alpha, p0))
+    assert np.array_equal(r1, oracle_lib.axpby(r0, -alpha, q))
+    rn_ref, rn_abs = oracle_lib.dot_compensated(r1, r1)
+    assert abs(s1[programs.CG_S_RHO] - rn_ref) <= 1e-12 * rn_abs
+    beta = s1[programs.CG_S_BETA]
+    assert beta == s1[programs.CG_S_RHO] / rho0
+    assert np.array_equal(host(t[programs.CG_P]), oracle_lib.axpby(r1, beta, p0))
+
+
+# ----------------------------------------------------------------------------
+# Histogram
+# ----------------------------------------------------------------------------
+
+def _hist_run(gfx, keys, nbins, mode, launch=None, init=None):
+    import torch
+    import paper_2306_11686_amd as gf
+    from paper_2306_11686_amd import programs
+    tk = dev(keys) if keys.size else torch.zeros(4, dtype=torch.int32, device="cuda")
+    bins = dev(np.zeros(nbins, dtype=np.uint32) if init is None else init)
+    inst = gf.Instance.make({0: tk, 1: bins}, scalars(), ip=(keys.size,))
+    gfx.run(programs.histogram(nbins), inst, mode=mode, launch=launch)
+    gfx.sync()
+    return host(bins)
+
+
+@pytest.mark.parametrize("mode", ["persistent", "per_region", "graph"])
+@pytest.mark.parametrize("n,nbins", [(0, 65536), (1, 65536), (13, 256), (100003, 65536), (1 << 20, 1024),
+                                      ((1 << 20) + 7, 65536), (3 << 18, 1 << 20)])
+def test_hist_uniform_bit_exact(gfx, oracle_lib, mode, n, nbins):
+    import paper_2306_11686_amd as gf
+    print(f"hist n={n} nbins={nbins} mode={mode}", flush=True)
+    keys = gi.hist_keys_uniform(n, seed=2)
+    init = (np.arange(nbins) % 5).astype(np.uint32)
+    got = _hist_run(gfx, keys, nbins, _mode(gf, mode), init=init)
+    ref = oracle_lib.hist_u32(keys, nbins, bins=init.copy())
+    assert np.array_equal(got, ref)
+
+
+@pytest.mark.parametrize("wg,items,nwg", [(64, 1, 2), (256, 2, 6), (1024, 4, 0), (512, 8, 64)])
+def test_hist_launch_configs(gfx, oracle_lib, wg, items, nwg):
+    import paper_2306_11686_amd as gf
+    keys = gi.hist_keys_zipf(300007, seed=3)
+    ref = oracle_lib.hist_u32(keys, 65536)
+    for mode in (gf.GF_EXEC_PERSISTENT, gf.GF_EXEC_PER_REGION):
+        got = _hist_run(gfx, keys, 65536, mode, launch=gf.Launch.make(wg_size=wg, items=items, num_wg=nwg))
+        assert np.array_equal(got, ref)
+
+
+def test_hist_invariants_on_gpu(gfx):
+    import paper_2306_11686_amd as gf
+    n = 1 << 22
+    got = _hist_run(gfx, np.arange(n, dtype=np.uint32), 65536, gf.GF_EXEC_PERSISTENT)
+    assert np.all(got == n // 65536)
+    got = _hist_run(gfx, np.full(n, 0xABCD1234, dtype=np.uint32), 65536, gf.GF_EXEC_PERSISTENT)
+    assert got[0x1234] == n and int(got.sum()) == n
+
+
+@pytest.mark.parametrize("dist", ["uniform", "zipf"])
+def test_hist_full_size_2_28(gfx, oracle_lib, dist):
+    """2^28 keys into 65,536 bins (the benchmark size), bit-exact."""
+    import paper_2306_11686_amd as gf
+    print(f"hist 2^28 {dist}", flush=True)
+    n = 1 << 28
+    keys = gi.hist_keys_uniform(n, seed=1) if dist == "uniform" else gi.hist_keys_zipf(n, seed=1)
+    got = _hist_run(gfx, keys, 65536, gf.GF_EXEC_PERSISTENT)
+    ref = oracle_lib.hist_u32(keys, 65536)
+    assert int(got.sum()) == n
+    assert np.array_equal(got, ref)

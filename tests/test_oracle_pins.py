@@ -45,6 +45,14 @@ def test_grids_depend_only_on_position():
     assert g2[3, 2] == gi.u01(2, 1, np.array([3 * 7 + 2], dtype=np.uint64))[0]
 
 
+def test_compiled_fills_match_numpy_definition():
+    gi.build(force=False)
+    for n in (3, 8, 17):
+        assert np.array_equal(gi.grid3d(n, seed=5), gi.grid3d(n, seed=5, fast=False))
+    assert np.array_equal(gi.hist_keys_uniform(5000, seed=3), gi.hist_keys_uniform(5000, seed=3, fast=False))
+    assert np.array_equal(gi.hist_keys_zipf(5000, seed=3), gi.hist_keys_zipf(5000, seed=3, fast=False))
+
+
 def test_zipf_hottest_bin_mass():
     keys = gi.hist_keys_zipf(1 << 20, seed=1)
     H = np.sum(np.arange(1, 65537, dtype=np.float64) ** -1.1)
