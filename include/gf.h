@@ -252,6 +252,43 @@ int32_t gf_persistent_capacity(gf_ctx *ctx, const gf_program *prog, int32_t wg_s
 gf_status gf_copy(gf_ctx *ctx, void *d_dst, const void *d_src, int64_t nbytes, int32_t num_wg,
                   void *hip_stream);
 
+/* ---- autotuner -----------------------------------------------------------
+ * The paper fixes team counts by hand and notes that matching them to the
+ * loop matters (Section 5.3, "Parallel Region Modeling"); libgf instead
+ * times a fixed list of GF_NUM_CANDIDATES launch shapes on the real run.
+ * Candidate c (0..31) is decoded per kernel family of the program, with
+ * a = c & 3, b = (c >> 2) & 3, h = c >> 4:
+ *   3D stencil : tile_y = {1,2,4,8}[a], tile_z = ceil((n-2)/{2,3,4,6}[b]),
+ *                xcd_remap = 1 - h
+ *   2D stencil : tile_y = {1,2,4,8}[a], wg_size = {64,128,192,256}[b],
+ *                xcd_remap = 1 - h
+ *   streaming (SpMV, dot, axpby): wg_size = {64,128,192,256}[a],
+ *                items = {1,2,4,8}[b], num_wg = h ? 4 * CUs : default
+ *   histogram  : wg_size = {256,512,768,1024}[a], items = {1,2,4,8}[b],
+ *                num_wg = (h + 1) * CUs
+ * (n is the size of the program's first stencil region in `inst`). */
+#define GF_NUM_CANDIDATES 32
+
+/* Write the GF_NUM_CANDIDATES decoded launches for prog/inst into out.
+ * Returns GF_NUM_CANDIDATES or a negative gf_status. */
+int32_t gf_tune_candidates(gf_ctx *ctx, const gf_program *prog, const gf_instance *inst, gf_launch *out);
+
+/* Time candidate launches by running the program for real on n_inst
+ * instances in `mode` on hip_stream: one warm-up run, then `reps` runs timed
+ * with HIP events; ms_out[i] receives the median (+infinity if candidate i
+ * cannot run). The runs' side effects on the instances' data happen
+ * (reps + 1) times per candidate. Blocks until done. candidates NULL uses
+ * the built-in list (n_cand = GF_NUM_CANDIDATES). *best_index receives the
+ * fastest candidate (gf_tune_pick). Returns the number of candidates that
+ * ran, or a negative gf_status. */
+int32_t gf_tune(gf_ctx *ctx, const gf_program *prog, const gf_instance *inst, int32_t n_inst, int32_t mode,
+                const gf_launch *candidates, int32_t n_cand, int32_t reps, float *ms_out, int32_t *best_index,
+                void *hip_stream);
+
+/* Index of the smallest finite ms[i] (ties: lowest index), or -1 if none is
+ * finite. Pure host function. */
+int32_t gf_tune_pick(const float *ms, int32_t n);
+
 #ifdef __cplusplus
 }
 #endif

@@ -134,7 +134,15 @@ _SIGS = {
     "gf_persistent_capacity": (ctypes.c_int32, [ctypes.c_void_p, ctypes.POINTER(Program), ctypes.c_int32]),
     "gf_copy": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64, ctypes.c_int32,
                                ctypes.c_void_p]),
+    "gf_tune_candidates": (ctypes.c_int32, [ctypes.c_void_p, ctypes.POINTER(Program), ctypes.POINTER(Instance),
+                                            ctypes.POINTER(Launch)]),
+    "gf_tune": (ctypes.c_int32, [ctypes.c_void_p, ctypes.POINTER(Program), ctypes.POINTER(Instance), ctypes.c_int32,
+                                 ctypes.c_int32, ctypes.POINTER(Launch), ctypes.c_int32, ctypes.c_int32,
+                                 ctypes.POINTER(ctypes.c_float), ctypes.POINTER(ctypes.c_int32), ctypes.c_void_p]),
+    "gf_tune_pick": (ctypes.c_int32, [ctypes.POINTER(ctypes.c_float), ctypes.c_int32]),
 }
+
+GF_NUM_CANDIDATES = 32
 
 
 def lib_path() -> str:
@@ -160,6 +168,13 @@ def load_library():
 
 def exported_symbols():
     return sorted(_SIGS)
+
+
+def tune_pick(ms) -> int:
+    """Host-only argmin over finite timings (the library's gf_tune_pick)."""
+    lib = load_library()
+    arr = (ctypes.c_float * len(ms))(*ms)
+    return lib.gf_tune_pick(arr, len(ms))
 
 
 def _stream_handle(stream):
@@ -244,6 +259,25 @@ class Context:
 
     def capacity(self, program: Program, wg_size: int = 0) -> int:
         return self.lib.gf_persistent_capacity(self.h, ctypes.byref(program), wg_size)
+
+    def tune_candidates(self, program: Program, instance: Instance):
+        out = (Launch * GF_NUM_CANDIDATES)()
+        self._check(self.lib.gf_tune_candidates(self.h, ctypes.byref(program), ctypes.byref(instance), out))
+        return list(out)
+
+    def tune(self, program: Program, instances, mode: int = GF_EXEC_PERSISTENT, candidates=None, reps: int = 3,
+             stream=None):
+        """Time candidate launches on real runs; returns (ms list, best index)."""
+        if isinstance(instances, Instance):
+            instances = [instances]
+        arr = (Instance * len(instances))(*instances)
+        n = len(candidates) if candidates is not None else GF_NUM_CANDIDATES
+        cand = (Launch * n)(*candidates) if candidates is not None else None
+        ms = (ctypes.c_float * n)()
+        best = ctypes.c_int32(-1)
+        self._check(self.lib.gf_tune(self.h, ctypes.byref(program), arr, len(instances), mode, cand, n, reps, ms,
+                                     ctypes.byref(best), _stream_handle(stream)))
+        return [float(v) for v in ms], best.value
 
     def copy(self, dst, src, nbytes: int, num_wg: int = 0, stream=None):
         self._check(self.lib.gf_copy(self.h, _ptr(dst), _ptr(src), nbytes, num_wg, _stream_handle(stream)))

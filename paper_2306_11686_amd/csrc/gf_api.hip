@@ -6,6 +6,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <cmath>
 #include <atomic>
 #include <chrono>
 #include <cstdarg>
@@ -238,7 +239,7 @@ gf_status gf_ctx_create(int32_t hip_device, const gf_ctx_opts *opts, gf_ctx **ou
     const int64_t cap = 1 << 20;
     const size_t part_bytes = 2 * cap * sizeof(double);
     const size_t line_bytes = (size_t)kNumLines * 128;
-    const size_t hist_bytes = (size_t)kHistRowsMax * 32768 * sizeof(uint32_t);
+    const size_t hist_bytes = (size_t)kHistRowsMax * 65536 * sizeof(uint32_t);
     const size_t total = part_bytes + line_bytes + 256 + hist_bytes;
     char *base = nullptr;
     if ((e = hipMalloc((void **)&base, total)) != hipSuccess) {
@@ -812,7 +813,10 @@ gf_status gf_region_run(gf_ctx *ctx, const gf_program *prog, const gf_instance *
         if (cap <= 0)
             return fail(ctx, GF_EHIP, "occupancy query failed");
         for (int i = 0; i < n_inst; ++i) {
-            int grid = (int)std::min<int64_t>(cap, max_items(p, inst[i], t));
+            // default grid: one workgroup per work item, at most two per CU
+            // (the grid barrier's cost grows with the number of members)
+            int grid = (int)std::min<int64_t>(std::min<int64_t>(cap, 2 * (int64_t)ctx->num_cu),
+                                              max_items(p, inst[i], t));
             if (launch && launch->num_wg > 0) {
                 if (launch->num_wg > cap)
                     return fail(ctx, GF_EINVAL, "num_wg %d exceeds the co-resident capacity %d", launch->num_wg, cap);
@@ -958,6 +962,138 @@ gf_status gf_sync(gf_ctx *ctx, void *hip_stream, gf_run_stats *stats)
         return fail(ctx, GF_EDEVICE, "device error code %d", code);
     }
     return GF_OK;
+}
+
+}  // extern "C"
+
+// ---------------------------------------------------------------------------
+// Autotuner
+// ---------------------------------------------------------------------------
+
+namespace {
+
+int64_t first_stencil_size(const DProg &p, const gf_instance &in)
+{
+    for (int i = 0; i < p.n_steps; ++i)
+        if (p.steps[i].kind == GF_R_JACOBI3D || p.steps[i].kind == GF_R_JACOBI2D)
+            return in.ip[p.steps[i].np];
+    return 0;
+}
+
+gf_launch decode_candidate(const DProg &p, const gf_instance &in, int c, int num_cu)
+{
+    gf_launch l;
+    std::memset(&l, 0, sizeof l);
+    const int a = c & 3, b = (c >> 2) & 3, h = (c >> 4) & 1;
+    const unsigned m = program_region_mask(p);
+    static const int ty[4] = {1, 2, 4, 8};
+    static const int zs[4] = {2, 3, 4, 6};
+    static const int wg[4] = {64, 128, 192, 256};
+    static const int hw[4] = {256, 512, 768, 1024};
+    static const int it[4] = {1, 2, 4, 8};
+    if (m & (1u << GF_R_HIST)) {
+        l.wg_size = hw[a];
+        l.items = it[b];
+        l.num_wg = (h + 1) * num_cu;
+        l.xcd_remap = 1;
+    } else if (m & (1u << GF_R_JACOBI3D)) {
+        const int64_t n = first_stencil_size(p, in);
+        const int64_t interior = n > 2 ? n - 2 : 1;
+        l.tile_y = ty[a];
+        l.tile_z = (int32_t)std::max<int64_t>(1, (interior + zs[b] - 1) / zs[b]);
+        l.xcd_remap = 1 - h;
+    } else if (m & (1u << GF_R_JACOBI2D)) {
+        l.tile_y = ty[a];
+        l.wg_size = wg[b];
+        l.xcd_remap = 1 - h;
+    } else {
+        l.wg_size = wg[a];
+        l.items = it[b];
+        l.num_wg = h ? 4 * num_cu : 0;
+        l.xcd_remap = 1;
+    }
+    return l;
+}
+
+}  // namespace
+
+extern "C" {
+
+int32_t gf_tune_pick(const float *ms, int32_t n)
+{
+    if (!ms || n <= 0)
+        return -1;
+    int32_t best = -1;
+    for (int32_t i = 0; i < n; ++i)
+        if (std::isfinite(ms[i]) && (best < 0 || ms[i] < ms[best]))
+            best = i;
+    return best;
+}
+
+int32_t gf_tune_candidates(gf_ctx *ctx, const gf_program *prog, const gf_instance *inst, gf_launch *out)
+{
+    if (!ctx || !inst || !out)
+        return GF_EINVAL;
+    DProg p;
+    gf_status st = build_program(ctx, prog, &p);
+    if (st != GF_OK)
+        return st;
+    for (int c = 0; c < GF_NUM_CANDIDATES; ++c)
+        out[c] = decode_candidate(p, *inst, c, ctx->num_cu);
+    return GF_NUM_CANDIDATES;
+}
+
+int32_t gf_tune(gf_ctx *ctx, const gf_program *prog, const gf_instance *inst, int32_t n_inst, int32_t mode,
+                const gf_launch *candidates, int32_t n_cand, int32_t reps, float *ms_out, int32_t *best_index,
+                void *hip_stream)
+{
+    if (!ctx || !inst || n_inst < 1 || !ms_out || reps < 1)
+        return GF_EINVAL;
+    std::vector<gf_launch> cands;
+    if (candidates) {
+        if (n_cand < 1)
+            return fail(ctx, GF_EINVAL, "no candidates");
+        cands.assign(candidates, candidates + n_cand);
+    } else {
+        cands.resize(GF_NUM_CANDIDATES);
+        int32_t k = gf_tune_candidates(ctx, prog, inst, cands.data());
+        if (k < 0)
+            return k;
+    }
+    hipSetDevice(ctx->device);
+    hipStream_t s = (hipStream_t)hip_stream;
+    hipEvent_t e0, e1;
+    if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess)
+        return fail(ctx, GF_EHIP, "event create");
+    int32_t ran = 0;
+    std::vector<float> t(reps);
+    for (size_t i = 0; i < cands.size(); ++i) {
+        ms_out[i] = INFINITY;
+        if (gf_region_run(ctx, prog, inst, n_inst, mode, &cands[i], nullptr, hip_stream) != GF_OK)
+            continue;
+        bool ok = true;
+        for (int r = 0; r < reps && ok; ++r) {
+            hipEventRecord(e0, s);
+            ok = gf_region_run(ctx, prog, inst, n_inst, mode, &cands[i], nullptr, hip_stream) == GF_OK;
+            hipEventRecord(e1, s);
+            if (hipEventSynchronize(e1) != hipSuccess)
+                ok = false;
+            float ms = 0.0f;
+            hipEventElapsedTime(&ms, e0, e1);
+            t[r] = ms;
+        }
+        if (gf_sync(ctx, hip_stream, nullptr) != GF_OK || !ok)
+            continue;
+        std::sort(t.begin(), t.end());
+        ms_out[i] = t[reps / 2];
+        ++ran;
+    }
+    hipEventDestroy(e0);
+    hipEventDestroy(e1);
+    if (best_index)
+        *best_index = gf_tune_pick(ms_out, (int32_t)cands.size());
+    ctx->err.clear();
+    return ran;
 }
 
 }  // extern "C"

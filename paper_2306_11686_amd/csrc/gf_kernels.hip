@@ -9,7 +9,7 @@ namespace gf {
 constexpr int kMaxWg = 256;         // workgroup size limit of the region kernels
 constexpr int kMaxWgHist = 1024;    // histogram kernels (one 128 KiB workgroup per CU)
 constexpr int kLdsRed = kMaxWgHist / kWave;
-constexpr int kHistPart = 32768;    // bins counted per workgroup pass (128 KiB of u32 in LDS)
+constexpr int kHistPart = 65536;    // bins counted per workgroup pass (16-bit counters, 128 KiB of LDS)
 
 // ---------------------------------------------------------------------------
 // Work decomposition shared by host and device.
@@ -52,6 +52,10 @@ __host__ __device__ inline StencilGeom j2_geom(int64_t n, const Tiling &t)
 
 __host__ __device__ inline int64_t chunk_elems(const Tiling &t) { return (int64_t)t.wg_size * t.items; }
 
+// SpMV rows per work item: half the workgroup, so a block of a stencil-like
+// matrix (<= 32 nonzeros per row) fits the 4096-product LDS tile.
+__host__ __device__ inline int64_t spmv_rows(const Tiling &t) { return t.wg_size / 2; }
+
 // Histogram work: chunks of wg_size * items * 4 keys (each thread reads
 // `items` 16-byte groups of four keys); every chunk is counted once per part
 // of kHistPart bins, and item = chunk * parts + part.
@@ -82,7 +86,7 @@ int64_t region_items(const DStep &st, int64_t n, const Tiling &t)
         return g.nxc * g.nyt;
     }
     case GF_R_SPMV:
-        return cdiv(n, t.wg_size);
+        return cdiv(n, spmv_rows(t));
     case GF_R_DOT:
     case GF_R_AXPBY:
         return cdiv(n, chunk_elems(t));
@@ -107,7 +111,7 @@ __device__ inline int64_t region_items_dev(const DStep &st, int64_t n, const Til
         return g.nxc * g.nyt;
     }
     case GF_R_SPMV:
-        return cdiv(n, t.wg_size);
+        return cdiv(n, spmv_rows(t));
     case GF_R_DOT:
     case GF_R_AXPBY:
         return cdiv(n, chunk_elems(t));
@@ -405,16 +409,17 @@ __device__ __forceinline__ double j2_item(const double *u_, double *w_, int64_t 
     return acc;
 }
 
-// CSR SpMV over a block of blockDim rows (CSR-stream): the block's products
+// CSR SpMV over a block of wg_size/2 rows (CSR-stream): the block's products
 // val[k] * x[col[k]] are formed by a coalesced pass over its nonzeros into
-// LDS, then each thread sums its own row serially in stored column order,
-// exactly as the legacy loop does (same products, same order, no
-// contraction). Blocks with more nonzeros than the LDS tile fall back to one
-// thread per row reading global memory.
+// LDS (eight gathers in flight per thread), then each of the first R threads
+// sums its own row serially in stored column order, exactly as the legacy
+// loop does (same products, same order, no contraction). Blocks with more
+// nonzeros than the LDS tile fall back to one thread per row.
 constexpr int kSpmvLds = 4096;  // doubles (32 KiB)
+constexpr int kSpmvUnroll = 8;
 
 __device__ __forceinline__ void spmv_item(const int32_t *rowptr_, const int32_t *col_, const double *val_,
-                                          const double *x_, double *y_, int64_t n, int64_t item)
+                                          const double *x_, double *y_, int64_t n, int64_t item, int64_t R)
 {
     __shared__ double s_prod[kSpmvLds];
     GF_GLOBAL const int32_t *__restrict__ rowptr = gptr(rowptr_);
@@ -422,16 +427,33 @@ __device__ __forceinline__ void spmv_item(const int32_t *rowptr_, const int32_t 
     GF_GLOBAL const double *__restrict__ val = gptr(val_);
     GF_GLOBAL const double *__restrict__ x = gptr(x_);
     GF_GLOBAL double *__restrict__ y = gptr(y_);
-    const int64_t r0 = item * blockDim.x;
-    const int64_t r1 = r0 + blockDim.x < n ? r0 + blockDim.x : n;
+    const int64_t r0 = item * R;
+    const int64_t r1 = r0 + R < n ? r0 + R : n;
     const int64_t row = r0 + threadIdx.x;
+    const bool mine = threadIdx.x < R && row < r1;
     const int32_t k0 = rowptr[r0];
-    const int32_t k1 = rowptr[r1];
-    if (k1 - k0 <= kSpmvLds) {
-        for (int32_t k = k0 + (int32_t)threadIdx.x; k < k1; k += (int32_t)blockDim.x)
-            s_prod[k - k0] = val[k] * x[col[k]];
+    const int32_t nnz = rowptr[r1] - k0;
+    if (nnz <= kSpmvLds) {
+        const int32_t B = (int32_t)blockDim.x;
+        for (int32_t base = (int32_t)threadIdx.x; base < nnz; base += kSpmvUnroll * B) {
+            int32_t c[kSpmvUnroll];
+            double v[kSpmvUnroll], xv[kSpmvUnroll];
+#pragma unroll
+            for (int j = 0; j < kSpmvUnroll; ++j) {
+                const int32_t kk = base + j * B;
+                c[j] = kk < nnz ? col[k0 + kk] : 0;
+                v[j] = kk < nnz ? val[k0 + kk] : 0.0;
+            }
+#pragma unroll
+            for (int j = 0; j < kSpmvUnroll; ++j)
+                xv[j] = base + j * B < nnz ? x[c[j]] : 0.0;
+#pragma unroll
+            for (int j = 0; j < kSpmvUnroll; ++j)
+                if (base + j * B < nnz)
+                    s_prod[base + j * B] = v[j] * xv[j];
+        }
         __syncthreads();
-        if (row < n) {
+        if (mine) {
             const int32_t b = rowptr[row] - k0, e = rowptr[row + 1] - k0;
             double acc = 0.0;
             for (int32_t k = b; k < e; ++k)
@@ -439,7 +461,7 @@ __device__ __forceinline__ void spmv_item(const int32_t *rowptr_, const int32_t 
             y[row] = acc;
         }
         __syncthreads();
-    } else if (row < n) {
+    } else if (mine) {
         double acc = 0.0;
         const int32_t e = rowptr[row + 1];
         for (int32_t k = rowptr[row]; k < e; ++k)
@@ -479,19 +501,38 @@ __device__ __forceinline__ void axpby_item(double *out_, const double *x_, doubl
 
 // Histogram, phase 1: this worker counts the keys of its chunks whose bin
 // falls in its part (all of a worker's items share one part because the
-// worker stride is a multiple of the part count) into 32-bit LDS counters,
-// then writes them as its partial row. Integer counts are exact in any order.
-__device__ __forceinline__ void hist_phase1(const uint32_t *keys_, uint32_t *rows_, uint32_t mask, int64_t n,
-                                            int64_t worker, int64_t G, const Tiling &t)
+// worker stride is a multiple of the part count) into 16-bit counters packed
+// two per 32-bit LDS word, then writes them as its partial row. A counter
+// that reaches 0x8000 hands 0x8000 to the global bin and drops back: its
+// half never exceeds 0x8000 plus the increments in flight, so no carry
+// crosses into the neighbouring counter and the escape needs no lock.
+// Integer counts are exact in any order.
+__device__ __forceinline__ void hist_count(uint32_t *s_h, GF_GLOBAL uint32_t *bins, uint32_t key, uint32_t mask,
+                                           uint32_t lo, uint32_t span)
 {
-    __shared__ uint32_t s_h[kHistPart];
+    const uint32_t b = (key & mask) - lo;
+    if (b < span) {
+        const uint32_t sh = (b & 1u) * 16u;
+        const uint32_t old = atomicAdd(&s_h[b >> 1], 1u << sh);
+        if (((old >> sh) & 0xFFFFu) == 0x7FFFu) {
+            atomicSub(&s_h[b >> 1], 0x8000u << sh);
+            __hip_atomic_fetch_add(&bins[lo + b], 0x8000u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        }
+    }
+}
+
+__device__ __forceinline__ void hist_phase1(const uint32_t *keys_, uint32_t *bins_, uint32_t *rows_, uint32_t mask,
+                                            int64_t n, int64_t worker, int64_t G, const Tiling &t)
+{
+    __shared__ uint32_t s_h[kHistPart / 2];
     GF_GLOBAL const uint32_t *__restrict__ keys = gptr(keys_);
+    GF_GLOBAL uint32_t *bins = gptr(bins_);
     const HistGeom g = hist_geom(n, mask, t);
     const int64_t part = worker % g.parts;
     const uint32_t lo = (uint32_t)(part * kHistPart);
     const int64_t span64 = g.nbins - (int64_t)lo < kHistPart ? g.nbins - (int64_t)lo : kHistPart;
     const uint32_t span = (uint32_t)span64;
-    for (int i = threadIdx.x; i < kHistPart; i += blockDim.x)
+    for (int i = threadIdx.x; i < kHistPart / 2; i += blockDim.x)
         s_h[i] = 0u;
     __syncthreads();
     for (int64_t it = worker; it < g.nitems; it += G) {
@@ -501,26 +542,20 @@ __device__ __forceinline__ void hist_phase1(const uint32_t *keys_, uint32_t *row
             if (i4 + 3 < n) {
                 typedef uint32_t gf_u4 __attribute__((ext_vector_type(4)));
                 const gf_u4 v = *(GF_GLOBAL const gf_u4 *)(keys + i4);
-                const uint32_t kk[4] = {v.x, v.y, v.z, v.w};
-#pragma unroll
-                for (int j = 0; j < 4; ++j) {
-                    const uint32_t b = (kk[j] & mask) - lo;
-                    if (b < span)
-                        atomicAdd(&s_h[b], 1u);
-                }
+                hist_count(s_h, bins, v.x, mask, lo, span);
+                hist_count(s_h, bins, v.y, mask, lo, span);
+                hist_count(s_h, bins, v.z, mask, lo, span);
+                hist_count(s_h, bins, v.w, mask, lo, span);
             } else {
-                for (int64_t i = i4; i < n && i < i4 + 4; ++i) {
-                    const uint32_t b = (keys[i] & mask) - lo;
-                    if (b < span)
-                        atomicAdd(&s_h[b], 1u);
-                }
+                for (int64_t i = i4; i < n && i < i4 + 4; ++i)
+                    hist_count(s_h, bins, keys[i], mask, lo, span);
             }
         }
     }
     __syncthreads();
     GF_GLOBAL uint32_t *row = gptr(rows_) + worker * kHistPart;
     for (uint32_t i = threadIdx.x; i < span; i += blockDim.x)
-        row[i] = s_h[i];
+        row[i] = (s_h[i >> 1] >> ((i & 1u) * 16u)) & 0xFFFFu;
 }
 
 // Histogram, phase 2: bins[b] += sum over the workers of b's part of their
@@ -580,7 +615,7 @@ __device__ __forceinline__ double region_item(const DStep &st, void *const *op, 
     case GF_R_SPMV:
         if constexpr ((KMASK >> GF_R_SPMV) & 1u) {
             spmv_item((const int32_t *)op[0], (const int32_t *)op[1], (const double *)op[2], (const double *)op[3],
-                      (double *)op[4], n, item);
+                      (double *)op[4], n, item, spmv_rows(t));
             return 0.0;
         }
         break;
@@ -704,7 +739,7 @@ __global__ void __launch_bounds__(family_max_threads<KMASK>())
                              (int64_t)blockIdx.x * blockDim.x + threadIdx.x);
             } else if (st.kind == GF_R_HIST) {
                 if constexpr ((KMASK >> GF_R_HIST) & 1u) {
-                    hist_phase1((const uint32_t *)op[0], scr.hist_rows, st.mask, n, worker, G, t);
+                    hist_phase1((const uint32_t *)op[0], (uint32_t *)op[1], scr.hist_rows, st.mask, n, worker, G, t);
                     if (!tree_barrier(genw, tree, blockIdx.x, (uint32_t)G, &s_bar, scr.error,
                                       scr.barrier_timeout_ticks))
                         return;
@@ -795,7 +830,7 @@ __global__ void __launch_bounds__(family_max_threads<KMASK>()) k_region(RegionLa
     } else if (st.kind == GF_R_HIST) {
         // phase 1 only; k_hist_merge finishes the region and runs the glue
         if constexpr ((KMASK >> GF_R_HIST) & 1u)
-            hist_phase1((const uint32_t *)rl.arr[0], scr.hist_rows, st.mask, rl.n,
+            hist_phase1((const uint32_t *)rl.arr[0], (uint32_t *)rl.arr[1], scr.hist_rows, st.mask, rl.n,
                         worker_id(blockIdx.x, G, t.xcd_remap), G, t);
         return;
     } else if (st.kind < 32) {
