@@ -289,6 +289,61 @@ int32_t gf_tune(gf_ctx *ctx, const gf_program *prog, const gf_instance *inst, in
  * finite. Pure host function. */
 int32_t gf_tune_pick(const float *ms, int32_t n);
 
+/* ---- learned launch-config predictor --------------------------------------
+ * Not in the paper (its team counts are chosen by hand): a small FP32 MLP
+ * maps 8 loop features to a predicted log(t_c / t_best) for each of the
+ * GF_NUM_CANDIDATES launch shapes; the argmin over valid shapes is used, and
+ * inputs outside the training distribution defer to the autotuner.
+ * Features (raw, before the log2(1+x) transform and standardisation): trip
+ * count, algorithmic bytes per iteration, flops per iteration, stencil
+ * radius, reduction count, nonzeros per row, instance count, element size.
+ * Parameters are one float array of GF_MLP_NPARAMS values laid out as
+ * W1[64][8] b1[64] W2[64][64] b2[64] W3[32][64] b3[32] (row-major). */
+#define GF_MLP_IN 8
+#define GF_MLP_HIDDEN 64
+#define GF_MLP_OUT GF_NUM_CANDIDATES
+#define GF_MLP_NPARAMS (64 * 8 + 64 + 64 * 64 + 64 + 32 * 64 + 32)
+
+/* Forward pass on the device: d_y[b][32] for b < batch; d_z1/d_z2 (nullable,
+ * batch x 64) receive the pre-activations the backward pass needs. */
+gf_status gf_mlp_forward(gf_ctx *ctx, const float *d_params, const float *d_feats, int32_t batch, float *d_y,
+                         float *d_z1, float *d_z2, void *hip_stream);
+
+/* Gradients of L = inv_norm * sum over b,c of mask[b][c] (y - target)^2 into
+ * d_grads (GF_MLP_NPARAMS floats, overwritten); relu'(0) = 0. Deterministic
+ * (per-block partials summed in block order). batch <= 65536. */
+gf_status gf_mlp_backward(gf_ctx *ctx, const float *d_params, const float *d_feats, const float *d_z1,
+                          const float *d_z2, const float *d_y, const float *d_target, const float *d_mask,
+                          int32_t batch, float inv_norm, float *d_grads, void *hip_stream);
+
+/* d_loss[0] = inv_norm * sum mask * (y - target)^2 over count entries. */
+gf_status gf_mlp_loss(gf_ctx *ctx, const float *d_y, const float *d_target, const float *d_mask, int64_t count,
+                      float inv_norm, float *d_loss, void *hip_stream);
+
+/* One Adam update (t >= 1 is the step number for bias correction). */
+gf_status gf_adam_step(gf_ctx *ctx, float *d_params, const float *d_grads, float *d_m, float *d_v, int32_t n,
+                       float lr, float beta1, float beta2, float eps, int32_t t, void *hip_stream);
+
+/* Full-batch training on the device: `epochs` steps of forward, loss,
+ * backward and Adam (beta1 0.9, beta2 0.999, eps 1e-8) starting from
+ * d_params (updated in place; d_m, d_v Adam moments, zero them to start);
+ * d_loss_hist[e] receives the loss before step e. inv_norm = 1 / sum(mask). */
+gf_status gf_train_predictor(gf_ctx *ctx, float *d_params, float *d_m, float *d_v, const float *d_feats,
+                             const float *d_target, const float *d_mask, int32_t batch, float inv_norm,
+                             int32_t epochs, float lr, float *d_loss_hist, void *hip_stream);
+
+/* Install a trained predictor for launch-time use: host copies of the
+ * parameters and the per-feature mean and standard deviation of the
+ * transformed training features. */
+gf_status gf_predictor_set(gf_ctx *ctx, const float *h_params, const float *h_mean, const float *h_std);
+
+/* Predict the launch shape for raw features (host FP32 forward). valid
+ * (nullable, GF_NUM_CANDIDATES bytes) restricts the argmin; scores
+ * (nullable) receives the 32 outputs. Returns the candidate index, -1 if no
+ * predictor is installed or any standardised feature lies outside [-4, 4]
+ * (the caller then tunes). */
+int32_t gf_predict(gf_ctx *ctx, const double *h_features, const uint8_t *valid, float *scores);
+
 #ifdef __cplusplus
 }
 #endif

@@ -140,7 +140,28 @@ _SIGS = {
                                  ctypes.c_int32, ctypes.POINTER(Launch), ctypes.c_int32, ctypes.c_int32,
                                  ctypes.POINTER(ctypes.c_float), ctypes.POINTER(ctypes.c_int32), ctypes.c_void_p]),
     "gf_tune_pick": (ctypes.c_int32, [ctypes.POINTER(ctypes.c_float), ctypes.c_int32]),
+    "gf_mlp_forward": (ctypes.c_int, [ctypes.c_void_p] + [ctypes.c_void_p] * 2 + [ctypes.c_int32] +
+                       [ctypes.c_void_p] * 4),
+    "gf_mlp_backward": (ctypes.c_int, [ctypes.c_void_p] + [ctypes.c_void_p] * 7 + [ctypes.c_int32, ctypes.c_float,
+                                                                                    ctypes.c_void_p, ctypes.c_void_p]),
+    "gf_mlp_loss": (ctypes.c_int, [ctypes.c_void_p] + [ctypes.c_void_p] * 3 + [ctypes.c_int64, ctypes.c_float,
+                                                                                ctypes.c_void_p, ctypes.c_void_p]),
+    "gf_adam_step": (ctypes.c_int, [ctypes.c_void_p] + [ctypes.c_void_p] * 4 + [ctypes.c_int32, ctypes.c_float,
+                                                                                 ctypes.c_float, ctypes.c_float,
+                                                                                 ctypes.c_float, ctypes.c_int32,
+                                                                                 ctypes.c_void_p]),
+    "gf_train_predictor": (ctypes.c_int, [ctypes.c_void_p] + [ctypes.c_void_p] * 6 + [ctypes.c_int32, ctypes.c_float,
+                                                                                      ctypes.c_int32, ctypes.c_float,
+                                                                                      ctypes.c_void_p,
+                                                                                      ctypes.c_void_p]),
+    "gf_predictor_set": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_float),
+                                        ctypes.POINTER(ctypes.c_float), ctypes.POINTER(ctypes.c_float)]),
+    "gf_predict": (ctypes.c_int32, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_uint8),
+                                    ctypes.POINTER(ctypes.c_float)]),
 }
+
+GF_MLP_IN, GF_MLP_HIDDEN, GF_MLP_OUT = 8, 64, 32
+GF_MLP_NPARAMS = 64 * 8 + 64 + 64 * 64 + 64 + 32 * 64 + 32
 
 GF_NUM_CANDIDATES = 32
 
@@ -278,6 +299,45 @@ class Context:
         self._check(self.lib.gf_tune(self.h, ctypes.byref(program), arr, len(instances), mode, cand, n, reps, ms,
                                      ctypes.byref(best), _stream_handle(stream)))
         return [float(v) for v in ms], best.value
+
+    # -- launch-config predictor ------------------------------------------
+    def mlp_forward(self, params, feats, batch, y, z1=None, z2=None, stream=None):
+        self._check(self.lib.gf_mlp_forward(self.h, _ptr(params), _ptr(feats), batch, _ptr(y), _ptr(z1), _ptr(z2),
+                                            _stream_handle(stream)))
+
+    def mlp_backward(self, params, feats, z1, z2, y, target, mask, batch, inv_norm, grads, stream=None):
+        self._check(self.lib.gf_mlp_backward(self.h, _ptr(params), _ptr(feats), _ptr(z1), _ptr(z2), _ptr(y),
+                                             _ptr(target), _ptr(mask), batch, inv_norm, _ptr(grads),
+                                             _stream_handle(stream)))
+
+    def mlp_loss(self, y, target, mask, count, inv_norm, loss, stream=None):
+        self._check(self.lib.gf_mlp_loss(self.h, _ptr(y), _ptr(target), _ptr(mask), count, inv_norm, _ptr(loss),
+                                         _stream_handle(stream)))
+
+    def adam_step(self, params, grads, m, v, n, lr, beta1, beta2, eps, t, stream=None):
+        self._check(self.lib.gf_adam_step(self.h, _ptr(params), _ptr(grads), _ptr(m), _ptr(v), n, lr, beta1, beta2,
+                                          eps, t, _stream_handle(stream)))
+
+    def train_predictor(self, params, m, v, feats, target, mask, batch, inv_norm, epochs, lr, loss_hist=None,
+                        stream=None):
+        self._check(self.lib.gf_train_predictor(self.h, _ptr(params), _ptr(m), _ptr(v), _ptr(feats), _ptr(target),
+                                                _ptr(mask), batch, inv_norm, epochs, lr, _ptr(loss_hist),
+                                                _stream_handle(stream)))
+
+    def predictor_set(self, params, mean, std):
+        P = (ctypes.c_float * GF_MLP_NPARAMS)(*[float(v) for v in params])
+        M = (ctypes.c_float * GF_MLP_IN)(*[float(v) for v in mean])
+        S = (ctypes.c_float * GF_MLP_IN)(*[float(v) for v in std])
+        self._check(self.lib.gf_predictor_set(self.h, P, M, S))
+
+    def predict(self, features, valid=None, want_scores=False):
+        f = (ctypes.c_double * GF_MLP_IN)(*[float(v) for v in features])
+        vm = (ctypes.c_uint8 * GF_MLP_OUT)(*[1 if x else 0 for x in valid]) if valid is not None else None
+        sc = (ctypes.c_float * GF_MLP_OUT)()
+        r = self.lib.gf_predict(self.h, f, vm, sc)
+        if r < -1:
+            self._check(r)
+        return (r, [float(v) for v in sc]) if want_scores else r
 
     def copy(self, dst, src, nbytes: int, num_wg: int = 0, stream=None):
         self._check(self.lib.gf_copy(self.h, _ptr(dst), _ptr(src), nbytes, num_wg, _stream_handle(stream)))

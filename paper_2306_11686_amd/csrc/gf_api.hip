@@ -124,7 +124,21 @@ struct gf_ctx {
 
     hipStream_t capture_stream = nullptr;
     std::unordered_map<std::string, GraphEntry> graphs;
+
+    // batched persistent launches: device table, pinned staging, and an
+    // event that marks when the staging buffer may be rewritten
+    void *d_batch = nullptr;
+    void *h_batch = nullptr;
+    hipEvent_t batch_copied = nullptr;
+    bool batch_pending = false;
+
+    // predictor: device scratch for training, host copy for inference
+    float *d_mlp = nullptr;       // gradient partials | grads | z1 | z2 | y | loss partials
+    size_t d_mlp_floats = 0;
+    std::vector<float> pred_params, pred_mean, pred_std;
 };
+
+constexpr size_t kBatchBytes = (size_t)4096 * sizeof(BatchEntry) + (size_t)GF_MAX_INSTANCES * sizeof(DInst);
 
 namespace {
 
@@ -283,6 +297,12 @@ gf_status gf_ctx_create(int32_t hip_device, const gf_ctx_opts *opts, gf_ctx **ou
     ctx->capture = o.rpc_capture != 0;
     if (hipStreamCreateWithFlags(&ctx->capture_stream, hipStreamNonBlocking) != hipSuccess)
         ctx->capture_stream = nullptr;
+    if (hipMalloc(&ctx->d_batch, kBatchBytes) != hipSuccess ||
+        hipHostMalloc(&ctx->h_batch, kBatchBytes, hipHostMallocDefault) != hipSuccess ||
+        hipEventCreateWithFlags(&ctx->batch_copied, hipEventDisableTiming) != hipSuccess) {
+        gf_ctx_destroy(ctx);
+        return GF_ENOMEM;
+    }
     if (o.rpc_thread) {
         ctx->server = std::thread([ctx] {
             while (!ctx->stop.load()) {
@@ -318,10 +338,18 @@ gf_status gf_ctx_destroy(gf_ctx *ctx)
     }
     if (ctx->capture_stream)
         hipStreamDestroy(ctx->capture_stream);
+    if (ctx->batch_copied)
+        hipEventDestroy(ctx->batch_copied);
+    if (ctx->h_batch)
+        hipHostFree(ctx->h_batch);
+    if (ctx->d_batch)
+        hipFree(ctx->d_batch);
     if (ctx->h_slots)
         hipHostFree(ctx->h_slots);
     if (ctx->d_scratch_lines)
         hipFree(ctx->d_scratch_lines);
+    if (ctx->d_mlp)
+        hipFree(ctx->d_mlp);
     delete ctx;
     return GF_OK;
 }
@@ -765,6 +793,119 @@ std::string graph_key(const DProg &p, const gf_instance *inst, int n_inst, const
 
 }  // namespace
 
+// Batched persistent launch (many uneven instances of one program in one
+// cooperative launch): instance i gets a group of g_i >= 1 workgroups with
+// g_i proportional to its work items (largest remainders, capped at its
+// item count), its own flat group barrier and its own slice of the
+// reduction partials. The device table is staged through pinned memory; the
+// staging buffer is rewritten only after the previous copy has executed.
+gf_status run_batched(gf_ctx *ctx, const DProg &p, const gf_instance *inst, int n_inst, const Tiling &t,
+                      const gf_launch *launch, int cap, gf_run_stats *stats, hipStream_t stream)
+{
+    if (program_is_hist_family(p))
+        return fail(ctx, GF_EUNSUPPORTED, "batched persistent runs of histogram programs are not supported");
+    int budget = cap;
+    if (launch && launch->num_wg > 0)
+        budget = std::min(budget, launch->num_wg);
+    budget = std::min(budget, 4096);
+    if (n_inst > budget)
+        return fail(ctx, GF_EINVAL, "%d instances need at least %d co-resident workgroups, capacity %d", n_inst,
+                    n_inst, budget);
+    std::vector<int64_t> items(n_inst), red(n_inst);
+    int64_t total = 0;
+    for (int i = 0; i < n_inst; ++i) {
+        items[i] = std::max<int64_t>(1, max_items(p, inst[i], t));
+        int64_t r = 0;
+        for (int k = 0; k < p.n_steps; ++k)
+            if (is_region(p.steps[k].kind) && p.steps[k].red_op != GF_OP_NONE)
+                r = std::max<int64_t>(r, region_items(p.steps[k], inst[i].ip[p.steps[k].np], t));
+        red[i] = r;
+        total += items[i];
+    }
+    // proportional allocation with a floor of one workgroup each
+    std::vector<int> g(n_inst, 1);
+    int used = n_inst;
+    std::vector<std::pair<double, int>> rem;
+    const int spare = budget - n_inst;
+    for (int i = 0; i < n_inst; ++i) {
+        const double share = (double)spare * (double)items[i] / (double)total;
+        int extra = (int)std::floor(share);
+        extra = (int)std::min<int64_t>(extra, items[i] - 1);
+        g[i] += extra;
+        used += extra;
+        rem.emplace_back(share - std::floor(share), i);
+    }
+    std::sort(rem.begin(), rem.end(), [](const std::pair<double, int> &a, const std::pair<double, int> &b) {
+        return a.first > b.first || (a.first == b.first && a.second < b.second);
+    });
+    for (size_t k = 0; k < rem.size() && used < budget; ++k) {
+        const int i = rem[k].second;
+        if (g[i] < items[i]) {
+            ++g[i];
+            ++used;
+        }
+    }
+    // partial slices
+    std::vector<int64_t> off(n_inst);
+    int64_t acc = 0;
+    for (int i = 0; i < n_inst; ++i) {
+        off[i] = acc;
+        acc += red[i];
+    }
+    if (acc > ctx->scr.partials_cap)
+        return fail(ctx, GF_EINVAL, "batched reductions need %lld partial slots, capacity %lld", (long long)acc,
+                    (long long)ctx->scr.partials_cap);
+    // stage the table (wait until the previous staging copy has executed)
+    if (ctx->batch_pending) {
+        hipError_t e = hipEventSynchronize(ctx->batch_copied);
+        if (e != hipSuccess)
+            return hipfail(ctx, e, "batch staging wait");
+        ctx->batch_pending = false;
+    }
+    BatchEntry *hb = (BatchEntry *)ctx->h_batch;
+    DInst *hi = (DInst *)((char *)ctx->h_batch + (size_t)4096 * sizeof(BatchEntry));
+    int wg = 0;
+    for (int i = 0; i < n_inst; ++i) {
+        for (int m = 0; m < g[i]; ++m, ++wg) {
+            hb[wg].inst = i;
+            hb[wg].member = m;
+            hb[wg].gsize = g[i];
+            hb[wg].pad_ = 0;
+            hb[wg].part_off = off[i];
+        }
+        std::memcpy(hi[i].arr, inst[i].arr, sizeof hi[i].arr);
+        hi[i].scal = inst[i].scal;
+        std::memcpy(hi[i].ip, inst[i].ip, sizeof hi[i].ip);
+    }
+    BatchEntry *db = (BatchEntry *)ctx->d_batch;
+    DInst *di = (DInst *)((char *)ctx->d_batch + (size_t)4096 * sizeof(BatchEntry));
+    hipError_t e = hipMemcpyAsync(db, hb, (size_t)wg * sizeof(BatchEntry), hipMemcpyHostToDevice, stream);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(di, hi, (size_t)n_inst * sizeof(DInst), hipMemcpyHostToDevice, stream);
+    if (e == hipSuccess)
+        e = hipEventRecord(ctx->batch_copied, stream);
+    if (e != hipSuccess)
+        return hipfail(ctx, e, "batch table copy");
+    ctx->batch_pending = true;
+    BatchTable bt{db, di};
+    DInst dummy;
+    std::memset(&dummy, 0, sizeof dummy);
+    e = launch_persistent(p, dummy, t, wg, ctx->scr, ring_of(ctx), stream, &bt);
+    if (e != hipSuccess)
+        return hipfail(ctx, e, "batched persistent launch");
+    if (stats) {
+        stats->launches = 1;
+        stats->num_wg = wg;
+        stats->wg_size = t.wg_size;
+        int nb = 0;
+        for (int k = p.n_pro; k < p.n_steps; ++k)
+            nb += is_region(p.steps[k].kind);
+        stats->regions = n_inst * nb * p.iters;
+        stats->barriers = nb * p.iters;
+    }
+    return GF_OK;
+}
+
 extern "C" {
 
 int32_t gf_persistent_capacity(gf_ctx *ctx, const gf_program *prog, int32_t wg_size)
@@ -812,6 +953,8 @@ gf_status gf_region_run(gf_ctx *ctx, const gf_program *prog, const gf_instance *
         const int cap = std::min(4096, persistent_capacity(p, t, ctx->num_cu));
         if (cap <= 0)
             return fail(ctx, GF_EHIP, "occupancy query failed");
+        if (n_inst > 1)
+            return run_batched(ctx, p, inst, n_inst, t, launch, cap, stats, stream);
         for (int i = 0; i < n_inst; ++i) {
             // default grid: one workgroup per work item, at most two per CU
             // (the grid barrier's cost grows with the number of members)
@@ -1094,6 +1237,169 @@ int32_t gf_tune(gf_ctx *ctx, const gf_program *prog, const gf_instance *inst, in
         *best_index = gf_tune_pick(ms_out, (int32_t)cands.size());
     ctx->err.clear();
     return ran;
+}
+
+}  // extern "C"
+
+// ---------------------------------------------------------------------------
+// Launch-config predictor
+// ---------------------------------------------------------------------------
+
+namespace {
+
+constexpr int kMaxMlpBatch = 65536;
+
+// Ensure the predictor scratch holds `floats` floats (grown by reallocation;
+// the previous contents are not kept).
+gf_status mlp_scratch(gf_ctx *ctx, size_t floats)
+{
+    if (ctx->d_mlp_floats >= floats)
+        return GF_OK;
+    if (ctx->d_mlp) {
+        hipDeviceSynchronize();
+        hipFree(ctx->d_mlp);
+        ctx->d_mlp = nullptr;
+        ctx->d_mlp_floats = 0;
+    }
+    if (hipMalloc((void **)&ctx->d_mlp, floats * sizeof(float)) != hipSuccess)
+        return fail(ctx, GF_ENOMEM, "predictor scratch");
+    ctx->d_mlp_floats = floats;
+    return GF_OK;
+}
+
+size_t mlp_part_floats(int32_t batch) { return (size_t)mlp_blocks(batch) * GF_MLP_NPARAMS; }
+
+}  // namespace
+
+extern "C" {
+
+gf_status gf_mlp_forward(gf_ctx *ctx, const float *d_params, const float *d_feats, int32_t batch, float *d_y,
+                         float *d_z1, float *d_z2, void *hip_stream)
+{
+    if (!ctx)
+        return GF_EINVAL;
+    if (!d_params || (batch > 0 && (!d_feats || !d_y)) || batch < 0 || batch > kMaxMlpBatch)
+        return fail(ctx, GF_EINVAL, "bad MLP forward arguments");
+    hipSetDevice(ctx->device);
+    hipError_t e = launch_mlp_forward(d_params, d_feats, batch, d_y, d_z1, d_z2, (hipStream_t)hip_stream);
+    return e == hipSuccess ? GF_OK : hipfail(ctx, e, "MLP forward");
+}
+
+gf_status gf_mlp_backward(gf_ctx *ctx, const float *d_params, const float *d_feats, const float *d_z1,
+                          const float *d_z2, const float *d_y, const float *d_target, const float *d_mask,
+                          int32_t batch, float inv_norm, float *d_grads, void *hip_stream)
+{
+    if (!ctx)
+        return GF_EINVAL;
+    if (!d_params || !d_feats || !d_z1 || !d_z2 || !d_y || !d_target || !d_mask || !d_grads || batch < 1 ||
+        batch > kMaxMlpBatch)
+        return fail(ctx, GF_EINVAL, "bad MLP backward arguments");
+    hipSetDevice(ctx->device);
+    gf_status st = mlp_scratch(ctx, mlp_part_floats(batch));
+    if (st != GF_OK)
+        return st;
+    hipError_t e = launch_mlp_backward(d_params, d_feats, d_z1, d_z2, d_y, d_target, d_mask, batch, inv_norm,
+                                       ctx->d_mlp, d_grads, (hipStream_t)hip_stream);
+    return e == hipSuccess ? GF_OK : hipfail(ctx, e, "MLP backward");
+}
+
+gf_status gf_mlp_loss(gf_ctx *ctx, const float *d_y, const float *d_target, const float *d_mask, int64_t count,
+                      float inv_norm, float *d_loss, void *hip_stream)
+{
+    if (!ctx)
+        return GF_EINVAL;
+    if (!d_y || !d_target || !d_mask || !d_loss || count < 0)
+        return fail(ctx, GF_EINVAL, "bad MLP loss arguments");
+    hipSetDevice(ctx->device);
+    gf_status st = mlp_scratch(ctx, 64);
+    if (st != GF_OK)
+        return st;
+    hipError_t e = launch_mlp_loss(d_y, d_target, d_mask, count, inv_norm, ctx->d_mlp, d_loss,
+                                   (hipStream_t)hip_stream);
+    return e == hipSuccess ? GF_OK : hipfail(ctx, e, "MLP loss");
+}
+
+gf_status gf_adam_step(gf_ctx *ctx, float *d_params, const float *d_grads, float *d_m, float *d_v, int32_t n,
+                       float lr, float beta1, float beta2, float eps, int32_t t, void *hip_stream)
+{
+    if (!ctx)
+        return GF_EINVAL;
+    if (!d_params || !d_grads || !d_m || !d_v || n < 0 || t < 1)
+        return fail(ctx, GF_EINVAL, "bad Adam arguments");
+    hipSetDevice(ctx->device);
+    hipError_t e = launch_adam(d_params, d_grads, d_m, d_v, n, lr, beta1, beta2, eps, t, (hipStream_t)hip_stream);
+    return e == hipSuccess ? GF_OK : hipfail(ctx, e, "Adam step");
+}
+
+gf_status gf_train_predictor(gf_ctx *ctx, float *d_params, float *d_m, float *d_v, const float *d_feats,
+                             const float *d_target, const float *d_mask, int32_t batch, float inv_norm,
+                             int32_t epochs, float lr, float *d_loss_hist, void *hip_stream)
+{
+    if (!ctx)
+        return GF_EINVAL;
+    if (!d_params || !d_m || !d_v || !d_feats || !d_target || !d_mask || batch < 1 || batch > kMaxMlpBatch ||
+        epochs < 0)
+        return fail(ctx, GF_EINVAL, "bad training arguments");
+    hipSetDevice(ctx->device);
+    // scratch: gradient partials | grads | z1 | z2 | y | loss partials
+    const size_t part = mlp_part_floats(batch);
+    const size_t zsz = (size_t)batch * GF_MLP_HIDDEN, ysz = (size_t)batch * GF_MLP_OUT;
+    gf_status st = mlp_scratch(ctx, part + GF_MLP_NPARAMS + 2 * zsz + ysz + 64);
+    if (st != GF_OK)
+        return st;
+    float *dpart = ctx->d_mlp, *dg = dpart + part, *z1 = dg + GF_MLP_NPARAMS, *z2 = z1 + zsz, *y = z2 + zsz,
+          *lpart = y + ysz;
+    hipStream_t s = (hipStream_t)hip_stream;
+    for (int32_t e = 0; e < epochs; ++e) {
+        hipError_t r = launch_mlp_forward(d_params, d_feats, batch, y, z1, z2, s);
+        if (r == hipSuccess && d_loss_hist)
+            r = launch_mlp_loss(y, d_target, d_mask, (int64_t)ysz, inv_norm, lpart, d_loss_hist + e, s);
+        if (r == hipSuccess)
+            r = launch_mlp_backward(d_params, d_feats, z1, z2, y, d_target, d_mask, batch, inv_norm, dpart, dg, s);
+        if (r == hipSuccess)
+            r = launch_adam(d_params, dg, d_m, d_v, GF_MLP_NPARAMS, lr, 0.9f, 0.999f, 1e-8f, e + 1, s);
+        if (r != hipSuccess)
+            return hipfail(ctx, r, "training step");
+    }
+    return GF_OK;
+}
+
+gf_status gf_predictor_set(gf_ctx *ctx, const float *h_params, const float *h_mean, const float *h_std)
+{
+    if (!ctx)
+        return GF_EINVAL;
+    if (!h_params || !h_mean || !h_std)
+        return fail(ctx, GF_EINVAL, "null predictor arrays");
+    ctx->pred_params.assign(h_params, h_params + GF_MLP_NPARAMS);
+    ctx->pred_mean.assign(h_mean, h_mean + GF_MLP_IN);
+    ctx->pred_std.assign(h_std, h_std + GF_MLP_IN);
+    return GF_OK;
+}
+
+int32_t gf_predict(gf_ctx *ctx, const double *h_features, const uint8_t *valid, float *scores)
+{
+    if (!ctx || !h_features)
+        return GF_EINVAL;
+    if (ctx->pred_params.empty())
+        return -1;
+    float f[GF_MLP_IN];
+    for (int k = 0; k < GF_MLP_IN; ++k) {
+        const double x = std::log2(1.0 + std::max(0.0, h_features[k]));
+        const double sd = ctx->pred_std[k] > 0.0f ? ctx->pred_std[k] : 1.0;
+        const double z = (x - ctx->pred_mean[k]) / sd;
+        if (!(std::fabs(z) <= 4.0))
+            return -1;
+        f[k] = (float)z;
+    }
+    float out[GF_MLP_OUT];
+    mlp_forward_host(ctx->pred_params.data(), f, out);
+    if (scores)
+        std::memcpy(scores, out, sizeof out);
+    int32_t best = -1;
+    for (int c = 0; c < GF_MLP_OUT; ++c)
+        if ((!valid || valid[c]) && (best < 0 || out[c] < out[best]))
+            best = c;
+    return best;
 }
 
 }  // extern "C"

@@ -204,6 +204,37 @@ __device__ __forceinline__ bool tree_barrier(uint32_t *genw, uint32_t *tree, uin
     return bs->ok != 0;
 }
 
+// Flat barrier for the small groups of a batched launch: one line, word 0
+// counts arrivals, word 1 is the generation (same publication protocol as
+// the tree barrier).
+__device__ __forceinline__ bool flat_barrier(uint32_t *line, uint32_t nmembers, BarrierState *bs, int32_t *err,
+                                             int64_t timeout_ticks)
+{
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        const uint32_t g = bs->gen;
+        int32_t ok = 1;
+        if (nmembers > 1) {
+            const uint32_t a = __hip_atomic_fetch_add(&line[0], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            if (a == nmembers - 1) {
+                __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+                __hip_atomic_store(&line[0], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                __hip_atomic_store(&line[1], g + 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+            } else {
+                ok = barrier_wait(&line[1], g, err, timeout_ticks) ? 1 : 0;
+            }
+        } else {
+            __hip_atomic_store(&line[1], g + 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        }
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+        bs->gen = g + 1u;
+        bs->ok = ok;
+    }
+    __syncthreads();
+    return bs->ok != 0;
+}
+
 // Logical worker id of workgroup `wg` among `nwg`: workgroups are dispatched
 // round-robin over the 8 XCDs (each with its own L2), so with remapping the
 // workers of one XCD get consecutive ids and hence neighbouring tiles.

@@ -46,6 +46,23 @@ struct DInst {
     int64_t ip[GF_MAX_IPARAMS];
 };
 
+// Batched persistent launch: workgroup b of the grid belongs to instance
+// `inst` as member `member` of a group of `gsize` workgroups; the group's
+// barrier lives on line kGroupLine0 + inst; its reduction partials start at
+// `part_off` in each half of the partials buffer.
+struct BatchEntry {
+    int32_t inst;
+    int32_t member;
+    int32_t gsize;
+    int32_t pad_;
+    int64_t part_off;
+};
+
+struct BatchTable {
+    const BatchEntry *wg;   // gridDim.x entries
+    const DInst *inst;      // per-instance bindings
+};
+
 // Tiling chosen on the host; identical in every workgroup of a launch.
 struct Tiling {
     int32_t wg_size;
@@ -143,9 +160,23 @@ struct RegionLaunch {
     Glue glue[kMaxGlue];
 };
 
+// Launch-config predictor (gf_mlp.hip).
+hipError_t launch_mlp_forward(const float *P, const float *feats, int32_t batch, float *y, float *z1, float *z2,
+                              hipStream_t s);
+hipError_t launch_mlp_backward(const float *P, const float *feats, const float *z1, const float *z2, const float *y,
+                               const float *tgt, const float *mask, int32_t batch, float inv_norm, float *part,
+                               float *grads, hipStream_t s);
+hipError_t launch_mlp_loss(const float *y, const float *tgt, const float *mask, int64_t count, float inv_norm,
+                           float *part, float *loss, hipStream_t s);
+hipError_t launch_adam(float *p, const float *g, float *m, float *v, int32_t n, float lr, float b1, float b2,
+                       float eps, int32_t t, hipStream_t s);
+int mlp_blocks(int32_t batch);
+void mlp_forward_host(const float *P, const float *f, float *out);
+
 // Host-side launch helpers implemented in gf_kernels.hip.
 hipError_t launch_persistent(const DProg &prog, const DInst &inst, const Tiling &t, int num_wg,
-                             const Scratch &scr, const RpcRing &rpc, hipStream_t s);
+                             const Scratch &scr, const RpcRing &rpc, hipStream_t s,
+                             const BatchTable *batch = nullptr);
 int persistent_capacity(const DProg &prog, const Tiling &t, int num_cu);
 hipError_t launch_region(const RegionLaunch &rl, const Tiling &t, int num_wg, const Scratch &scr,
                          const RpcRing &rpc, hipStream_t s);

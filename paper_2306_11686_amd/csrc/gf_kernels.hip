@@ -690,17 +690,37 @@ constexpr int family_max_threads()
 
 template <unsigned KMASK, int TY>
 __global__ void __launch_bounds__(family_max_threads<KMASK>())
-    k_persistent(DProg prog, DInst inst, Tiling t, Scratch scr, RpcRing rpc)
+    k_persistent(DProg prog, DInst inst_arg, Tiling t, Scratch scr, RpcRing rpc, BatchTable batch)
 {
     __shared__ double s_scal[GF_MAX_SCALARS];
     __shared__ void *s_arr[GF_MAX_ARRAYS];
     __shared__ double s_red[kLdsRed];
     __shared__ BarrierState s_bar;
 
-    const int64_t G = gridDim.x;
-    const int64_t worker = worker_id(blockIdx.x, G, t.xcd_remap);
-    uint32_t *genw = scr.lines + 1;  // line 0, word 1: the grid barrier's generation
+    // Single instance: the whole grid, tree barrier. Batched: this
+    // workgroup's group of its instance, flat group barrier.
+    const bool batched = batch.wg != nullptr;
+    BatchEntry be;
+    if (batched) {
+        be = batch.wg[blockIdx.x];
+    } else {
+        be.inst = 0;
+        be.member = (int32_t)blockIdx.x;
+        be.gsize = (int32_t)gridDim.x;
+        be.part_off = 0;
+    }
+    const DInst &inst = batched ? batch.inst[be.inst] : inst_arg;
+    const int64_t G = be.gsize;
+    const int64_t member = be.member;
+    const int64_t worker = batched ? member : worker_id(blockIdx.x, G, t.xcd_remap);
+    uint32_t *gline = scr.lines + (int64_t)(kGroupLine0 + be.inst) * kLineWords;
+    uint32_t *genw = batched ? gline + 1 : scr.lines + 1;  // generation word
     uint32_t *tree = scr.lines + kTreeLine0 * kLineWords;
+    auto barrier = [&]() -> bool {
+        return batched ? flat_barrier(gline, (uint32_t)G, &s_bar, scr.error, scr.barrier_timeout_ticks)
+                       : tree_barrier(genw, tree, (uint32_t)member, (uint32_t)G, &s_bar, scr.error,
+                                      scr.barrier_timeout_ticks);
+    };
     if (threadIdx.x < GF_MAX_SCALARS)
         s_scal[threadIdx.x] = inst.scal[threadIdx.x];
     if (threadIdx.x < GF_MAX_ARRAYS)
@@ -728,20 +748,18 @@ __global__ void __launch_bounds__(family_max_threads<KMASK>())
         if (st.kind < 32) {
             const int64_t n = inst.ip[st.np];
             const bool red = st.red_op != GF_OP_NONE;
-            double *part = scr.partials + (parity ? scr.partials_cap : 0);
+            double *part = scr.partials + (parity ? scr.partials_cap : 0) + be.part_off;
             void *op[5];
 #pragma unroll
             for (int k = 0; k < 5; ++k)
                 op[k] = uniform_ptr(st.arr[k] >= 0 ? s_arr[st.arr[k]] : nullptr);
             const double coef = uniform_f64((st.kind == GF_R_AXPBY) ? s_scal[st.sc[1]] * st.c : 0.0);
             if (st.kind == GF_R_OWNER) {
-                owner_region((int32_t *)op[0], n, st.chunk, G * blockDim.x,
-                             (int64_t)blockIdx.x * blockDim.x + threadIdx.x);
+                owner_region((int32_t *)op[0], n, st.chunk, G * blockDim.x, member * blockDim.x + threadIdx.x);
             } else if (st.kind == GF_R_HIST) {
                 if constexpr ((KMASK >> GF_R_HIST) & 1u) {
                     hist_phase1((const uint32_t *)op[0], (uint32_t *)op[1], scr.hist_rows, st.mask, n, worker, G, t);
-                    if (!tree_barrier(genw, tree, blockIdx.x, (uint32_t)G, &s_bar, scr.error,
-                                      scr.barrier_timeout_ticks))
+                    if (!barrier())
                         return;
                     hist_merge((uint32_t *)op[1], scr.hist_rows, st.mask, G, worker * blockDim.x + threadIdx.x,
                                G * blockDim.x);
@@ -756,7 +774,7 @@ __global__ void __launch_bounds__(family_max_threads<KMASK>())
                             part[it] = v;
                     }
                 }
-                if (!tree_barrier(genw, tree, blockIdx.x, (uint32_t)G, &s_bar, scr.error, scr.barrier_timeout_ticks))
+                if (!barrier())
                     return;
                 if (red) {
                     const double v = reduce_partials(st.red_op, part, nitems, s_red);
@@ -767,7 +785,7 @@ __global__ void __launch_bounds__(family_max_threads<KMASK>())
                 __syncthreads();
                 continue;
             }
-            if (!tree_barrier(genw, tree, blockIdx.x, (uint32_t)G, &s_bar, scr.error, scr.barrier_timeout_ticks))
+            if (!barrier())
                 return;
         } else if (threadIdx.x == 0) {
             if (st.kind == GF_S_SWAP) {
@@ -775,10 +793,10 @@ __global__ void __launch_bounds__(family_max_threads<KMASK>())
                 s_arr[st.arr[0]] = s_arr[st.arr[1]];
                 s_arr[st.arr[1]] = tmp;
             } else if (st.kind == GF_S_RECORD) {
-                if (blockIdx.x == 0 && iter >= 0)
+                if (member == 0 && iter >= 0)
                     ((double *)s_arr[st.arr[0]])[iter] = s_scal[st.sc[0]];
             } else if (st.kind == GF_S_PRINTF) {
-                if (blockIdx.x == 0 && iter >= 0 && st.every > 0 && (iter + 1) % st.every == 0)
+                if (member == 0 && iter >= 0 && st.every > 0 && (iter + 1) % st.every == 0)
                     serial_printf(rpc, st.fmt_id, st.nargs, st.flags, st.sc, iter, s_scal, scr.error);
             } else {
                 serial_scalar(st.kind, st.sc, st.c, s_scal);
@@ -786,7 +804,7 @@ __global__ void __launch_bounds__(family_max_threads<KMASK>())
         }
         __syncthreads();
     }
-    if (blockIdx.x == 0 && threadIdx.x < GF_MAX_SCALARS)
+    if (member == 0 && threadIdx.x < GF_MAX_SCALARS)
         inst.scal[threadIdx.x] = s_scal[threadIdx.x];
 }
 
@@ -929,7 +947,7 @@ static unsigned pick_family(unsigned kinds)
     return kFamAll;
 }
 
-typedef void (*PersistentFn)(DProg, DInst, Tiling, Scratch, RpcRing);
+typedef void (*PersistentFn)(DProg, DInst, Tiling, Scratch, RpcRing, BatchTable);
 typedef void (*RegionFn)(RegionLaunch, Tiling, Scratch, RpcRing);
 
 template <unsigned F>
@@ -1019,7 +1037,7 @@ int persistent_capacity(const DProg &prog, const Tiling &t, int num_cu)
 }
 
 hipError_t launch_persistent(const DProg &prog, const DInst &inst, const Tiling &t, int num_wg, const Scratch &scr,
-                             const RpcRing &rpc, hipStream_t s)
+                             const RpcRing &rpc, hipStream_t s, const BatchTable *batch)
 {
     PersistentFn fn = persistent_fn(pick_family(program_kinds(prog)), t.tile_y);
     if (!fn)
@@ -1029,7 +1047,10 @@ hipError_t launch_persistent(const DProg &prog, const DInst &inst, const Tiling 
     Tiling tt = t;
     Scratch sc = scr;
     RpcRing r = rpc;
-    void *args[] = {&p, &i, &tt, &sc, &r};
+    BatchTable bt{nullptr, nullptr};
+    if (batch)
+        bt = *batch;
+    void *args[] = {&p, &i, &tt, &sc, &r, &bt};
     return hipLaunchCooperativeKernel(reinterpret_cast<const void *>(fn), dim3(num_wg), dim3(t.wg_size), args, 0, s);
 }
 

@@ -1,0 +1,80 @@
+"""GPU parity of the batched persistent launch: many uneven 2D Jacobi
+instances in one cooperative launch, each on its own group of workgroups.
+Every instance must equal the oracle on that instance (grid bit-exact,
+residuals within 1e-12 of the compensated sum) and, bit for bit, the same
+program run alone."""
+import numpy as np
+import pytest
+
+import gf_inputs as gi
+from tests.gpu_helpers import dev, host, run_jacobi2d
+
+pytestmark = pytest.mark.gpu
+
+
+def _batch(gf, programs, sides, sweeps, seed=1):
+    import torch
+    us, ws, rs, scs, insts = [], [], [], [], []
+    for i, n in enumerate(sides):
+        u = dev(gi.batched_grid(i, int(n), seed))
+        w = u.clone()
+        r = torch.zeros(sweeps, dtype=torch.float64, device="cuda")
+        sc = torch.zeros(16, dtype=torch.float64, device="cuda")
+        us.append(u); ws.append(w); rs.append(r); scs.append(sc)
+        insts.append(gf.Instance.make({programs.J2_U: u, programs.J2_W: w, programs.J2_RES: r}, sc, ip=(int(n),)))
+    return us, ws, rs, insts
+
+
+@pytest.mark.parametrize("nwg", [0, 40, 300])
+def test_batched_small_uneven_instances(gfx, oracle_lib, nwg):
+    import paper_2306_11686_amd as gf
+    from paper_2306_11686_amd import programs
+    sides = [3, 4, 5, 17, 64, 65, 100, 129, 200, 31, 9, 250]
+    sweeps = 7
+    us, ws, rs, insts = _batch(gf, programs, sides, sweeps)
+    st = gfx.run(programs.jacobi2d(sweeps), insts, mode=gf.GF_EXEC_PERSISTENT,
+                 launch=gf.Launch.make(num_wg=nwg) if nwg else None)
+    gfx.sync()
+    assert st["launches"] == 1 and st["num_wg"] >= len(sides)
+    for i, n in enumerate(sides):
+        g_ref, _, r_comp, _ = oracle_lib.jacobi2d(gi.batched_grid(i, n, 1), sweeps)
+        g = host(us[i] if sweeps % 2 == 0 else ws[i])
+        assert np.array_equal(g, g_ref), (i, n)
+        r = host(rs[i])
+        assert np.all(np.abs(r - r_comp) <= 1e-12 * r_comp + 1e-300), (i, n)
+
+
+def test_batched_equals_single_instance_bitwise(gfx):
+    import paper_2306_11686_amd as gf
+    from paper_2306_11686_amd import programs
+    sides = [70, 300, 45, 1000, 129]
+    sweeps = 6
+    us, ws, rs, insts = _batch(gf, programs, sides, sweeps, seed=3)
+    gfx.run(programs.jacobi2d(sweeps), insts, mode=gf.GF_EXEC_PERSISTENT)
+    gfx.sync()
+    for i, n in enumerate(sides):
+        g1, r1, _ = run_jacobi2d(gfx, gi.batched_grid(i, n, 3), sweeps, gf.GF_EXEC_PERSISTENT)
+        assert np.array_equal(host(us[i]), g1) and np.array_equal(host(rs[i]), r1)
+
+
+def test_batched_256_instances_config(gfx, oracle_lib):
+    """256 instances, sides floor(64 * 32^U) in [64, 2048], 50 sweeps with an
+    L2 residual, in one launch. Sampled instances (smallest, largest and every
+    32nd) are checked against the oracle; all against their residual decay."""
+    import paper_2306_11686_amd as gf
+    from paper_2306_11686_amd import programs
+    sides = gi.batched_sides(256, seed=1)
+    sweeps = 50
+    print(f"batched 256 instances, sum n^2 = {int((sides.astype(np.int64) ** 2).sum())}", flush=True)
+    us, ws, rs, insts = _batch(gf, programs, sides, sweeps)
+    gfx.run(programs.jacobi2d(sweeps), insts, mode=gf.GF_EXEC_PERSISTENT)
+    gfx.sync()
+    sample = sorted({int(np.argmin(sides)), int(np.argmax(sides))} | set(range(0, 256, 32)))
+    for i in sample:
+        n = int(sides[i])
+        g_ref, _, r_comp, _ = oracle_lib.jacobi2d(gi.batched_grid(i, n, 1), sweeps)
+        assert np.array_equal(host(us[i]), g_ref), (i, n)
+        assert np.all(np.abs(host(rs[i]) - r_comp) <= 1e-12 * r_comp), (i, n)
+    for i in range(256):
+        r = host(rs[i])
+        assert np.all(r > 0) and np.all(np.diff(r) <= 1e-12 * r[:-1])
