@@ -541,9 +541,12 @@ Tiling choose_tiling(const DProg &p, const gf_launch *l)
     std::memset(&t, 0, sizeof t);
     const unsigned m = program_region_mask(p);
     t.wg_size = program_is_hist_family(p) ? 1024 : 256;
+    if (program_is_hist_family(p))
+        t.items = 8;
     t.tile_y = (m & (1u << GF_R_JACOBI3D)) ? 8 : ((m & (1u << GF_R_JACOBI2D)) ? 1 : 1);
     t.tile_z = 64;
-    t.items = 4;
+    if (!program_is_hist_family(p))
+        t.items = 4;
     t.xcd_remap = 1;
     if (l) {
         if (l->wg_size)
@@ -570,6 +573,8 @@ gf_status check_tiling(gf_ctx *ctx, const DProg &p, const Tiling &t)
         return fail(ctx, GF_EINVAL, "tile_z out of range");
     if (t.items < 1 || t.items > 64)
         return fail(ctx, GF_EINVAL, "items must be 1..64");
+    if (program_is_hist_family(p) && (int64_t)t.wg_size * t.items * 4 > 32768)
+        return fail(ctx, GF_EINVAL, "histogram chunks hold at most 32768 keys (wg_size * items * 4)");
     return GF_OK;
 }
 

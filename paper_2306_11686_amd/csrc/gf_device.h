@@ -167,11 +167,23 @@ __device__ __forceinline__ bool barrier_wait(uint32_t *genw, uint32_t g, int32_t
 
 // member: this workgroup's index in the barrier's group of nmembers.
 // genw: the generation word; tree: first counter line of this barrier.
+// Publication of a workgroup's stores before it arrives: every wavefront
+// waits until its own stores are acknowledged (s_waitcnt vmcnt(0)), then the
+// workgroup barrier, then one agent-scope release by thread 0 (which writes
+// the XCD's L2 back for the other XCDs). One release per workgroup instead of
+// one per wavefront halves the barrier's cost at 256+ workgroups.
+__device__ __forceinline__ void wg_publish()
+{
+    __builtin_amdgcn_s_waitcnt(0x0F70);  // vmcnt(0); expcnt and lgkmcnt left at their maxima
+    __syncthreads();
+    if (threadIdx.x == 0)
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+}
+
 __device__ __forceinline__ bool tree_barrier(uint32_t *genw, uint32_t *tree, uint32_t member, uint32_t nmembers,
                                              BarrierState *bs, int32_t *err, int64_t timeout_ticks)
 {
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
-    __syncthreads();
+    wg_publish();
     if (threadIdx.x == 0) {
         const uint32_t g = bs->gen;
         uint32_t idx = member, n = nmembers, base = 0;
@@ -210,8 +222,7 @@ __device__ __forceinline__ bool tree_barrier(uint32_t *genw, uint32_t *tree, uin
 __device__ __forceinline__ bool flat_barrier(uint32_t *line, uint32_t nmembers, BarrierState *bs, int32_t *err,
                                              int64_t timeout_ticks)
 {
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
-    __syncthreads();
+    wg_publish();
     if (threadIdx.x == 0) {
         const uint32_t g = bs->gen;
         int32_t ok = 1;

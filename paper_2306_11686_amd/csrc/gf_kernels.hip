@@ -502,23 +502,38 @@ __device__ __forceinline__ void axpby_item(double *out_, const double *x_, doubl
 // Histogram, phase 1: this worker counts the keys of its chunks whose bin
 // falls in its part (all of a worker's items share one part because the
 // worker stride is a multiple of the part count) into 16-bit counters packed
-// two per 32-bit LDS word, then writes them as its partial row. A counter
-// that reaches 0x8000 hands 0x8000 to the global bin and drops back: its
-// half never exceeds 0x8000 plus the increments in flight, so no carry
-// crosses into the neighbouring counter and the escape needs no lock.
-// Integer counts are exact in any order.
-__device__ __forceinline__ void hist_count(uint32_t *s_h, GF_GLOBAL uint32_t *bins, uint32_t key, uint32_t mask,
-                                           uint32_t lo, uint32_t span)
+// two per 32-bit LDS word, with non-returning LDS atomics, then writes them
+// as its partial row. After every chunk (at most 32768 keys, checked on the
+// host) the workgroup moves 0x8000 of every counter that reached 0x8000 into
+// the global bin: a counter is below 0x8000 after a scan and grows by at most
+// 32768 before the next one, so it never wraps and no carry crosses into the
+// neighbouring counter. Integer counts are exact in any order.
+__device__ __forceinline__ void hist_count(uint32_t *s_h, uint32_t key, uint32_t mask, uint32_t lo, uint32_t span)
 {
     const uint32_t b = (key & mask) - lo;
-    if (b < span) {
-        const uint32_t sh = (b & 1u) * 16u;
-        const uint32_t old = atomicAdd(&s_h[b >> 1], 1u << sh);
-        if (((old >> sh) & 0xFFFFu) == 0x7FFFu) {
-            atomicSub(&s_h[b >> 1], 0x8000u << sh);
-            __hip_atomic_fetch_add(&bins[lo + b], 0x8000u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    if (b < span)
+        __hip_atomic_fetch_add(&s_h[b >> 1], 1u << ((b & 1u) * 16u), __ATOMIC_RELAXED,
+                               __HIP_MEMORY_SCOPE_WORKGROUP);
+}
+
+__device__ __forceinline__ void hist_escape(uint32_t *s_h, GF_GLOBAL uint32_t *bins, uint32_t lo, uint32_t span)
+{
+    __syncthreads();
+    for (uint32_t wd = threadIdx.x; wd < (span + 1) / 2; wd += blockDim.x) {
+        uint32_t v = s_h[wd];
+        if (v & 0x80008000u) {
+            if (v & 0x8000u) {
+                __hip_atomic_fetch_add(&bins[lo + 2 * wd], 0x8000u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                v -= 0x8000u;
+            }
+            if (v & 0x80000000u) {
+                __hip_atomic_fetch_add(&bins[lo + 2 * wd + 1], 0x8000u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                v -= 0x80000000u;
+            }
+            s_h[wd] = v;
         }
     }
+    __syncthreads();
 }
 
 __device__ __forceinline__ void hist_phase1(const uint32_t *keys_, uint32_t *bins_, uint32_t *rows_, uint32_t mask,
@@ -542,17 +557,17 @@ __device__ __forceinline__ void hist_phase1(const uint32_t *keys_, uint32_t *bin
             if (i4 + 3 < n) {
                 typedef uint32_t gf_u4 __attribute__((ext_vector_type(4)));
                 const gf_u4 v = *(GF_GLOBAL const gf_u4 *)(keys + i4);
-                hist_count(s_h, bins, v.x, mask, lo, span);
-                hist_count(s_h, bins, v.y, mask, lo, span);
-                hist_count(s_h, bins, v.z, mask, lo, span);
-                hist_count(s_h, bins, v.w, mask, lo, span);
+                hist_count(s_h, v.x, mask, lo, span);
+                hist_count(s_h, v.y, mask, lo, span);
+                hist_count(s_h, v.z, mask, lo, span);
+                hist_count(s_h, v.w, mask, lo, span);
             } else {
                 for (int64_t i = i4; i < n && i < i4 + 4; ++i)
-                    hist_count(s_h, bins, keys[i], mask, lo, span);
+                    hist_count(s_h, keys[i], mask, lo, span);
             }
         }
+        hist_escape(s_h, bins, lo, span);
     }
-    __syncthreads();
     GF_GLOBAL uint32_t *row = gptr(rows_) + worker * kHistPart;
     for (uint32_t i = threadIdx.x; i < span; i += blockDim.x)
         row[i] = (s_h[i >> 1] >> ((i & 1u) * 16u)) & 0xFFFFu;
@@ -867,10 +882,9 @@ __global__ void __launch_bounds__(family_max_threads<KMASK>()) k_region(RegionLa
         return;
     // last-workgroup finalize
     uint32_t *cnt = scr.lines + (int64_t)(kFinalizeLine0 + rl.inst) * kLineWords;
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
-    __syncthreads();
+    wg_publish();
     if (threadIdx.x == 0) {
-        const uint32_t a = __hip_atomic_fetch_add(cnt, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
+        const uint32_t a = __hip_atomic_fetch_add(cnt, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         s_last = (a == (uint32_t)G - 1);
     }
     __syncthreads();
@@ -899,10 +913,9 @@ __global__ void __launch_bounds__(kMaxWg) k_hist_merge(RegionLaunch rl, int64_t 
     if (rl.n_glue == 0)
         return;
     uint32_t *cnt = scr.lines + (int64_t)(kFinalizeLine0 + rl.inst) * kLineWords;
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
-    __syncthreads();
+    wg_publish();
     if (threadIdx.x == 0) {
-        const uint32_t a = __hip_atomic_fetch_add(cnt, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
+        const uint32_t a = __hip_atomic_fetch_add(cnt, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         s_last = (a == (uint32_t)G - 1);
     }
     __syncthreads();
@@ -1140,10 +1153,9 @@ __global__ void __launch_bounds__(kMaxWg) k_reduce(const TI *__restrict__ in, in
     acc = block_reduce_t<T, OP>(acc, s_red);
     if (threadIdx.x == 0)
         partials[blockIdx.x] = acc;
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
-    __syncthreads();
+    wg_publish();
     if (threadIdx.x == 0) {
-        const uint32_t a = __hip_atomic_fetch_add(cnt, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
+        const uint32_t a = __hip_atomic_fetch_add(cnt, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         s_last = (a == (uint32_t)G - 1);
     }
     __syncthreads();

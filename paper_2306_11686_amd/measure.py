@@ -1,0 +1,167 @@
+"""Measure the legacy-loop workloads other than the benchmark's headline.
+
+    python -m paper_2306_11686_amd.measure [--configs 2d,cg,hist,batched] [--reps 3]
+
+Each configuration prints one JSON line: time per run in the persistent,
+per-region and per-region-graph modes, regions per second, and algorithmic
+GB/s (bytes the sweep-at-a-time legacy loops must move; for the 2D grid the
+working set is cache-resident, so its GB/s is labelled as such).
+Launch shapes come from the tuning database when present.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import sys
+
+import numpy as np
+
+MODES = (("persistent", 1), ("per_region", 0), ("per_region_graph", 2))
+
+
+def log(msg):
+    print(msg, file=sys.stderr, flush=True)
+
+
+def _time(ctx, torch, fn, reps):
+    fn()
+    torch.cuda.synchronize()
+    ctx.sync()
+    ts = []
+    for _ in range(reps):
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record()
+        fn()
+        e1.record()
+        torch.cuda.synchronize()
+        ts.append(e0.elapsed_time(e1))
+    ctx.sync()
+    return float(np.median(ts))
+
+
+def _launch(tuner, key):
+    return tuner.lookup(key)
+
+
+def measure_2d(ctx, gf, programs, tuner, torch, gi, reps):
+    n, sweeps = 256, 100
+    fmt = ctx.register_format(programs.JACOBI2D_FORMAT, "id")
+    u = torch.from_numpy(gi.grid2d(n)).cuda()
+    w = u.clone()
+    res = torch.zeros(sweeps, dtype=torch.float64, device="cuda")
+    sc = torch.zeros(16, dtype=torch.float64, device="cuda")
+    inst = gf.Instance.make({0: u, 1: w, 2: res}, sc, ip=(n,))
+    bpsweep = 8 * (n * n - 4) + 8 * (n - 2) ** 2
+    out = {"config": "jacobi2d_5pt_256^2_f64_100sweeps_l2res_printf10", "alg_bytes_per_sweep": bpsweep}
+    launch = _launch(tuner, "jacobi2d_256")
+    for name, mode in MODES:
+        for pf in (True, False):
+            prog = programs.jacobi2d(sweeps, fmt_id=fmt if pf else -1, print_every=10)
+            ms = _time(ctx, torch, lambda: ctx.run(prog, inst, mode=mode, launch=launch), reps)
+            ctx.take_output()
+            key = name + ("" if pf else "_no_printf")
+            out[key] = {"ms_per_run": round(ms, 4), "us_per_region": round(ms * 1e3 / sweeps, 3),
+                        "regions_per_s": round(sweeps / (ms * 1e-3), 1),
+                        "GBps_cache_resident": round(bpsweep * sweeps / (ms * 1e-3) / 1e9, 1)}
+    for name, _ in MODES:
+        out[name]["printf_us_each"] = round((out[name]["ms_per_run"] - out[name + "_no_printf"]["ms_per_run"])
+                                            * 1e3 / 10, 3)
+    return out
+
+
+def measure_cg(ctx, gf, programs, tuner, torch, gi, reps):
+    m, iters = 128, 500
+    N = m ** 3
+    rowptr, col, val = gi.poisson27_csr(m)
+    b = gi.cg_rhs(N, seed=1)
+    t = {programs.CG_ROWPTR: torch.from_numpy(rowptr).cuda(), programs.CG_COL: torch.from_numpy(col).cuda(),
+         programs.CG_VAL: torch.from_numpy(val).cuda(), programs.CG_X: torch.zeros(N, dtype=torch.float64,
+                                                                                    device="cuda"),
+         programs.CG_R: torch.from_numpy(b).cuda(), programs.CG_P: torch.from_numpy(b).cuda(),
+         programs.CG_Q: torch.zeros(N, dtype=torch.float64, device="cuda"),
+         programs.CG_RHO: torch.zeros(iters, dtype=torch.float64, device="cuda")}
+    sc = torch.zeros(16, dtype=torch.float64, device="cuda")
+    inst = gf.Instance.make(t, sc, ip=(N,))
+    nnz = int(col.size)
+    spmv_b = 12 * nnz + 4 * (N + 1) + 8 * N + 8 * N
+    it_b = spmv_b + 2 * 16 * N + 3 * 24 * N
+    out = {"config": f"cg_27pt_{m}^3_f64_{iters}iters", "rows": N, "nnz": nnz, "alg_bytes_per_iteration": it_b}
+    launch = _launch(tuner, "cg_128")
+
+    def reset():
+        t[programs.CG_X].zero_()
+        t[programs.CG_R].copy_(torch.from_numpy(b).cuda())
+        t[programs.CG_P].copy_(t[programs.CG_R])
+
+    for name, mode in MODES:
+        reset()
+        ms = _time(ctx, torch, lambda: ctx.run(programs.cg(iters), inst, mode=mode, launch=launch), reps)
+        out[name] = {"ms_per_run": round(ms, 3), "GBps": round(iters * it_b / (ms * 1e-3) / 1e9, 1),
+                     "regions_per_s": round(6 * iters / (ms * 1e-3), 1)}
+    return out
+
+
+def measure_hist(ctx, gf, programs, tuner, torch, gi, reps):
+    n = 1 << 28
+    out = {"config": "hist_u32_2^28_keys_65536_bins", "alg_bytes": 4 * n + 2 * 4 * 65536}
+    launch = _launch(tuner, "hist_2^28")
+    for dist in ("uniform", "zipf"):
+        keys = gi.hist_keys_uniform(n, seed=1) if dist == "uniform" else gi.hist_keys_zipf(n, seed=1)
+        tk = torch.from_numpy(keys).cuda()
+        del keys
+        bins = torch.zeros(65536, dtype=torch.int32, device="cuda")
+        sc = torch.zeros(16, dtype=torch.float64, device="cuda")
+        inst = gf.Instance.make({0: tk, 1: bins}, sc, ip=(n,))
+        for name, mode in MODES[:2]:
+            ms = _time(ctx, torch, lambda: ctx.run(programs.histogram(65536), inst, mode=mode, launch=launch), reps)
+            out[f"{dist}_{name}"] = {"us_per_run": round(ms * 1e3, 1),
+                                     "GBps": round(out["alg_bytes"] / (ms * 1e-3) / 1e9, 1)}
+        del tk
+        torch.cuda.empty_cache()
+    return out
+
+
+def measure_batched(ctx, gf, programs, tuner, torch, gi, reps):
+    sides = gi.batched_sides(256, seed=1)
+    sweeps = 50
+    insts, keep = [], []
+    for i, n in enumerate(sides):
+        n = int(n)
+        u = torch.from_numpy(gi.batched_grid(i, n, 1)).cuda()
+        w = u.clone()
+        r = torch.zeros(sweeps, dtype=torch.float64, device="cuda")
+        sc = torch.zeros(16, dtype=torch.float64, device="cuda")
+        keep += [u, w, r, sc]
+        insts.append(gf.Instance.make({0: u, 1: w, 2: r}, sc, ip=(n,)))
+    bytes_per_sweepset = int(sum(8 * (int(n) ** 2 - 4) + 8 * (int(n) - 2) ** 2 for n in sides))
+    out = {"config": "batched_256x_jacobi2d_sides_64_2048_50sweeps", "sum_n2": int((sides.astype(np.int64) ** 2).sum()),
+           "alg_bytes_per_run": bytes_per_sweepset * sweeps, "regions_per_run": 256 * sweeps}
+    launch = _launch(tuner, "batched_256")
+    prog = programs.jacobi2d(sweeps)
+    for name, mode in MODES:
+        ms = _time(ctx, torch, lambda: ctx.run(prog, insts, mode=mode, launch=launch), reps)
+        out[name] = {"ms_per_run": round(ms, 3), "GBps": round(out["alg_bytes_per_run"] / (ms * 1e-3) / 1e9, 1),
+                     "regions_per_s": round(256 * sweeps / (ms * 1e-3), 1)}
+    return out
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--configs", default="2d,cg,hist,batched")
+    ap.add_argument("--reps", type=int, default=3)
+    args = ap.parse_args()
+    import torch
+    import gf_inputs as gi
+    import paper_2306_11686_amd as gf
+    from paper_2306_11686_amd import programs, tuner
+    ctx = gf.Context(0, rpc_capture=True)
+    fns = {"2d": measure_2d, "cg": measure_cg, "hist": measure_hist, "batched": measure_batched}
+    for c in args.configs.split(","):
+        log(f"[measure] {c}")
+        print(json.dumps(fns[c](ctx, gf, programs, tuner, torch, gi, args.reps)), flush=True)
+    ctx.close()
+
+
+if __name__ == "__main__":
+    main()
