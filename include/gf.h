@@ -265,7 +265,7 @@ gf_status gf_copy(gf_ctx *ctx, void *d_dst, const void *d_src, int64_t nbytes, i
  *   streaming (SpMV, dot, axpby): wg_size = {64,128,192,256}[a],
  *                items = {1,2,4,8}[b], num_wg = h ? 4 * CUs : default
  *   histogram  : wg_size = {256,512,768,1024}[a], items = {1,2,4,8}[b],
- *                num_wg = (h + 1) * CUs
+ *                num_wg = h ? CUs : CUs / 2
  * (n is the size of the program's first stencil region in `inst`). */
 #define GF_NUM_CANDIDATES 32
 

@@ -1142,7 +1142,7 @@ gf_launch decode_candidate(const DProg &p, const gf_instance &in, int c, int num
     if (m & (1u << GF_R_HIST)) {
         l.wg_size = hw[a];
         l.items = it[b];
-        l.num_wg = (h + 1) * num_cu;
+        l.num_wg = h ? num_cu : num_cu / 2;  // one 128 KiB-LDS workgroup per CU at most
         l.xcd_remap = 1;
     } else if (m & (1u << GF_R_JACOBI3D)) {
         const int64_t n = first_stencil_size(p, in);

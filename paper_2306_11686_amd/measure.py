@@ -146,9 +146,30 @@ def measure_batched(ctx, gf, programs, tuner, torch, gi, reps):
     return out
 
 
+def measure_sync(ctx, gf, programs, tuner, torch, gi, reps):
+    """Cost of one region of a trivial program (3D Jacobi on a 4^3 grid, one
+    interior point): the grid barrier plus serial glue in the persistent mode,
+    the launch gap in the per-region modes, at several grid sizes."""
+    regions = 2000
+    u = torch.zeros(64, dtype=torch.float64, device="cuda")
+    w = u.clone()
+    r = torch.zeros(regions, dtype=torch.float64, device="cuda")
+    sc = torch.zeros(16, dtype=torch.float64, device="cuda")
+    inst = gf.Instance.make({0: u, 1: w, 2: r}, sc, ip=(4,))
+    prog = programs.jacobi3d(regions)
+    out = {"config": "sync_cost_trivial_region", "regions": regions}
+    for nwg in (1, 64, 256, 512):
+        ms = _time(ctx, torch, lambda: ctx.run(prog, inst, mode=1, launch=gf.Launch.make(num_wg=nwg)), reps)
+        out[f"persistent_wg{nwg}_us_per_region"] = round(ms * 1e3 / regions, 3)
+    for name, mode in MODES[1:]:
+        ms = _time(ctx, torch, lambda: ctx.run(prog, inst, mode=mode), reps)
+        out[f"{name}_us_per_region"] = round(ms * 1e3 / regions, 3)
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
-    ap.add_argument("--configs", default="2d,cg,hist,batched")
+    ap.add_argument("--configs", default="sync,2d,cg,hist,batched")
     ap.add_argument("--reps", type=int, default=3)
     args = ap.parse_args()
     import torch
@@ -156,7 +177,8 @@ def main():
     import paper_2306_11686_amd as gf
     from paper_2306_11686_amd import programs, tuner
     ctx = gf.Context(0, rpc_capture=True)
-    fns = {"2d": measure_2d, "cg": measure_cg, "hist": measure_hist, "batched": measure_batched}
+    fns = {"sync": measure_sync, "2d": measure_2d, "cg": measure_cg, "hist": measure_hist,
+           "batched": measure_batched}
     for c in args.configs.split(","):
         log(f"[measure] {c}")
         print(json.dumps(fns[c](ctx, gf, programs, tuner, torch, gi, args.reps)), flush=True)

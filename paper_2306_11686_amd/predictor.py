@@ -184,9 +184,13 @@ def train(ctx, raw_feats, ms, epochs: int = 2000, lr: float = 3e-3, seed: int = 
             "loss_history": hist.cpu().numpy().tolist()}
 
 
-def predict_indices(ctx, model, raw_feats):
+def predict_indices(ctx, model, raw_feats, valid=None):
+    """Predicted candidate per nest; valid (optional, [N,32] bool) restricts
+    the argmin to shapes that can run."""
     ctx.predictor_set(model["params"], model["mean"], model["std"])
-    return [ctx.predict(f) for f in raw_feats]
+    if valid is None:
+        return [ctx.predict(f) for f in raw_feats]
+    return [ctx.predict(f, valid=v) for f, v in zip(raw_feats, valid)]
 
 
 def evaluate(pred_idx, ms, default_idx=None):

@@ -66,9 +66,9 @@ def main():
     log(f"[predictor] trained {args.epochs} epochs in {train_s:.2f} s, loss {hist[0]:.4f} -> {hist[-1]:.4f}")
 
     t0 = time.perf_counter()
-    pred_te = predictor.predict_indices(ctx, model, f_te)
+    pred_te = predictor.predict_indices(ctx, model, f_te, valid=np.isfinite(ms_te))
     infer_us = (time.perf_counter() - t0) / max(1, len(f_te)) * 1e6
-    pred_tr = predictor.predict_indices(ctx, model, f_tr)
+    pred_tr = predictor.predict_indices(ctx, model, f_tr, valid=np.isfinite(ms_tr))
     # best single fixed shape on the training set (per family shapes differ in
     # meaning, so the fixed baseline is chosen per kind)
     kinds_tr = [s["kind"] for s in specs_tr]
