@@ -172,6 +172,8 @@ typedef struct {
     int32_t tile_z;      /* 3D stencil z-segment length */
     int32_t items;       /* elements per thread for streaming regions */
     int32_t xcd_remap;   /* 1: map consecutive tiles to one XCD (8 XCDs) */
+    int32_t prefetch;    /* 3D stencil: planes loaded ahead of the one computed, 1 or 2
+                          * (2 needs tile_y <= 8); ignored by other regions */
 } gf_launch;
 
 typedef struct {
@@ -259,7 +261,7 @@ gf_status gf_copy(gf_ctx *ctx, void *d_dst, const void *d_src, int64_t nbytes, i
  * Candidate c (0..31) is decoded per kernel family of the program, with
  * a = c & 3, b = (c >> 2) & 3, h = c >> 4:
  *   3D stencil : tile_y = {1,2,4,8}[a], tile_z = ceil((n-2)/{2,3,4,6}[b]),
- *                xcd_remap = 1 - h
+ *                prefetch = 1 + h
  *   2D stencil : tile_y = {1,2,4,8}[a], wg_size = {64,128,192,256}[b],
  *                xcd_remap = 1 - h
  *   streaming (SpMV, dot, axpby): wg_size = {64,128,192,256}[a],

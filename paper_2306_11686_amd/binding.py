@@ -85,11 +85,12 @@ class Instance(ctypes.Structure):
 
 class Launch(ctypes.Structure):
     _fields_ = [("wg_size", ctypes.c_int32), ("num_wg", ctypes.c_int32), ("tile_y", ctypes.c_int32),
-                ("tile_z", ctypes.c_int32), ("items", ctypes.c_int32), ("xcd_remap", ctypes.c_int32)]
+                ("tile_z", ctypes.c_int32), ("items", ctypes.c_int32), ("xcd_remap", ctypes.c_int32),
+                ("prefetch", ctypes.c_int32)]
 
     @classmethod
-    def make(cls, wg_size=0, num_wg=0, tile_y=0, tile_z=0, items=0, xcd_remap=1):
-        return cls(wg_size, num_wg, tile_y, tile_z, items, xcd_remap)
+    def make(cls, wg_size=0, num_wg=0, tile_y=0, tile_z=0, items=0, xcd_remap=1, prefetch=0):
+        return cls(wg_size, num_wg, tile_y, tile_z, items, xcd_remap, prefetch)
 
 
 class RunStats(ctypes.Structure):

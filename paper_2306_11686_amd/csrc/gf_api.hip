@@ -545,6 +545,7 @@ Tiling choose_tiling(const DProg &p, const gf_launch *l)
         t.items = 8;
     t.tile_y = (m & (1u << GF_R_JACOBI3D)) ? 8 : ((m & (1u << GF_R_JACOBI2D)) ? 1 : 1);
     t.tile_z = 64;
+    t.prefetch = 1;
     if (!program_is_hist_family(p))
         t.items = 4;
     t.xcd_remap = 1;
@@ -558,6 +559,8 @@ Tiling choose_tiling(const DProg &p, const gf_launch *l)
         if (l->items)
             t.items = l->items;
         t.xcd_remap = l->xcd_remap;
+        if (l->prefetch)
+            t.prefetch = l->prefetch;
     }
     return t;
 }
@@ -573,6 +576,10 @@ gf_status check_tiling(gf_ctx *ctx, const DProg &p, const Tiling &t)
         return fail(ctx, GF_EINVAL, "tile_z out of range");
     if (t.items < 1 || t.items > 64)
         return fail(ctx, GF_EINVAL, "items must be 1..64");
+    if (t.prefetch != 1 && t.prefetch != 2)
+        return fail(ctx, GF_EINVAL, "prefetch must be 1 or 2");
+    if (t.prefetch == 2 && t.tile_y > 8)
+        return fail(ctx, GF_EINVAL, "prefetch 2 needs tile_y <= 8");
     if (program_is_hist_family(p) && (int64_t)t.wg_size * t.items * 4 > 32768)
         return fail(ctx, GF_EINVAL, "histogram chunks hold at most 32768 keys (wg_size * items * 4)");
     return GF_OK;
@@ -1149,7 +1156,8 @@ gf_launch decode_candidate(const DProg &p, const gf_instance &in, int c, int num
         const int64_t interior = n > 2 ? n - 2 : 1;
         l.tile_y = ty[a];
         l.tile_z = (int32_t)std::max<int64_t>(1, (interior + zs[b] - 1) / zs[b]);
-        l.xcd_remap = 1 - h;
+        l.xcd_remap = 1;
+        l.prefetch = 1 + h;
     } else if (m & (1u << GF_R_JACOBI2D)) {
         l.tile_y = ty[a];
         l.wg_size = wg[b];

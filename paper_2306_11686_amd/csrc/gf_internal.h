@@ -70,7 +70,7 @@ struct Tiling {
     int32_t tile_z;
     int32_t items;
     int32_t xcd_remap;
-    int32_t pad_;
+    int32_t prefetch;  // 3D stencil: planes requested ahead of the one computed (1 or 2)
 };
 
 // One RPC request slot in pinned, coherent host memory (cf. the paper's

@@ -245,7 +245,7 @@ __device__ __forceinline__ gf_d2 ld_row(GF_GLOBAL const double *p, int r)
     return *(GF_GLOBAL const gf_d2 *)p;
 }
 
-template <int TY, bool FULL>
+template <int TY, int PF, bool FULL>
 __device__ __forceinline__ double j3v2_tile(GF_GLOBAL const double *__restrict__ u, GF_GLOBAL double *__restrict__ w,
                                             int64_t n, int64_t x, int64_t y0, int ny, int64_t z0, int64_t z1,
                                             bool want_red)
@@ -263,7 +263,9 @@ __device__ __forceinline__ double j3v2_tile(GF_GLOBAL const double *__restrict__
     const int64_t SY = n, SZ = n * n;
     const double c6 = 1.0 / 6.0;
     double mx = -INFINITY;
-    gf_d2 pm[TY], pc[TY + 2], pn[TY + 2], pf[TY + 2];
+    // pm: plane z-1 (own rows); pc: plane z (with halo rows); q[k]: plane
+    // z+1+k, k < PF in hand, q[PF] being requested.
+    gf_d2 pm[TY], pc[TY + 2], q[PF + 1][TY + 2];
     const gf_d2 zero2 = {0.0, 0.0};
     GF_GLOBAL const double *col = u + (y0 - 1) * SY + xs;  // row y0-1 of plane 0
 #pragma unroll
@@ -272,15 +274,24 @@ __device__ __forceinline__ double j3v2_tile(GF_GLOBAL const double *__restrict__
 #pragma unroll
     for (int r = 0; r < TY + 2; ++r) {
         pc[r] = (FULL || r < ny + 2) ? ld_row<TY>(col + z0 * SZ + r * SY, r) : zero2;
-        pn[r] = (FULL || r < ny + 2) ? ld_row<TY>(col + (z0 + 1) * SZ + r * SY, r) : zero2;
-        pf[r] = zero2;
+#pragma unroll
+        for (int k = 0; k <= PF; ++k)
+            q[k][r] = zero2;
     }
-    for (int64_t z = z0; z < z1; ++z) {
-        if (z + 2 <= z1) {
+#pragma unroll
+    for (int k = 0; k < PF; ++k)
+        if (z0 + 1 + k <= z1) {
 #pragma unroll
             for (int r = 0; r < TY + 2; ++r)
                 if (FULL || r < ny + 2)
-                    pf[r] = ld_row<TY>(col + (z + 2) * SZ + r * SY, r);
+                    q[k][r] = ld_row<TY>(col + (z0 + 1 + k) * SZ + r * SY, r);
+        }
+    for (int64_t z = z0; z < z1; ++z) {
+        if (z + 1 + PF <= z1) {
+#pragma unroll
+            for (int r = 0; r < TY + 2; ++r)
+                if (FULL || r < ny + 2)
+                    q[PF][r] = ld_row<TY>(col + (z + 1 + PF) * SZ + r * SY, r);
         }
         const int par = (int)(z & 1);
         if (lane == 0) {
@@ -321,9 +332,10 @@ __device__ __forceinline__ double j3v2_tile(GF_GLOBAL const double *__restrict__
                 const double er = wv < nw - 1 ? s_edge[par][wv + 1][r][0] : gr[r];
                 const double xl = lane == 0 ? el : sl;
                 const double xr = lane == kWave - 1 ? er : sr;
+                const gf_d2 zp = q[0][r + 1];
                 gf_d2 v;
-                v.x = (((xl + c.y) + (pc[r].x + pc[r + 2].x)) + (pm[r].x + pn[r + 1].x)) * c6;
-                v.y = (((c.x + xr) + (pc[r].y + pc[r + 2].y)) + (pm[r].y + pn[r + 1].y)) * c6;
+                v.x = (((xl + c.y) + (pc[r].x + pc[r + 2].x)) + (pm[r].x + zp.x)) * c6;
+                v.y = (((c.x + xr) + (pc[r].y + pc[r + 2].y)) + (pm[r].y + zp.y)) * c6;
                 if (in0 && in1) {
                     __builtin_nontemporal_store(v, (GF_GLOBAL gf_d2 *)(out + r * SY));
                 } else if (in0) {
@@ -344,14 +356,16 @@ __device__ __forceinline__ double j3v2_tile(GF_GLOBAL const double *__restrict__
             pm[r] = pc[r + 1];
 #pragma unroll
         for (int r = 0; r < TY + 2; ++r) {
-            pc[r] = pn[r];
-            pn[r] = pf[r];
+            pc[r] = q[0][r];
+#pragma unroll
+            for (int k = 0; k < PF; ++k)
+                q[k][r] = q[k + 1][r];
         }
     }
     return mx;
 }
 
-template <int TY>
+template <int TY, int PF>
 __device__ __forceinline__ double j3v2_item(const double *u_, double *w_, int64_t n, int64_t item, const Tiling &t,
                                             bool want_red)
 {
@@ -366,8 +380,8 @@ __device__ __forceinline__ double j3v2_item(const double *u_, double *w_, int64_
     const int64_t z0 = 1 + zs * t.tile_z;
     const int64_t z1 = (z0 + t.tile_z < n - 1) ? z0 + t.tile_z : n - 1;
     if (ny == TY)
-        return j3v2_tile<TY, true>(gptr(u_), gptr(w_), n, x, y0, ny, z0, z1, want_red);
-    return j3v2_tile<TY, false>(gptr(u_), gptr(w_), n, x, y0, ny, z0, z1, want_red);
+        return j3v2_tile<TY, PF, true>(gptr(u_), gptr(w_), n, x, y0, ny, z0, z1, want_red);
+    return j3v2_tile<TY, PF, false>(gptr(u_), gptr(w_), n, x, y0, ny, z0, z1, want_red);
 }
 
 // 2D 5-point Jacobi: the workgroup owns (row chunk) x (TY rows); each thread
@@ -610,7 +624,7 @@ __device__ __forceinline__ void owner_region(int32_t *owner, int64_t n, int64_t 
 // Executes one work item of a region; returns the thread's reduction value.
 // op[i] is the region's i-th array operand (slot st.arr[i] resolved by the
 // caller); s is the AXPBY coefficient scal[st.sc[1]] * st.c.
-template <unsigned KMASK, int TY>
+template <unsigned KMASK, int TY, int PF>
 __device__ __forceinline__ double region_item(const DStep &st, void *const *op, double s, int64_t n, int64_t item,
                                               const Tiling &t)
 {
@@ -619,7 +633,7 @@ __device__ __forceinline__ double region_item(const DStep &st, void *const *op, 
     case GF_R_JACOBI3D:
         if constexpr ((KMASK >> GF_R_JACOBI3D) & 1u) {
             if ((n & 1) == 0)
-                return j3v2_item<TY>((const double *)op[0], (double *)op[1], n, item, t, red);
+                return j3v2_item<TY, PF>((const double *)op[0], (double *)op[1], n, item, t, red);
             return j3_item<TY>((const double *)op[0], (double *)op[1], n, item, t, red);
         }
         break;
@@ -703,7 +717,7 @@ constexpr int family_max_threads()
     return KMASK == kFamHist ? kMaxWgHist : kMaxWg;
 }
 
-template <unsigned KMASK, int TY>
+template <unsigned KMASK, int TY, int PF>
 __global__ void __launch_bounds__(family_max_threads<KMASK>())
     k_persistent(DProg prog, DInst inst_arg, Tiling t, Scratch scr, RpcRing rpc, BatchTable batch)
 {
@@ -782,7 +796,7 @@ __global__ void __launch_bounds__(family_max_threads<KMASK>())
             } else {
                 const int64_t nitems = region_items_dev(st, n, t);
                 for (int64_t it = worker; it < nitems; it += G) {
-                    double v = region_item<KMASK, TY>(st, op, coef, n, it, t);
+                    double v = region_item<KMASK, TY, PF>(st, op, coef, n, it, t);
                     if (red) {
                         v = block_reduce_rt(st.red_op, v, s_red);
                         if (threadIdx.x == 0)
@@ -847,7 +861,7 @@ __device__ inline void run_glue(const RegionLaunch &rl, const RpcRing &rpc, int3
     }
 }
 
-template <unsigned KMASK, int TY>
+template <unsigned KMASK, int TY, int PF>
 __global__ void __launch_bounds__(family_max_threads<KMASK>()) k_region(RegionLaunch rl, Tiling t, Scratch scr,
                                                                          RpcRing rpc)
 {
@@ -870,7 +884,7 @@ __global__ void __launch_bounds__(family_max_threads<KMASK>()) k_region(RegionLa
         const double coef = (st.kind == GF_R_AXPBY) ? rl.scal[st.sc[1]] * st.c : 0.0;
         const int64_t worker = worker_id(blockIdx.x, G, t.xcd_remap);
         for (int64_t it = worker; it < rl.n_items; it += G) {
-            double v = region_item<KMASK, TY>(st, rl.arr, coef, rl.n, it, t);
+            double v = region_item<KMASK, TY, PF>(st, rl.arr, coef, rl.n, it, t);
             if (red) {
                 v = block_reduce_rt(st.red_op, v, s_red);
                 if (threadIdx.x == 0)
@@ -963,54 +977,85 @@ static unsigned pick_family(unsigned kinds)
 typedef void (*PersistentFn)(DProg, DInst, Tiling, Scratch, RpcRing, BatchTable);
 typedef void (*RegionFn)(RegionLaunch, Tiling, Scratch, RpcRing);
 
+// The prefetch depth is a kernel template parameter so each kernel carries
+// one plane ring; depth 2 exists only for the 3D stencil family at the tile
+// heights the tuner explores.
 template <unsigned F>
-static PersistentFn persistent_for_ty(int ty)
+static PersistentFn persistent_for_ty(int ty, int pf)
 {
     if constexpr (F == kFamVec || F == kFamHist)
-        return ty >= 1 ? k_persistent<F, 1> : nullptr;
+        return ty >= 1 ? k_persistent<F, 1, 1> : nullptr;
+    if constexpr (F == kFamJ3) {
+        if (pf == 2) {
+            switch (ty) {
+            case 1: return k_persistent<F, 1, 2>;
+            case 2: return k_persistent<F, 2, 2>;
+            case 4: return k_persistent<F, 4, 2>;
+            case 8: return k_persistent<F, 8, 2>;
+            default: return nullptr;
+            }
+        }
+    }
+    if (pf != 1)
+        return nullptr;
     switch (ty) {
-    case 1: return k_persistent<F, 1>;
-    case 2: return k_persistent<F, 2>;
-    case 4: return k_persistent<F, 4>;
-    case 8: return k_persistent<F, 8>;
-    case 16: return k_persistent<F, 16>;
+    case 1: return k_persistent<F, 1, 1>;
+    case 2: return k_persistent<F, 2, 1>;
+    case 4: return k_persistent<F, 4, 1>;
+    case 8: return k_persistent<F, 8, 1>;
+    case 16: return k_persistent<F, 16, 1>;
     default: return nullptr;
     }
 }
 
 template <unsigned F>
-static RegionFn region_for_ty(int ty)
+static RegionFn region_for_ty(int ty, int pf)
 {
     if constexpr (F == kFamVec || F == kFamHist)
-        return ty >= 1 ? k_region<F, 1> : nullptr;
+        return ty >= 1 ? k_region<F, 1, 1> : nullptr;
+    if constexpr (F == kFamJ3) {
+        if (pf == 2) {
+            switch (ty) {
+            case 1: return k_region<F, 1, 2>;
+            case 2: return k_region<F, 2, 2>;
+            case 4: return k_region<F, 4, 2>;
+            case 8: return k_region<F, 8, 2>;
+            default: return nullptr;
+            }
+        }
+    }
+    if (pf != 1)
+        return nullptr;
     switch (ty) {
-    case 1: return k_region<F, 1>;
-    case 2: return k_region<F, 2>;
-    case 4: return k_region<F, 4>;
-    case 8: return k_region<F, 8>;
-    case 16: return k_region<F, 16>;
+    case 1: return k_region<F, 1, 1>;
+    case 2: return k_region<F, 2, 1>;
+    case 4: return k_region<F, 4, 1>;
+    case 8: return k_region<F, 8, 1>;
+    case 16: return k_region<F, 16, 1>;
     default: return nullptr;
     }
 }
 
-static PersistentFn persistent_fn(unsigned fam, int ty)
+// Families other than the 3D stencil have no plane ring: their prefetch
+// depth is ignored.
+static PersistentFn persistent_fn(unsigned fam, int ty, int pf)
 {
     switch (fam) {
-    case kFamJ3: return persistent_for_ty<kFamJ3>(ty);
-    case kFamJ2: return persistent_for_ty<kFamJ2>(ty);
-    case kFamVec: return persistent_for_ty<kFamVec>(1);
-    case kFamHist: return persistent_for_ty<kFamHist>(1);
-    default: return persistent_for_ty<kFamAll>(ty);
+    case kFamJ3: return persistent_for_ty<kFamJ3>(ty, pf);
+    case kFamJ2: return persistent_for_ty<kFamJ2>(ty, 1);
+    case kFamVec: return persistent_for_ty<kFamVec>(1, 1);
+    case kFamHist: return persistent_for_ty<kFamHist>(1, 1);
+    default: return persistent_for_ty<kFamAll>(ty, 1);
     }
 }
 
-static RegionFn region_fn(int kind, int ty)
+static RegionFn region_fn(int kind, int ty, int pf)
 {
     switch (kind) {
-    case GF_R_JACOBI3D: return region_for_ty<kFamJ3>(ty);
-    case GF_R_JACOBI2D: return region_for_ty<kFamJ2>(ty);
-    case GF_R_HIST: return region_for_ty<kFamHist>(1);
-    default: return region_for_ty<kFamVec>(1);
+    case GF_R_JACOBI3D: return region_for_ty<kFamJ3>(ty, pf);
+    case GF_R_JACOBI2D: return region_for_ty<kFamJ2>(ty, 1);
+    case GF_R_HIST: return region_for_ty<kFamHist>(1, 1);
+    default: return region_for_ty<kFamVec>(1, 1);
     }
 }
 
@@ -1039,7 +1084,7 @@ hipError_t launch_hist_merge(const RegionLaunch &rl, int64_t rows_used, const Sc
 
 int persistent_capacity(const DProg &prog, const Tiling &t, int num_cu)
 {
-    PersistentFn fn = persistent_fn(pick_family(program_kinds(prog)), t.tile_y);
+    PersistentFn fn = persistent_fn(pick_family(program_kinds(prog)), t.tile_y, t.prefetch);
     if (!fn)
         return 0;
     int per_cu = 0;
@@ -1052,7 +1097,7 @@ int persistent_capacity(const DProg &prog, const Tiling &t, int num_cu)
 hipError_t launch_persistent(const DProg &prog, const DInst &inst, const Tiling &t, int num_wg, const Scratch &scr,
                              const RpcRing &rpc, hipStream_t s, const BatchTable *batch)
 {
-    PersistentFn fn = persistent_fn(pick_family(program_kinds(prog)), t.tile_y);
+    PersistentFn fn = persistent_fn(pick_family(program_kinds(prog)), t.tile_y, t.prefetch);
     if (!fn)
         return hipErrorInvalidValue;
     DProg p = prog;
@@ -1070,7 +1115,7 @@ hipError_t launch_persistent(const DProg &prog, const DInst &inst, const Tiling 
 hipError_t launch_region(const RegionLaunch &rl, const Tiling &t, int num_wg, const Scratch &scr,
                          const RpcRing &rpc, hipStream_t s)
 {
-    RegionFn fn = region_fn(rl.step.kind, t.tile_y);
+    RegionFn fn = region_fn(rl.step.kind, t.tile_y, t.prefetch);
     if (!fn)
         return hipErrorInvalidValue;
     hipLaunchKernelGGL(fn, dim3(num_wg), dim3(t.wg_size), 0, s, rl, t, scr, rpc);

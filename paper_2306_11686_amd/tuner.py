@@ -14,7 +14,7 @@ import os
 from .binding import GF_EXEC_PERSISTENT, Launch
 
 DEFAULT_DB = os.path.join(os.path.dirname(os.path.abspath(__file__)), "tuning_db.json")
-_FIELDS = ("wg_size", "num_wg", "tile_y", "tile_z", "items", "xcd_remap")
+_FIELDS = ("wg_size", "num_wg", "tile_y", "tile_z", "items", "xcd_remap", "prefetch")
 
 
 def launch_to_dict(l: Launch) -> dict:
