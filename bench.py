@@ -132,6 +132,7 @@ def main():
     ap.add_argument("--wg-size", type=int, default=0)
     ap.add_argument("--num-wg", type=int, default=0)
     ap.add_argument("--xcd-remap", type=int, default=-1)
+    ap.add_argument("--prefetch", type=int, default=0)
     args = ap.parse_args()
 
     if args.gpus != 1:
@@ -155,6 +156,7 @@ def main():
         tile_y=args.tile_y or tuned.get("tile_y", 0),
         tile_z=args.tile_z or tuned.get("tile_z", 0),
         xcd_remap=args.xcd_remap if args.xcd_remap >= 0 else tuned.get("xcd_remap", 1),
+        prefetch=args.prefetch or tuned.get("prefetch", 0),
     )
 
     log(f"[bench] generating {n}^3 grid")

@@ -183,6 +183,8 @@ typedef struct {
     int32_t num_wg;        /* workgroups used (largest launch) */
     int32_t wg_size;
     int32_t rpc_posted;    /* filled by gf_sync: RPC requests serviced so far */
+    int32_t candidate;     /* gf_region_run with launch NULL: the launch shape the
+                              installed predictor chose (0..31), -1 if none */
 } gf_run_stats;
 
 typedef struct {
@@ -208,7 +210,9 @@ const char *gf_last_error(const gf_ctx *ctx);
  * hip_stream in execution mode `mode`. With n_inst > 1 the instances run
  * concurrently in one persistent launch, each on its own group of
  * workgroups with group barriers (GF_EXEC_PERSISTENT), or as per-instance
- * launches (per-region modes). launch may be NULL (tuning DB / defaults).
+ * launches (per-region modes). launch may be NULL: with one instance and an
+ * installed predictor the predicted launch shape is used (gf_predict_launch;
+ * for SpMV programs that call waits for hip_stream), otherwise the defaults.
  * stats (nullable) receives counts. Asynchronous: results are valid after
  * the stream completes; call gf_sync to surface device errors. */
 gf_status gf_region_run(gf_ctx *ctx, const gf_program *prog, const gf_instance *inst,
@@ -345,6 +349,30 @@ gf_status gf_predictor_set(gf_ctx *ctx, const float *h_params, const float *h_me
  * predictor is installed or any standardised feature lies outside [-4, 4]
  * (the caller then tunes). */
 int32_t gf_predict(gf_ctx *ctx, const double *h_features, const uint8_t *valid, float *scores);
+
+/* The predictor's raw features of a program: those of its dominant region
+ * (largest trip count x bytes per iteration) bound by inst[0], with the
+ * instance count n_inst. Per region kind (trip count; bytes, flops per
+ * iteration; stencil radius; reduction targets; nonzeros per row; element
+ * size): 2D/3D stencil ((n-2)^d; 16, 2d+3; 1; 1 with a reduction clause
+ * else 0; 0; 8), SpMV (rows; 12 nz + 20, 2 nz; 0; 0; nz = rowptr[n] / n; 8),
+ * dot (n; 16, 2; 0; 1; 0; 8), axpby (n; 24, 2; 0; 0; 0; 8), histogram
+ * (n; 4, 0; 0; bins, the array section reduced into; 0; 4). For SpMV the
+ * row pointer's last entry is read from the device on hip_stream (this call
+ * then waits for that stream). out receives GF_MLP_IN doubles. */
+gf_status gf_nest_features(gf_ctx *ctx, const gf_program *prog, const gf_instance *inst, int32_t n_inst,
+                           double *out, void *hip_stream);
+
+/* Launch-time choice: features (gf_nest_features), the candidates that can
+ * run prog on inst in `mode` (tiling, instance and co-residency checks), and
+ * gf_predict over them. On success writes the decoded launch to *out and
+ * returns its index; returns -1 when no predictor is installed, the program
+ * lies outside the training distribution or no candidate can run (the caller
+ * then tunes or uses the defaults); argument errors also return a negative
+ * status. gf_region_run does this by itself for launch == NULL and one
+ * instance when a predictor is installed. */
+int32_t gf_predict_launch(gf_ctx *ctx, const gf_program *prog, const gf_instance *inst, int32_t n_inst,
+                          int32_t mode, gf_launch *out, void *hip_stream);
 
 #ifdef __cplusplus
 }

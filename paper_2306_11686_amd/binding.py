@@ -95,7 +95,8 @@ class Launch(ctypes.Structure):
 
 class RunStats(ctypes.Structure):
     _fields_ = [("regions", ctypes.c_int32), ("launches", ctypes.c_int32), ("barriers", ctypes.c_int32),
-                ("num_wg", ctypes.c_int32), ("wg_size", ctypes.c_int32), ("rpc_posted", ctypes.c_int32)]
+                ("num_wg", ctypes.c_int32), ("wg_size", ctypes.c_int32), ("rpc_posted", ctypes.c_int32),
+                ("candidate", ctypes.c_int32)]
 
     def as_dict(self):
         return {f: getattr(self, f) for f, _ in self._fields_}
@@ -159,6 +160,10 @@ _SIGS = {
                                         ctypes.POINTER(ctypes.c_float), ctypes.POINTER(ctypes.c_float)]),
     "gf_predict": (ctypes.c_int32, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_uint8),
                                     ctypes.POINTER(ctypes.c_float)]),
+    "gf_nest_features": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(Program), ctypes.POINTER(Instance),
+                                        ctypes.c_int32, ctypes.POINTER(ctypes.c_double), ctypes.c_void_p]),
+    "gf_predict_launch": (ctypes.c_int32, [ctypes.c_void_p, ctypes.POINTER(Program), ctypes.POINTER(Instance),
+                                           ctypes.c_int32, ctypes.c_int32, ctypes.POINTER(Launch), ctypes.c_void_p]),
 }
 
 GF_MLP_IN, GF_MLP_HIDDEN, GF_MLP_OUT = 8, 64, 32
@@ -339,6 +344,28 @@ class Context:
         if r < -1:
             self._check(r)
         return (r, [float(v) for v in sc]) if want_scores else r
+
+    def nest_features(self, program: Program, instances, stream=None):
+        """The predictor's raw features of `program` bound to `instances`."""
+        if isinstance(instances, Instance):
+            instances = [instances]
+        arr = (Instance * len(instances))(*instances)
+        out = (ctypes.c_double * GF_MLP_IN)()
+        self._check(self.lib.gf_nest_features(self.h, ctypes.byref(program), arr, len(instances), out,
+                                              _stream_handle(stream)))
+        return [float(v) for v in out]
+
+    def predict_launch(self, program: Program, instances, mode: int = GF_EXEC_PERSISTENT, stream=None):
+        """(candidate index, Launch) chosen by the installed predictor, or (-1, None)."""
+        if isinstance(instances, Instance):
+            instances = [instances]
+        arr = (Instance * len(instances))(*instances)
+        out = Launch()
+        r = self.lib.gf_predict_launch(self.h, ctypes.byref(program), arr, len(instances), mode, ctypes.byref(out),
+                                       _stream_handle(stream))
+        if r < -1:
+            self._check(r)
+        return (r, out) if r >= 0 else (-1, None)
 
     def copy(self, dst, src, nbytes: int, num_wg: int = 0, stream=None):
         self._check(self.lib.gf_copy(self.h, _ptr(dst), _ptr(src), nbytes, num_wg, _stream_handle(stream)))

@@ -918,6 +918,22 @@ gf_status run_batched(gf_ctx *ctx, const DProg &p, const gf_instance *inst, int 
     return GF_OK;
 }
 
+namespace {
+int32_t predict_launch(gf_ctx *ctx, const DProg &p, const gf_instance *inst, int n_inst, int mode, hipStream_t s,
+                       gf_launch *out);
+
+// Writes the predictor's choice into the caller's stats when the run returns.
+struct CandidateNote {
+    gf_run_stats *stats;
+    int32_t cand;
+    ~CandidateNote()
+    {
+        if (stats)
+            stats->candidate = cand;
+    }
+};
+}  // namespace
+
 extern "C" {
 
 int32_t gf_persistent_capacity(gf_ctx *ctx, const gf_program *prog, int32_t wg_size)
@@ -949,14 +965,25 @@ gf_status gf_region_run(gf_ctx *ctx, const gf_program *prog, const gf_instance *
     gf_status st = build_program(ctx, prog, &p);
     if (st != GF_OK)
         return st;
+    hipSetDevice(ctx->device);
+    hipStream_t stream = (hipStream_t)hip_stream;
+    gf_launch predicted;
+    CandidateNote note{stats, -1};
+    if (!launch && n_inst == 1 && !ctx->pred_params.empty()) {
+        const int32_t k = predict_launch(ctx, p, inst, n_inst, mode, stream, &predicted);
+        if (k < -1)
+            return (gf_status)k;
+        if (k >= 0) {
+            note.cand = k;
+            launch = &predicted;
+        }
+    }
     Tiling t = choose_tiling(p, launch);
     if ((st = check_tiling(ctx, p, t)) != GF_OK)
         return st;
     for (int i = 0; i < n_inst; ++i)
         if ((st = check_instance(ctx, p, inst[i], t, i)) != GF_OK)
             return st;
-    hipSetDevice(ctx->device);
-    hipStream_t stream = (hipStream_t)hip_stream;
     if (stats)
         std::memset(stats, 0, sizeof *stats);
 
@@ -1171,9 +1198,151 @@ gf_launch decode_candidate(const DProg &p, const gf_instance &in, int c, int num
     return l;
 }
 
+// Raw predictor features of the program's dominant region (largest trip
+// count x bytes per iteration); see gf_nest_features.
+gf_status nest_features(gf_ctx *ctx, const DProg &p, const gf_instance &in, int n_inst, hipStream_t s, double *f)
+{
+    double best = -1.0;
+    for (int k = 0; k < GF_MLP_IN; ++k)
+        f[k] = 0.0;
+    for (int i = 0; i < p.n_steps; ++i) {
+        const DStep &st = p.steps[i];
+        if (!is_region(st.kind))
+            continue;
+        const int64_t n = in.ip[st.np];
+        const double m = (double)std::max<int64_t>(n - 2, 0);
+        const double red = st.red_op != GF_OP_NONE ? 1.0 : 0.0;
+        double g[GF_MLP_IN] = {(double)n, 0.0, 0.0, 0.0, 0.0, 0.0, (double)n_inst, 8.0};
+        switch (st.kind) {
+        case GF_R_JACOBI2D:
+            g[0] = m * m, g[1] = 16.0, g[2] = 7.0, g[3] = 1.0, g[4] = red;
+            break;
+        case GF_R_JACOBI3D:
+            g[0] = m * m * m, g[1] = 16.0, g[2] = 9.0, g[3] = 1.0, g[4] = red;
+            break;
+        case GF_R_SPMV: {
+            int32_t nnz = 0;
+            if (n > 0) {
+                const int32_t *rp = (const int32_t *)in.arr[st.arr[0]];
+                hipError_t e = hipMemcpyAsync(&nnz, rp + n, sizeof nnz, hipMemcpyDeviceToHost, s);
+                if (e == hipSuccess)
+                    e = hipStreamSynchronize(s);
+                if (e != hipSuccess)
+                    return hipfail(ctx, e, "reading the row pointer");
+            }
+            const double nz = n > 0 ? (double)nnz / (double)n : 0.0;
+            g[1] = 12.0 * nz + 20.0, g[2] = 2.0 * nz, g[5] = nz;
+            break;
+        }
+        case GF_R_DOT:
+            g[1] = 16.0, g[2] = 2.0, g[4] = 1.0;
+            break;
+        case GF_R_AXPBY:
+            g[1] = 24.0, g[2] = 2.0;
+            break;
+        case GF_R_HIST:
+            g[1] = 4.0, g[4] = (double)st.mask + 1.0, g[7] = 4.0;
+            break;
+        default:  // GF_R_OWNER
+            g[1] = 4.0, g[7] = 4.0;
+            break;
+        }
+        const double w = g[0] * g[1];
+        if (w > best) {
+            best = w;
+            std::memcpy(f, g, sizeof g);
+        }
+    }
+    return GF_OK;
+}
+
+// Whether `l` passes every check gf_region_run makes before enqueueing
+// (tiling, instances, co-residency of the persistent grid). Leaves the
+// context's error message untouched.
+bool launch_runnable(gf_ctx *ctx, const DProg &p, const gf_instance *inst, int n_inst, int mode, const gf_launch &l)
+{
+    const std::string saved = ctx->err;
+    bool ok = true;
+    const Tiling t = choose_tiling(p, &l);
+    if (check_tiling(ctx, p, t) != GF_OK)
+        ok = false;
+    for (int i = 0; ok && i < n_inst; ++i)
+        ok = check_instance(ctx, p, inst[i], t, i) == GF_OK;
+    if (ok && mode == GF_EXEC_PERSISTENT) {
+        const int cap = std::min(4096, persistent_capacity(p, t, ctx->num_cu));
+        ok = cap > 0 && l.num_wg <= cap;
+        if (ok && n_inst > 1)
+            ok = !program_is_hist_family(p) && n_inst <= (l.num_wg > 0 ? l.num_wg : cap);
+        if (ok && program_is_hist_family(p)) {
+            uint32_t mask = 0;
+            for (int k = 0; k < p.n_steps; ++k)
+                if (p.steps[k].kind == GF_R_HIST)
+                    mask = std::max(mask, p.steps[k].mask);
+            ok = hist_grid(l.num_wg > 0 ? l.num_wg : cap, mask) <= cap;
+        }
+    }
+    ctx->err = saved;
+    return ok;
+}
+
+int32_t predict_launch(gf_ctx *ctx, const DProg &p, const gf_instance *inst, int n_inst, int mode, hipStream_t s,
+                       gf_launch *out)
+{
+    double f[GF_MLP_IN];
+    const gf_status st = nest_features(ctx, p, inst[0], n_inst, s, f);
+    if (st != GF_OK)
+        return st;
+    uint8_t valid[GF_NUM_CANDIDATES];
+    gf_launch cand[GF_NUM_CANDIDATES];
+    bool any = false;
+    for (int c = 0; c < GF_NUM_CANDIDATES; ++c) {
+        cand[c] = decode_candidate(p, inst[0], c, ctx->num_cu);
+        valid[c] = launch_runnable(ctx, p, inst, n_inst, mode, cand[c]) ? 1 : 0;
+        any = any || valid[c];
+    }
+    if (!any)
+        return -1;
+    const int32_t k = gf_predict(ctx, f, valid, nullptr);
+    if (k >= 0)
+        *out = cand[k];
+    return k;
+}
+
 }  // namespace
 
 extern "C" {
+
+gf_status gf_nest_features(gf_ctx *ctx, const gf_program *prog, const gf_instance *inst, int32_t n_inst,
+                           double *out, void *hip_stream)
+{
+    if (!ctx)
+        return GF_EINVAL;
+    if (!inst || !out || n_inst < 1)
+        return fail(ctx, GF_EINVAL, "null instance or output, or n_inst < 1");
+    DProg p;
+    gf_status st = build_program(ctx, prog, &p);
+    if (st != GF_OK)
+        return st;
+    hipSetDevice(ctx->device);
+    return nest_features(ctx, p, inst[0], n_inst, (hipStream_t)hip_stream, out);
+}
+
+int32_t gf_predict_launch(gf_ctx *ctx, const gf_program *prog, const gf_instance *inst, int32_t n_inst,
+                          int32_t mode, gf_launch *out, void *hip_stream)
+{
+    if (!ctx)
+        return GF_EINVAL;
+    if (!inst || !out || n_inst < 1 || n_inst > GF_MAX_INSTANCES)
+        return fail(ctx, GF_EINVAL, "null instance or output, or n_inst out of range");
+    DProg p;
+    gf_status st = build_program(ctx, prog, &p);
+    if (st != GF_OK)
+        return st;
+    if (ctx->pred_params.empty())
+        return -1;
+    hipSetDevice(ctx->device);
+    return predict_launch(ctx, p, inst, n_inst, mode, (hipStream_t)hip_stream, out);
+}
 
 int32_t gf_tune_pick(const float *ms, int32_t n)
 {

@@ -3,10 +3,12 @@
 A loop nest is one region of the legacy-loop families (2D/3D Jacobi sweep,
 CSR SpMV, dot, axpby, histogram) at a sampled size. Its label is the
 autotuner's measurement of all GF_NUM_CANDIDATES launch shapes (gf_tune on
-real runs); the network regresses t_c = log(time_c / min time) on eight loop
-features and is trained on the device by the library's own forward, backward
-and Adam kernels. At launch time the argmin over the predicted t_c is used;
-nests outside the training distribution defer to the autotuner.
+real runs); the network regresses t_c = log(time_c / min time) on the eight
+loop features the library computes (gf_nest_features) and is trained on the
+device by the library's own forward, backward and Adam kernels. At launch
+time (gf_region_run without a launch, or gf_predict_launch) the argmin over
+the predicted t_c of the runnable shapes is used; nests outside the training
+distribution defer to the autotuner.
 
 Timing inputs are device-random (their values do not change the timings);
 the sizes and structure follow the workload families.
@@ -48,28 +50,6 @@ def sample_nests(count: int, seed: int = 1, first: int = 0):
                     "zipf": bool(u[3] < 0.5)}
         specs.append(spec)
     return specs
-
-
-def features(spec) -> list:
-    """Raw features: trip count, bytes/iter, flops/iter, stencil radius,
-    reductions, nonzeros/row, instance count, element size."""
-    k = spec["kind"]
-    if k == "j2":
-        n = spec["n"]
-        return [(n - 2) ** 2, 16, 7, 1, 1, 0, 1, 8]
-    if k == "j3":
-        n = spec["n"]
-        return [(n - 2) ** 3, 16, 9, 1, 1, 0, 1, 8]
-    m = spec.get("m", 0)
-    if k == "spmv":
-        rows = m ** 3
-        nnzr = (3 * m - 2) ** 3 / rows
-        return [rows, 12 * nnzr + 20, 2 * nnzr, 0, 0, nnzr, 1, 8]
-    if k == "dot":
-        return [m ** 3, 16, 2, 0, 1, 0, 1, 8]
-    if k == "axpby":
-        return [m ** 3, 24, 2, 0, 0, 0, 1, 8]
-    return [spec["keys"], 4, 0, 0, 1, 0, 1, 4]
 
 
 _CSR_CACHE = {}
@@ -132,7 +112,7 @@ def collect(ctx, specs, reps: int = 3, log=None):
     for i, spec in enumerate(specs):
         prog, inst, keep = build_nest(spec)
         t, _ = ctx.tune(prog, inst, mode=GF_EXEC_PERSISTENT, reps=reps)
-        feats[i] = features(spec)
+        feats[i] = ctx.nest_features(prog, inst)
         ms[i] = t
         del keep
         if log and (i + 1) % 100 == 0:

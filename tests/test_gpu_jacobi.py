@@ -52,6 +52,22 @@ def test_jacobi3d_tilings(gfx, oracle_lib, ty, tz, wg, remap, mode, n):
     assert np.array_equal(r, r_ref)
 
 
+@pytest.mark.parametrize("ty,tz", [(1, 3), (2, 9), (4, 1), (8, 40)])
+@pytest.mark.parametrize("mode", ["persistent", "per_region"])
+@pytest.mark.parametrize("n", [41, 64])
+def test_jacobi3d_prefetch2(gfx, oracle_lib, ty, tz, mode, n):
+    """Two planes requested ahead: segments shorter than, equal to and longer
+    than the prefetch depth."""
+    import paper_2306_11686_amd as gf
+    print(f"jacobi3d prefetch2 n={n} ty={ty} tz={tz} mode={mode}", flush=True)
+    u0 = gi.grid3d(n, seed=4)
+    g_ref, r_ref = oracle_lib.jacobi3d(u0, 3)
+    launch = gf.Launch.make(wg_size=64 if n == 41 else 256, tile_y=ty, tile_z=tz, prefetch=2)
+    g, r, _ = run_jacobi3d(gfx, u0, 3, _mode(gf, mode), launch=launch)
+    assert np.array_equal(g, g_ref)
+    assert np.array_equal(r, r_ref)
+
+
 def test_jacobi3d_persistent_small_grid_count(gfx, oracle_lib):
     import paper_2306_11686_amd as gf
     u0 = gi.grid3d(30, seed=3)
@@ -178,7 +194,7 @@ def _bench_launch(gf):
     tuned = bench.load_tuned("jacobi3d_512") or {}
     return gf.Launch.make(wg_size=tuned.get("wg_size", 0), num_wg=tuned.get("num_wg", 0),
                           tile_y=tuned.get("tile_y", 0), tile_z=tuned.get("tile_z", 0),
-                          xcd_remap=tuned.get("xcd_remap", 1))
+                          xcd_remap=tuned.get("xcd_remap", 1), prefetch=tuned.get("prefetch", 0))
 
 
 @pytest.mark.parametrize("mode", ["persistent", "per_region"])

@@ -45,3 +45,85 @@ def test_tune_picks_fastest_and_result_is_correct(gfx, oracle_lib):
     g_ref, r_ref = oracle_lib.jacobi3d(u0, 4)
     g, r, _ = run_jacobi3d(gfx, u0, 4, gf.GF_EXEC_PERSISTENT, launch=cands[best])
     assert np.array_equal(g, g_ref) and np.array_equal(r, r_ref)
+
+
+def test_nest_features_per_region_kind(gfx):
+    """The library's predictor features follow the documented per-kind
+    formulas (SpMV's nonzeros per row read from the row pointer)."""
+    import torch
+    import paper_2306_11686_amd as gf
+    from paper_2306_11686_amd import programs
+    sc = scalars()
+    u = dev(np.zeros(66 ** 3))
+    i3 = gf.Instance.make({0: u, 1: u, 2: sc}, sc, ip=(66,))
+    assert gfx.nest_features(programs.jacobi3d(3), i3) == [64.0 ** 3, 16, 9, 1, 1, 0, 1, 8]
+    i2 = gf.Instance.make({0: u, 1: u, 2: sc}, sc, ip=(100,))
+    assert gfx.nest_features(programs.jacobi2d(3), i2) == [98.0 ** 2, 16, 7, 1, 1, 0, 1, 8]
+    m = 8
+    rp, col, val = gi.poisson27_csr(m)
+    N = m ** 3
+    nz = (3 * m - 2) ** 3 / N
+    t = {programs.CG_ROWPTR: dev(rp), programs.CG_COL: dev(col), programs.CG_VAL: dev(val)}
+    for slot in (programs.CG_X, programs.CG_R, programs.CG_P, programs.CG_Q):
+        t[slot] = torch.zeros(N, dtype=torch.float64, device="cuda")
+    t[programs.CG_RHO] = torch.zeros(4, dtype=torch.float64, device="cuda")
+    icg = gf.Instance.make(t, sc, ip=(N,))
+    f = gfx.nest_features(programs.cg(4), icg)   # dominant region: the SpMV
+    assert f == pytest.approx([N, 12 * nz + 20, 2 * nz, 0, 0, nz, 1, 8], rel=1e-12)
+    keys = torch.zeros(1000, dtype=torch.int32, device="cuda")
+    bins = torch.zeros(4096, dtype=torch.int32, device="cuda")
+    ih = gf.Instance.make({0: keys, 1: bins}, sc, ip=(1000,))
+    assert gfx.nest_features(programs.histogram(4096), ih) == [1000, 4, 0, 0, 4096, 0, 1, 4]
+
+
+def _constant_predictor(ctx, best, std=1e3):
+    """A network whose output is the constant b3 (all weights zero), minimal
+    at candidate `best`; std large keeps every feature in distribution."""
+    import paper_2306_11686_amd as gf
+    p = np.zeros(gf.GF_MLP_NPARAMS, np.float32)
+    b3 = np.linspace(1.0, 2.0, gf.GF_MLP_OUT).astype(np.float32)
+    b3[best] = 0.0
+    p[-gf.GF_MLP_OUT:] = b3
+    ctx.predictor_set(p, np.zeros(gf.GF_MLP_IN), np.full(gf.GF_MLP_IN, std))
+
+
+def test_region_run_without_launch_uses_installed_predictor(oracle_lib):
+    import paper_2306_11686_amd as gf
+    from paper_2306_11686_amd import programs
+    ctx = gf.Context(0)
+    try:
+        n, sweeps = 66, 3
+        u0 = gi.grid3d(n, seed=5)
+        prog = programs.jacobi3d(sweeps)
+        g_ref, r_ref = oracle_lib.jacobi3d(u0, sweeps)
+        best = 5 + 16                      # tile_y 2, tile_z ceil(64/3), prefetch 2
+        _constant_predictor(ctx, best)
+        u = dev(u0)
+        w = u.clone()
+        import torch
+        res = torch.zeros(sweeps, dtype=torch.float64, device="cuda")
+        sc = scalars()
+        inst = gf.Instance.make({0: u, 1: w, 2: res}, sc, ip=(n,))
+        k, launch = ctx.predict_launch(prog, inst)
+        cands = ctx.tune_candidates(prog, inst)
+        assert k == best and bytes(launch) == bytes(cands[best])
+        for mode in (gf.GF_EXEC_PERSISTENT, gf.GF_EXEC_PER_REGION):
+            u.copy_(dev(u0))
+            w.copy_(u)
+            st = ctx.run(prog, inst, mode=mode)
+            ctx.sync()
+            assert st["candidate"] == best
+            out = (u if sweeps % 2 == 0 else w).cpu().numpy().reshape(g_ref.shape)
+            assert np.array_equal(out, g_ref) and np.array_equal(res.cpu().numpy(), r_ref)
+        # an explicit launch bypasses the predictor
+        st = ctx.run(prog, inst, launch=gf.Launch.make(tile_y=4))
+        ctx.sync()
+        assert st["candidate"] == -1
+        # out of distribution: defaults, no candidate
+        _constant_predictor(ctx, best, std=1e-3)
+        assert ctx.predict_launch(prog, inst) == (-1, None)
+        st = ctx.run(prog, inst)
+        ctx.sync()
+        assert st["candidate"] == -1
+    finally:
+        ctx.close()
