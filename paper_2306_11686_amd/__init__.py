@@ -13,7 +13,8 @@ from .binding import (  # noqa: F401
     GF_OP_SUM, GF_OP_MAX, GF_OP_NONE, GF_F64, GF_U32, GF_U64, GF_I64,
     GF_R_JACOBI2D, GF_R_JACOBI3D, GF_R_SPMV, GF_R_DOT, GF_R_AXPBY, GF_R_HIST, GF_R_OWNER,
     GF_S_SET, GF_S_COPY, GF_S_DIV, GF_S_SQRT, GF_S_SWAP, GF_S_RECORD, GF_S_PRINTF,
-    GF_STEP_BLOCKING, GF_NUM_CANDIDATES, GfError, Context, Step, Launch, Program, Instance, lib_path, load_library,
+    GF_STEP_BLOCKING, GF_NUM_CANDIDATES, GF_MLP_IN, GF_MLP_HIDDEN, GF_MLP_OUT, GF_MLP_NPARAMS,
+    GfError, Context, Step, Launch, Program, Instance, lib_path, load_library,
     exported_symbols, tune_pick,
 )
 from . import programs  # noqa: F401

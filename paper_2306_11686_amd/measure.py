@@ -158,11 +158,16 @@ def measure_sync(ctx, gf, programs, tuner, torch, gi, reps):
     inst = gf.Instance.make({0: u, 1: w, 2: r}, sc, ip=(4,))
     prog = programs.jacobi3d(regions)
     out = {"config": "sync_cost_trivial_region", "regions": regions}
-    for nwg in (1, 64, 256, 512):
-        ms = _time(ctx, torch, lambda: ctx.run(prog, inst, mode=1, launch=gf.Launch.make(num_wg=nwg)), reps)
+    launch = gf.Launch.make(tile_y=1)
+    for nwg in (1, 64, 256, 512, 768):
+        try:
+            ms = _time(ctx, torch, lambda: ctx.run(prog, inst, mode=1, launch=gf.Launch.make(tile_y=1, num_wg=nwg)),
+                       reps)
+        except gf.GfError:          # beyond the co-resident capacity
+            continue
         out[f"persistent_wg{nwg}_us_per_region"] = round(ms * 1e3 / regions, 3)
     for name, mode in MODES[1:]:
-        ms = _time(ctx, torch, lambda: ctx.run(prog, inst, mode=mode), reps)
+        ms = _time(ctx, torch, lambda: ctx.run(prog, inst, mode=mode, launch=launch), reps)
         out[f"{name}_us_per_region"] = round(ms * 1e3 / regions, 3)
     return out
 
