@@ -16,6 +16,8 @@ import sys
 
 import numpy as np
 
+from . import workloads
+
 MODES = (("persistent", 1), ("per_region", 0), ("per_region_graph", 2))
 
 
@@ -44,20 +46,14 @@ def _launch(tuner, key):
     return tuner.lookup(key)
 
 
-def measure_2d(ctx, gf, programs, tuner, torch, gi, reps):
+def measure_2d(ctx, gf, programs, tuner, torch, reps):
     n, sweeps = 256, 100
-    fmt = ctx.register_format(programs.JACOBI2D_FORMAT, "id")
-    u = torch.from_numpy(gi.grid2d(n)).cuda()
-    w = u.clone()
-    res = torch.zeros(sweeps, dtype=torch.float64, device="cuda")
-    sc = torch.zeros(16, dtype=torch.float64, device="cuda")
-    inst = gf.Instance.make({0: u, 1: w, 2: res}, sc, ip=(n,))
     bpsweep = 8 * (n * n - 4) + 8 * (n - 2) ** 2
     out = {"config": "jacobi2d_5pt_256^2_f64_100sweeps_l2res_printf10", "alg_bytes_per_sweep": bpsweep}
     launch = _launch(tuner, "jacobi2d_256")
-    for name, mode in MODES:
-        for pf in (True, False):
-            prog = programs.jacobi2d(sweeps, fmt_id=fmt if pf else -1, print_every=10)
+    for pf in (True, False):
+        prog, inst, keep, _ = workloads.jacobi2d(ctx, n, sweeps, printf=pf)
+        for name, mode in MODES:
             ms = _time(ctx, torch, lambda: ctx.run(prog, inst, mode=mode, launch=launch), reps)
             ctx.take_output()
             key = name + ("" if pf else "_no_printf")
@@ -70,75 +66,46 @@ def measure_2d(ctx, gf, programs, tuner, torch, gi, reps):
     return out
 
 
-def measure_cg(ctx, gf, programs, tuner, torch, gi, reps):
+def measure_cg(ctx, gf, programs, tuner, torch, reps):
     m, iters = 128, 500
+    prog, inst, keep, reset = workloads.cg(m, iters)
     N = m ** 3
-    rowptr, col, val = gi.poisson27_csr(m)
-    b = gi.cg_rhs(N, seed=1)
-    t = {programs.CG_ROWPTR: torch.from_numpy(rowptr).cuda(), programs.CG_COL: torch.from_numpy(col).cuda(),
-         programs.CG_VAL: torch.from_numpy(val).cuda(), programs.CG_X: torch.zeros(N, dtype=torch.float64,
-                                                                                    device="cuda"),
-         programs.CG_R: torch.from_numpy(b).cuda(), programs.CG_P: torch.from_numpy(b).cuda(),
-         programs.CG_Q: torch.zeros(N, dtype=torch.float64, device="cuda"),
-         programs.CG_RHO: torch.zeros(iters, dtype=torch.float64, device="cuda")}
-    sc = torch.zeros(16, dtype=torch.float64, device="cuda")
-    inst = gf.Instance.make(t, sc, ip=(N,))
-    nnz = int(col.size)
+    nnz = (3 * m - 2) ** 3
     spmv_b = 12 * nnz + 4 * (N + 1) + 8 * N + 8 * N
     it_b = spmv_b + 2 * 16 * N + 3 * 24 * N
     out = {"config": f"cg_27pt_{m}^3_f64_{iters}iters", "rows": N, "nnz": nnz, "alg_bytes_per_iteration": it_b}
     launch = _launch(tuner, "cg_128")
-
-    def reset():
-        t[programs.CG_X].zero_()
-        t[programs.CG_R].copy_(torch.from_numpy(b).cuda())
-        t[programs.CG_P].copy_(t[programs.CG_R])
-
     for name, mode in MODES:
         reset()
-        ms = _time(ctx, torch, lambda: ctx.run(programs.cg(iters), inst, mode=mode, launch=launch), reps)
+        ms = _time(ctx, torch, lambda: ctx.run(prog, inst, mode=mode, launch=launch), reps)
         out[name] = {"ms_per_run": round(ms, 3), "GBps": round(iters * it_b / (ms * 1e-3) / 1e9, 1),
                      "regions_per_s": round(6 * iters / (ms * 1e-3), 1)}
     return out
 
 
-def measure_hist(ctx, gf, programs, tuner, torch, gi, reps):
+def measure_hist(ctx, gf, programs, tuner, torch, reps):
     n = 1 << 28
     out = {"config": "hist_u32_2^28_keys_65536_bins", "alg_bytes": 4 * n + 2 * 4 * 65536}
     launch = _launch(tuner, "hist_2^28")
     for dist in ("uniform", "zipf"):
-        keys = gi.hist_keys_uniform(n, seed=1) if dist == "uniform" else gi.hist_keys_zipf(n, seed=1)
-        tk = torch.from_numpy(keys).cuda()
-        del keys
-        bins = torch.zeros(65536, dtype=torch.int32, device="cuda")
-        sc = torch.zeros(16, dtype=torch.float64, device="cuda")
-        inst = gf.Instance.make({0: tk, 1: bins}, sc, ip=(n,))
+        prog, inst, keep, _ = workloads.histogram(n, 65536, dist)
         for name, mode in MODES[:2]:
-            ms = _time(ctx, torch, lambda: ctx.run(programs.histogram(65536), inst, mode=mode, launch=launch), reps)
+            ms = _time(ctx, torch, lambda: ctx.run(prog, inst, mode=mode, launch=launch), reps)
             out[f"{dist}_{name}"] = {"us_per_run": round(ms * 1e3, 1),
                                      "GBps": round(out["alg_bytes"] / (ms * 1e-3) / 1e9, 1)}
-        del tk
+        del keep, inst
         torch.cuda.empty_cache()
     return out
 
 
-def measure_batched(ctx, gf, programs, tuner, torch, gi, reps):
-    sides = gi.batched_sides(256, seed=1)
+def measure_batched(ctx, gf, programs, tuner, torch, reps):
     sweeps = 50
-    insts, keep = [], []
-    for i, n in enumerate(sides):
-        n = int(n)
-        u = torch.from_numpy(gi.batched_grid(i, n, 1)).cuda()
-        w = u.clone()
-        r = torch.zeros(sweeps, dtype=torch.float64, device="cuda")
-        sc = torch.zeros(16, dtype=torch.float64, device="cuda")
-        keep += [u, w, r, sc]
-        insts.append(gf.Instance.make({0: u, 1: w, 2: r}, sc, ip=(n,)))
-    bytes_per_sweepset = int(sum(8 * (int(n) ** 2 - 4) + 8 * (int(n) - 2) ** 2 for n in sides))
-    out = {"config": "batched_256x_jacobi2d_sides_64_2048_50sweeps", "sum_n2": int((sides.astype(np.int64) ** 2).sum()),
+    prog, insts, keep, _ = workloads.batched(256, sweeps)
+    sides = [int(i.ip[0]) for i in insts]
+    bytes_per_sweepset = int(sum(8 * (n ** 2 - 4) + 8 * (n - 2) ** 2 for n in sides))
+    out = {"config": "batched_256x_jacobi2d_sides_64_2048_50sweeps", "sum_n2": int(sum(n * n for n in sides)),
            "alg_bytes_per_run": bytes_per_sweepset * sweeps, "regions_per_run": 256 * sweeps}
     launch = _launch(tuner, "batched_256")
-    prog = programs.jacobi2d(sweeps)
     for name, mode in MODES:
         ms = _time(ctx, torch, lambda: ctx.run(prog, insts, mode=mode, launch=launch), reps)
         out[name] = {"ms_per_run": round(ms, 3), "GBps": round(out["alg_bytes_per_run"] / (ms * 1e-3) / 1e9, 1),
@@ -146,7 +113,7 @@ def measure_batched(ctx, gf, programs, tuner, torch, gi, reps):
     return out
 
 
-def measure_sync(ctx, gf, programs, tuner, torch, gi, reps):
+def measure_sync(ctx, gf, programs, tuner, torch, reps):
     """Cost of one region of a trivial program (3D Jacobi on a 4^3 grid, one
     interior point): the grid barrier plus serial glue in the persistent mode,
     the launch gap in the per-region modes, at several grid sizes."""
@@ -178,7 +145,6 @@ def main():
     ap.add_argument("--reps", type=int, default=3)
     args = ap.parse_args()
     import torch
-    import gf_inputs as gi
     import paper_2306_11686_amd as gf
     from paper_2306_11686_amd import programs, tuner
     ctx = gf.Context(0, rpc_capture=True)
@@ -186,7 +152,7 @@ def main():
            "batched": measure_batched}
     for c in args.configs.split(","):
         log(f"[measure] {c}")
-        print(json.dumps(fns[c](ctx, gf, programs, tuner, torch, gi, args.reps)), flush=True)
+        print(json.dumps(fns[c](ctx, gf, programs, tuner, torch, args.reps)), flush=True)
     ctx.close()
 
 
