@@ -995,10 +995,13 @@ gf_status gf_region_run(gf_ctx *ctx, const gf_program *prog, const gf_instance *
         if (n_inst > 1)
             return run_batched(ctx, p, inst, n_inst, t, launch, cap, stats, stream);
         for (int i = 0; i < n_inst; ++i) {
-            // default grid: one workgroup per work item, at most two per CU
-            // (the grid barrier's cost grows with the number of members)
-            int grid = (int)std::min<int64_t>(std::min<int64_t>(cap, 2 * (int64_t)ctx->num_cu),
-                                              max_items(p, inst[i], t));
+            // default grid: at most two workgroups per CU (the grid barrier's
+            // cost grows with the number of members), sized so that every
+            // workgroup gets the same number of work items (balanced rounds)
+            const int64_t gmax = std::min<int64_t>(cap, 2 * (int64_t)ctx->num_cu);
+            const int64_t items = max_items(p, inst[i], t);
+            const int64_t rounds = (items + gmax - 1) / gmax;
+            int grid = (int)((items + rounds - 1) / rounds);
             if (launch && launch->num_wg > 0) {
                 if (launch->num_wg > cap)
                     return fail(ctx, GF_EINVAL, "num_wg %d exceeds the co-resident capacity %d", launch->num_wg, cap);
