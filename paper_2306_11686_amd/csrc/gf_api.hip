@@ -11,6 +11,7 @@
 #include <chrono>
 #include <cstdarg>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <map>
 #include <mutex>
@@ -273,6 +274,10 @@ gf_status gf_ctx_create(int32_t hip_device, const gf_ctx_opts *opts, gf_ctx **ou
     ctx->scr.hist_rows = (uint32_t *)(base + part_bytes + line_bytes + 256);
     const int64_t btus = o.barrier_timeout_us > 0 ? o.barrier_timeout_us : 10 * 1000 * 1000;
     ctx->scr.barrier_timeout_ticks = btus * 100;
+    ctx->scr.epoch = 0;
+    ctx->scr.barrier_kind = kBarrierTree;
+    if (const char *bk = std::getenv("GF_BARRIER"))
+        ctx->scr.barrier_kind = std::strcmp(bk, "xcd") == 0 ? kBarrierXcd : kBarrierTree;
 
     // RPC ring
     uint32_t ns = o.rpc_slots > 0 ? (uint32_t)o.rpc_slots : 256u;
@@ -1021,6 +1026,7 @@ gf_status gf_region_run(gf_ctx *ctx, const gf_program *prog, const gf_instance *
             std::memcpy(di.arr, inst[i].arr, sizeof di.arr);
             di.scal = inst[i].scal;
             std::memcpy(di.ip, inst[i].ip, sizeof di.ip);
+            ctx->scr.epoch += 1;
             hipError_t e = launch_persistent(p, di, t, grid, ctx->scr, ring_of(ctx), stream);
             if (e != hipSuccess)
                 return hipfail(ctx, e, "persistent launch");
@@ -1138,7 +1144,10 @@ gf_status gf_sync(gf_ctx *ctx, void *hip_stream, gf_run_stats *stats)
     if ((e = hipMemcpy(&code, ctx->scr.error, sizeof code, hipMemcpyDeviceToHost)) != hipSuccess)
         return hipfail(ctx, e, "error word read");
     if (code != kErrNone) {
+        // a kernel that stopped on the error may have left barrier counters
+        // mid-count: clear every counter line with the error word
         const int32_t zero = 0;
+        hipMemset(ctx->scr.lines, 0, (size_t)kNumLines * kLineWords * sizeof(uint32_t));
         hipMemcpy(ctx->scr.error, &zero, sizeof zero, hipMemcpyHostToDevice);
         if (code == kErrBarrierTimeout)
             return fail(ctx, GF_ETIMEOUT, "device: grid barrier watchdog expired");

@@ -246,6 +246,130 @@ __device__ __forceinline__ bool flat_barrier(uint32_t *line, uint32_t nmembers, 
     return bs->ok != 0;
 }
 
+// ---------------------------------------------------------------------------
+// XCD-aware grid barrier. The L2 is per XCD, so what the release and acquire
+// fences of the tree barrier do per workgroup (write the XCD's L2 back,
+// invalidate it) needs doing once per XCD: a workgroup's stores are in its
+// XCD's L2 once acknowledged, so after the XCD's last arrival has counted
+// every member it writes that L2 back for all of them; after the global
+// generation moves it invalidates that L2 once and releases the XCD's
+// members, which then only invalidate their own CU's L1.
+// Membership is counted once per launch: each workgroup reads its XCD id
+// from the hardware register and adds itself to that XCD's registration word
+// (tagged with the launch's epoch so stale counts from earlier launches are
+// ignored); a tree barrier then makes the counts final.
+// ---------------------------------------------------------------------------
+
+struct XcdState {
+    uint32_t x;    // this workgroup's XCD
+    uint32_t mx;   // members on that XCD
+    uint32_t nx;   // XCDs with members
+    int32_t use;   // 1: XCD barrier usable (every id was in range)
+};
+
+__device__ __forceinline__ uint32_t hw_xcc_id()
+{
+    // s_getreg_b32 of HW_REG_XCC_ID (id 20), bits [3:0]
+    return __builtin_amdgcn_s_getreg(20 | (0 << 6) | (3 << 11));
+}
+
+// Thread 0 only: register this workgroup with its XCD for launch `epoch`.
+__device__ __forceinline__ void xcd_register(uint32_t *lines, uint32_t epoch, XcdState *xs)
+{
+    const uint32_t id = hw_xcc_id();
+    if (id >= (uint32_t)kNumXcd) {
+        __hip_atomic_fetch_add(lines + kXcdBadLine * kLineWords, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        xs->x = 0;
+        return;
+    }
+    xs->x = id;
+    uint64_t *w = (uint64_t *)(lines + (kXcdRegLine0 + id) * kLineWords);
+    uint64_t old = __hip_atomic_load(w, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    for (;;) {
+        const uint64_t nw = ((uint32_t)(old >> 32) == epoch) ? old + 1u : (((uint64_t)epoch << 32) | 1u);
+        if (__hip_atomic_compare_exchange_strong(w, &old, nw, __ATOMIC_RELAXED, __ATOMIC_RELAXED,
+                                                 __HIP_MEMORY_SCOPE_AGENT))
+            break;
+    }
+}
+
+// Thread 0 only, after a full barrier that follows every registration.
+// The bad-id counter is read by every workgroup after that barrier and reset
+// by nobody: any non-zero value disables the XCD barrier for this context.
+__device__ __forceinline__ void xcd_finalize(uint32_t *lines, uint32_t epoch, XcdState *xs)
+{
+    uint32_t nx = 0, mx = 0;
+    for (int k = 0; k < kNumXcd; ++k) {
+        const uint64_t v = __hip_atomic_load((uint64_t *)(lines + (kXcdRegLine0 + k) * kLineWords),
+                                             __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        const uint32_t c = ((uint32_t)(v >> 32) == epoch) ? (uint32_t)v : 0u;
+        nx += c ? 1u : 0u;
+        if ((uint32_t)k == xs->x)
+            mx = c;
+    }
+    xs->mx = mx;
+    xs->nx = nx;
+    xs->use = __hip_atomic_load(lines + kXcdBadLine * kLineWords, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == 0u &&
+              mx > 0;
+}
+
+__device__ __forceinline__ bool wait_equal(uint32_t *w, uint32_t want, int32_t *err, int64_t timeout_ticks)
+{
+    const uint64_t t0 = now_ticks();
+    uint32_t spins = 0;
+    while (__hip_atomic_load(w, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != want) {
+        __builtin_amdgcn_s_sleep(1);
+        if ((++spins & 63u) == 0) {
+            if (read_error(err) != kErrNone)
+                return false;
+            if ((int64_t)(now_ticks() - t0) > timeout_ticks) {
+                set_error(err, kErrBarrierTimeout);
+                return false;
+            }
+        }
+    }
+    return true;
+}
+
+__device__ __forceinline__ bool xcd_barrier(uint32_t *lines, const XcdState &xs, BarrierState *bs, int32_t *err,
+                                            int64_t timeout_ticks)
+{
+    __builtin_amdgcn_s_waitcnt(0x0F70);  // vmcnt(0): this wavefront's stores are in the XCD's L2
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        uint32_t *genw = lines + 1;
+        uint32_t *xcnt = lines + (kXcdCntLine0 + xs.x) * kLineWords;
+        uint32_t *xgen = lines + (kXcdGenLine0 + xs.x) * kLineWords;
+        uint32_t *top = lines + kXcdTopLine * kLineWords;
+        const uint32_t g = bs->gen;
+        int32_t ok = 1;
+        const uint32_t a = __hip_atomic_fetch_add(xcnt, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        if (a == xs.mx - 1) {
+            // leader of this XCD: every member's stores are in this L2
+            __hip_atomic_store(xcnt, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");  // write this XCD's L2 back
+            const uint32_t b = __hip_atomic_fetch_add(top, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            if (b == xs.nx - 1) {
+                __hip_atomic_store(top, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                __builtin_amdgcn_s_waitcnt(0x0F70);
+                __hip_atomic_store(genw, g + 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            } else {
+                ok = wait_equal(genw, g + 1u, err, timeout_ticks) ? 1 : 0;
+            }
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");  // invalidate this XCD's L2 (and our L1)
+            __builtin_amdgcn_s_waitcnt(0x0F70);
+            __hip_atomic_store(xgen, g + 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        } else {
+            ok = wait_equal(xgen, g + 1u, err, timeout_ticks) ? 1 : 0;
+            __asm__ __volatile__("buffer_inv sc0" ::: "memory");  // this CU's L1 only
+        }
+        bs->gen = g + 1u;
+        bs->ok = ok;
+    }
+    __syncthreads();
+    return bs->ok != 0;
+}
+
 // Logical worker id of workgroup `wg` among `nwg`: workgroups are dispatched
 // round-robin over the 8 XCDs (each with its own L2), so with remapping the
 // workers of one XCD get consecutive ids and hence neighbouring tiles.

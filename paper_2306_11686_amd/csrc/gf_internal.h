@@ -116,7 +116,12 @@ struct Scratch {
     int32_t *error;          // sticky device error word
     int64_t barrier_timeout_ticks;
     uint32_t *hist_rows;     // histogram partial rows (kHistRowsMax rows of 65536 u32)
+    uint32_t epoch;          // persistent-launch sequence number (XCD registration)
+    int32_t barrier_kind;    // kBarrierTree or kBarrierXcd
 };
+
+constexpr int kBarrierTree = 0;  // every workgroup writes back and invalidates its L2
+constexpr int kBarrierXcd = 1;   // one write-back and one L2 invalidate per XCD
 
 constexpr int kHistRowsMax = 512;
 
@@ -130,7 +135,15 @@ constexpr int kTreeLine0 = 1;
 constexpr int kTreeLines = 512;  // >= 4096/16 + 4096/256 + 1
 constexpr int kGroupLine0 = kTreeLine0 + kTreeLines;
 constexpr int kFinalizeLine0 = kGroupLine0 + GF_MAX_INSTANCES;
-constexpr int kNumLines = kFinalizeLine0 + GF_MAX_INSTANCES;
+// XCD barrier: per-XCD registration words (epoch << 32 | members), per-XCD
+// arrival counters and release generations, the count of XCD leaders, and
+// the count of workgroups that reported an unexpected XCD id.
+constexpr int kXcdRegLine0 = kFinalizeLine0 + GF_MAX_INSTANCES;
+constexpr int kXcdCntLine0 = kXcdRegLine0 + kNumXcd;
+constexpr int kXcdGenLine0 = kXcdCntLine0 + kNumXcd;
+constexpr int kXcdTopLine = kXcdGenLine0 + kNumXcd;
+constexpr int kXcdBadLine = kXcdTopLine + 1;
+constexpr int kNumLines = kXcdBadLine + 1;
 
 // A serial step attached to a per-region launch, with its array operand
 // resolved on the host (SWAPs are applied by the host while it walks the

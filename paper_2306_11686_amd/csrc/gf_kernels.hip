@@ -725,8 +725,9 @@ __global__ void __launch_bounds__(family_max_threads<KMASK>())
     __shared__ void *s_arr[GF_MAX_ARRAYS];
     __shared__ double s_red[kLdsRed];
     __shared__ BarrierState s_bar;
+    __shared__ XcdState s_xcd;
 
-    // Single instance: the whole grid, tree barrier. Batched: this
+    // Single instance: the whole grid, tree or XCD barrier. Batched: this
     // workgroup's group of its instance, flat group barrier.
     const bool batched = batch.wg != nullptr;
     BatchEntry be;
@@ -745,10 +746,13 @@ __global__ void __launch_bounds__(family_max_threads<KMASK>())
     uint32_t *gline = scr.lines + (int64_t)(kGroupLine0 + be.inst) * kLineWords;
     uint32_t *genw = batched ? gline + 1 : scr.lines + 1;  // generation word
     uint32_t *tree = scr.lines + kTreeLine0 * kLineWords;
+    const bool xmode = !batched && scr.barrier_kind == kBarrierXcd && G > 1;
     auto barrier = [&]() -> bool {
-        return batched ? flat_barrier(gline, (uint32_t)G, &s_bar, scr.error, scr.barrier_timeout_ticks)
-                       : tree_barrier(genw, tree, (uint32_t)member, (uint32_t)G, &s_bar, scr.error,
-                                      scr.barrier_timeout_ticks);
+        if (batched)
+            return flat_barrier(gline, (uint32_t)G, &s_bar, scr.error, scr.barrier_timeout_ticks);
+        if (xmode && s_xcd.use)
+            return xcd_barrier(scr.lines, s_xcd, &s_bar, scr.error, scr.barrier_timeout_ticks);
+        return tree_barrier(genw, tree, (uint32_t)member, (uint32_t)G, &s_bar, scr.error, scr.barrier_timeout_ticks);
     };
     if (threadIdx.x < GF_MAX_SCALARS)
         s_scal[threadIdx.x] = inst.scal[threadIdx.x];
@@ -757,8 +761,18 @@ __global__ void __launch_bounds__(family_max_threads<KMASK>())
     if (threadIdx.x == 0) {
         s_bar.gen = __hip_atomic_load(genw, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         s_bar.ok = 1;
+        s_xcd.use = 0;
+        if (xmode)
+            xcd_register(scr.lines, scr.epoch, &s_xcd);
     }
     __syncthreads();
+    if (xmode) {
+        if (!tree_barrier(genw, tree, (uint32_t)member, (uint32_t)G, &s_bar, scr.error, scr.barrier_timeout_ticks))
+            return;
+        if (threadIdx.x == 0)
+            xcd_finalize(scr.lines, scr.epoch, &s_xcd);
+        __syncthreads();
+    }
 
     int parity = 0;
     const int64_t total = (int64_t)prog.n_pro + (int64_t)prog.iters * prog.n_body;
@@ -983,56 +997,60 @@ typedef void (*RegionFn)(RegionLaunch, Tiling, Scratch, RpcRing);
 template <unsigned F>
 static PersistentFn persistent_for_ty(int ty, int pf)
 {
-    if constexpr (F == kFamVec || F == kFamHist)
-        return ty >= 1 ? k_persistent<F, 1, 1> : nullptr;
-    if constexpr (F == kFamJ3) {
-        if (pf == 2) {
-            switch (ty) {
-            case 1: return k_persistent<F, 1, 2>;
-            case 2: return k_persistent<F, 2, 2>;
-            case 4: return k_persistent<F, 4, 2>;
-            case 8: return k_persistent<F, 8, 2>;
-            default: return nullptr;
+    if constexpr (F == kFamVec || F == kFamHist) {
+        return ty >= 1 && pf == 1 ? k_persistent<F, 1, 1> : nullptr;
+    } else {
+        if constexpr (F == kFamJ3) {
+            if (pf == 2) {
+                switch (ty) {
+                case 1: return k_persistent<F, 1, 2>;
+                case 2: return k_persistent<F, 2, 2>;
+                case 4: return k_persistent<F, 4, 2>;
+                case 8: return k_persistent<F, 8, 2>;
+                default: return nullptr;
+                }
             }
         }
-    }
-    if (pf != 1)
-        return nullptr;
-    switch (ty) {
-    case 1: return k_persistent<F, 1, 1>;
-    case 2: return k_persistent<F, 2, 1>;
-    case 4: return k_persistent<F, 4, 1>;
-    case 8: return k_persistent<F, 8, 1>;
-    case 16: return k_persistent<F, 16, 1>;
-    default: return nullptr;
+        if (pf != 1)
+            return nullptr;
+        switch (ty) {
+        case 1: return k_persistent<F, 1, 1>;
+        case 2: return k_persistent<F, 2, 1>;
+        case 4: return k_persistent<F, 4, 1>;
+        case 8: return k_persistent<F, 8, 1>;
+        case 16: return k_persistent<F, 16, 1>;
+        default: return nullptr;
+        }
     }
 }
 
 template <unsigned F>
 static RegionFn region_for_ty(int ty, int pf)
 {
-    if constexpr (F == kFamVec || F == kFamHist)
-        return ty >= 1 ? k_region<F, 1, 1> : nullptr;
-    if constexpr (F == kFamJ3) {
-        if (pf == 2) {
-            switch (ty) {
-            case 1: return k_region<F, 1, 2>;
-            case 2: return k_region<F, 2, 2>;
-            case 4: return k_region<F, 4, 2>;
-            case 8: return k_region<F, 8, 2>;
-            default: return nullptr;
+    if constexpr (F == kFamVec || F == kFamHist) {
+        return ty >= 1 && pf == 1 ? k_region<F, 1, 1> : nullptr;
+    } else {
+        if constexpr (F == kFamJ3) {
+            if (pf == 2) {
+                switch (ty) {
+                case 1: return k_region<F, 1, 2>;
+                case 2: return k_region<F, 2, 2>;
+                case 4: return k_region<F, 4, 2>;
+                case 8: return k_region<F, 8, 2>;
+                default: return nullptr;
+                }
             }
         }
-    }
-    if (pf != 1)
-        return nullptr;
-    switch (ty) {
-    case 1: return k_region<F, 1, 1>;
-    case 2: return k_region<F, 2, 1>;
-    case 4: return k_region<F, 4, 1>;
-    case 8: return k_region<F, 8, 1>;
-    case 16: return k_region<F, 16, 1>;
-    default: return nullptr;
+        if (pf != 1)
+            return nullptr;
+        switch (ty) {
+        case 1: return k_region<F, 1, 1>;
+        case 2: return k_region<F, 2, 1>;
+        case 4: return k_region<F, 4, 1>;
+        case 8: return k_region<F, 8, 1>;
+        case 16: return k_region<F, 16, 1>;
+        default: return nullptr;
+        }
     }
 }
 
