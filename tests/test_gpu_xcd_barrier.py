@@ -49,12 +49,12 @@ def test_jacobi2d_xcd_barrier_with_printf(xctx, oracle_lib):
     print("xcd barrier jacobi2d 256 printf", flush=True)
     fmt = xctx.register_format(programs.JACOBI2D_FORMAT, "id")
     u0 = gi.grid2d(256, seed=1)
-    g_ref, r_ref = oracle_lib.jacobi2d(u0, 100)
+    g_ref, _, r_comp, text = oracle_lib.jacobi2d(u0, 100, print_every=10)
     g, r, _ = run_jacobi2d(xctx, u0, 100, gf.GF_EXEC_PERSISTENT, fmt_id=fmt, print_every=10)
     out = xctx.take_output()
     assert np.array_equal(g, g_ref)
-    assert np.all(np.abs(r - r_ref) <= 1e-12 * np.abs(r_ref))
-    assert out.count("\n") == 10
+    assert np.all(np.abs(r - r_comp) <= 1e-12 * np.abs(r_comp))
+    assert out.count("\n") == 10 and len(out.splitlines()) == len(text.splitlines())
 
 
 def test_cg_xcd_barrier_matches_per_region(xctx):
