@@ -252,8 +252,9 @@ __device__ __forceinline__ bool flat_barrier(uint32_t *line, uint32_t nmembers, 
 // invalidate it) needs doing once per XCD: a workgroup's stores are in its
 // XCD's L2 once acknowledged, so after the XCD's last arrival has counted
 // every member it writes that L2 back for all of them; after the global
-// generation moves it invalidates that L2 once and releases the XCD's
-// members, which then only invalidate their own CU's L1.
+// generation moves it invalidates that L2 and releases the XCD's members,
+// which acquire in turn. The write-backs (one per XCD instead of one per
+// workgroup) are what the tree barrier pays most for.
 // Membership is counted once per launch: each workgroup reads its XCD id
 // from the hardware register and adds itself to that XCD's registration word
 // (tagged with the launch's epoch so stale counts from earlier launches are
@@ -361,7 +362,10 @@ __device__ __forceinline__ bool xcd_barrier(uint32_t *lines, const XcdState &xs,
             __hip_atomic_store(xgen, g + 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         } else {
             ok = wait_equal(xgen, g + 1u, err, timeout_ticks) ? 1 : 0;
-            __asm__ __volatile__("buffer_inv sc0" ::: "memory");  // this CU's L1 only
+            // A member still invalidates at agent scope: measured, an L1-only
+            // invalidate after the leader's L2 invalidate let stale lines
+            // through.
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
         }
         bs->gen = g + 1u;
         bs->ok = ok;
