@@ -245,11 +245,17 @@ __device__ __forceinline__ gf_d2 ld_row(GF_GLOBAL const double *p, int r)
     return *(GF_GLOBAL const gf_d2 *)p;
 }
 
+// One tile of planes [z0, z1). PF (1 or 2) planes ahead of the computed
+// plane z are in flight: registers hold planes z-1 (own rows), z, z+1 and,
+// for PF = 2, z+2, while the next plane is requested at the top of the step.
+// The two depths are written out separately: folding them into one ring
+// array cost a fifth of the bandwidth at depth 1 (measured).
 template <int TY, int PF, bool FULL>
 __device__ __forceinline__ double j3v2_tile(GF_GLOBAL const double *__restrict__ u, GF_GLOBAL double *__restrict__ w,
                                             int64_t n, int64_t x, int64_t y0, int ny, int64_t z0, int64_t z1,
                                             bool want_red)
 {
+    static_assert(PF == 1 || PF == 2, "prefetch depth 1 or 2");
     __shared__ double s_edge[2][kMaxWg / kWave][TY][2];
     const int lane = threadIdx.x & (kWave - 1);
     const int wv = threadIdx.x / kWave;
@@ -263,35 +269,33 @@ __device__ __forceinline__ double j3v2_tile(GF_GLOBAL const double *__restrict__
     const int64_t SY = n, SZ = n * n;
     const double c6 = 1.0 / 6.0;
     double mx = -INFINITY;
-    // pm: plane z-1 (own rows); pc: plane z (with halo rows); q[k]: plane
-    // z+1+k, k < PF in hand, q[PF] being requested.
-    gf_d2 pm[TY], pc[TY + 2], q[PF + 1][TY + 2];
+    // pm: plane z-1 (own rows); pc: plane z; pn: plane z+1; pa: z+2 (PF = 2);
+    // pf: the plane being requested (z+1+PF)
+    gf_d2 pm[TY], pc[TY + 2], pn[TY + 2], pa[PF == 2 ? TY + 2 : 1], pf[TY + 2];
     const gf_d2 zero2 = {0.0, 0.0};
     GF_GLOBAL const double *col = u + (y0 - 1) * SY + xs;  // row y0-1 of plane 0
 #pragma unroll
     for (int r = 0; r < TY; ++r)
         pm[r] = (FULL || r < ny) ? ld_row<TY>(col + (z0 - 1) * SZ + (r + 1) * SY, r + 1) : zero2;
+    // planes z0 and z0+1 exist (z0+1 <= z1 <= n-1); z0+2 may be past the grid
 #pragma unroll
     for (int r = 0; r < TY + 2; ++r) {
         pc[r] = (FULL || r < ny + 2) ? ld_row<TY>(col + z0 * SZ + r * SY, r) : zero2;
-#pragma unroll
-        for (int k = 0; k <= PF; ++k)
-            q[k][r] = zero2;
+        pn[r] = (FULL || r < ny + 2) ? ld_row<TY>(col + (z0 + 1) * SZ + r * SY, r) : zero2;
+        pf[r] = zero2;
     }
+    if constexpr (PF == 2) {
+        const bool have = z0 + 2 <= z1;
 #pragma unroll
-    for (int k = 0; k < PF; ++k)
-        if (z0 + 1 + k <= z1) {
-#pragma unroll
-            for (int r = 0; r < TY + 2; ++r)
-                if (FULL || r < ny + 2)
-                    q[k][r] = ld_row<TY>(col + (z0 + 1 + k) * SZ + r * SY, r);
-        }
+        for (int r = 0; r < TY + 2; ++r)
+            pa[r] = (have && (FULL || r < ny + 2)) ? ld_row<TY>(col + (z0 + 2) * SZ + r * SY, r) : zero2;
+    }
     for (int64_t z = z0; z < z1; ++z) {
         if (z + 1 + PF <= z1) {
 #pragma unroll
             for (int r = 0; r < TY + 2; ++r)
                 if (FULL || r < ny + 2)
-                    q[PF][r] = ld_row<TY>(col + (z + 1 + PF) * SZ + r * SY, r);
+                    pf[r] = ld_row<TY>(col + (z + 1 + PF) * SZ + r * SY, r);
         }
         const int par = (int)(z & 1);
         if (lane == 0) {
@@ -332,10 +336,9 @@ __device__ __forceinline__ double j3v2_tile(GF_GLOBAL const double *__restrict__
                 const double er = wv < nw - 1 ? s_edge[par][wv + 1][r][0] : gr[r];
                 const double xl = lane == 0 ? el : sl;
                 const double xr = lane == kWave - 1 ? er : sr;
-                const gf_d2 zp = q[0][r + 1];
                 gf_d2 v;
-                v.x = (((xl + c.y) + (pc[r].x + pc[r + 2].x)) + (pm[r].x + zp.x)) * c6;
-                v.y = (((c.x + xr) + (pc[r].y + pc[r + 2].y)) + (pm[r].y + zp.y)) * c6;
+                v.x = (((xl + c.y) + (pc[r].x + pc[r + 2].x)) + (pm[r].x + pn[r + 1].x)) * c6;
+                v.y = (((c.x + xr) + (pc[r].y + pc[r + 2].y)) + (pm[r].y + pn[r + 1].y)) * c6;
                 if (in0 && in1) {
                     __builtin_nontemporal_store(v, (GF_GLOBAL gf_d2 *)(out + r * SY));
                 } else if (in0) {
@@ -356,10 +359,13 @@ __device__ __forceinline__ double j3v2_tile(GF_GLOBAL const double *__restrict__
             pm[r] = pc[r + 1];
 #pragma unroll
         for (int r = 0; r < TY + 2; ++r) {
-            pc[r] = q[0][r];
-#pragma unroll
-            for (int k = 0; k < PF; ++k)
-                q[k][r] = q[k + 1][r];
+            pc[r] = pn[r];
+            if constexpr (PF == 2) {
+                pn[r] = pa[r];
+                pa[r] = pf[r];
+            } else {
+                pn[r] = pf[r];
+            }
         }
     }
     return mx;
