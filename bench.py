@@ -12,7 +12,6 @@ serial CPU oracle timed on a bounded sample on this host.
 from __future__ import annotations
 
 import argparse
-import hashlib
 import json
 import os
 import sys
@@ -36,12 +35,8 @@ def alg_bytes_per_sweep(n: int) -> int:
 
 
 def kernel_source_hash() -> str:
-    h = hashlib.sha256()
-    csrc = os.path.join(ROOT, "paper_2306_11686_amd", "csrc")
-    for fn in sorted(os.listdir(csrc)):
-        with open(os.path.join(csrc, fn), "rb") as f:
-            h.update(f.read())
-    return h.hexdigest()[:16]
+    from paper_2306_11686_amd.build import kernel_source_hash as h
+    return h()
 
 
 def load_traffic(workload: str):

@@ -265,7 +265,7 @@ gf_status gf_copy(gf_ctx *ctx, void *d_dst, const void *d_src, int64_t nbytes, i
  * Candidate c (0..31) is decoded per kernel family of the program, with
  * a = c & 3, b = (c >> 2) & 3, h = c >> 4:
  *   3D stencil : tile_y = {1,2,4,8}[a], tile_z = ceil((n-2)/{2,3,4,6}[b]),
- *                prefetch = 1 + h
+ *                num_wg = h ? 3 * CUs : default
  *   2D stencil : tile_y = {1,2,4,8}[a], wg_size = {64,128,192,256}[b],
  *                xcd_remap = 1 - h
  *   streaming (SpMV, dot, axpby): wg_size = {64,128,192,256}[a],

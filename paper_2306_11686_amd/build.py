@@ -20,6 +20,17 @@ LIB = os.path.join(HERE, "libgf.so")
 ARCH = "gfx950"
 
 
+def kernel_source_hash() -> str:
+    """Short hash of every kernel source under csrc/:
+    measurements tied to the kernels record it and lapse when it changes."""
+    import hashlib
+    h = hashlib.sha256()
+    for fn in sorted(os.listdir(CSRC)):
+        with open(os.path.join(CSRC, fn), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
+
+
 def hipcc() -> str:
     for cand in (os.environ.get("HIPCC"), "/opt/rocm/bin/hipcc", "hipcc"):
         if cand and (os.path.isabs(cand) and os.path.exists(cand) or not os.path.isabs(cand)):

@@ -275,9 +275,11 @@ gf_status gf_ctx_create(int32_t hip_device, const gf_ctx_opts *opts, gf_ctx **ou
     const int64_t btus = o.barrier_timeout_us > 0 ? o.barrier_timeout_us : 10 * 1000 * 1000;
     ctx->scr.barrier_timeout_ticks = btus * 100;
     ctx->scr.epoch = 0;
-    ctx->scr.barrier_kind = kBarrierTree;
+    // XCD barrier by default; GF_BARRIER=tree selects the per-workgroup
+    // publication of the tree barrier (for comparison)
+    ctx->scr.barrier_kind = kBarrierXcd;
     if (const char *bk = std::getenv("GF_BARRIER"))
-        ctx->scr.barrier_kind = std::strcmp(bk, "xcd") == 0 ? kBarrierXcd : kBarrierTree;
+        ctx->scr.barrier_kind = std::strcmp(bk, "tree") == 0 ? kBarrierTree : kBarrierXcd;
 
     // RPC ring
     uint32_t ns = o.rpc_slots > 0 ? (uint32_t)o.rpc_slots : 256u;
@@ -1196,7 +1198,7 @@ gf_launch decode_candidate(const DProg &p, const gf_instance &in, int c, int num
         l.tile_y = ty[a];
         l.tile_z = (int32_t)std::max<int64_t>(1, (interior + zs[b] - 1) / zs[b]);
         l.xcd_remap = 1;
-        l.prefetch = 1 + h;
+        l.num_wg = h ? 3 * num_cu : 0;  // three workgroups per CU, or the default grid
     } else if (m & (1u << GF_R_JACOBI2D)) {
         l.tile_y = ty[a];
         l.wg_size = wg[b];

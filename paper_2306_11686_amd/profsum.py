@@ -1,0 +1,113 @@
+"""Summaries of rocprofv3 output for the committed profiles.
+
+    python -m paper_2306_11686_amd.profsum stats KERNEL_STATS_CSV [--top 8]
+    python -m paper_2306_11686_amd.profsum traffic --fetch COUNTER_CSV --write COUNTER_CSV \\
+        --workload jacobi3d_512 --kernel k_persistent --alg-bytes N [--copy-bytes 1073741824] \\
+        [--update profiles/traffic.json]
+
+`stats` prints the kernel-trace statistics (``--kernel-trace --stats``) as a
+markdown table. `traffic` turns two counter passes (FETCH_SIZE, WRITE_SIZE,
+in KiB per dispatch) into HBM bytes per launch of the named kernel, each
+scaled by what the same counter read for the copy kernel (`gf::k_copy_tiles`,
+copy_bytes read and copy_bytes written per dispatch) in the same run, and
+records them with the kernels' source hash (measurements lapse when the
+kernels change).
+"""
+from __future__ import annotations
+
+import argparse
+import csv
+import json
+import statistics
+import sys
+
+from .build import kernel_source_hash
+
+
+def _rows(path):
+    with open(path, newline="") as f:
+        return list(csv.DictReader(f))
+
+
+def stats_table(path: str, top: int = 8) -> str:
+    rows = _rows(path)
+    rows.sort(key=lambda r: -float(r["TotalDurationNs"]))
+    out = ["| kernel | calls | average (us) | min (us) | max (us) | share |", "|---|---|---|---|---|---|"]
+    for r in rows[:top]:
+        name = r["Name"] if len(r["Name"]) <= 100 else r["Name"][:97] + "..."
+        out.append(f"| `{name}` | {r['Calls']} | {float(r['AverageNs']) / 1e3:.1f} | {float(r['MinNs']) / 1e3:.1f} | "
+                   f"{float(r['MaxNs']) / 1e3:.1f} | {float(r['Percentage']):.2f}% |")
+    return "\n".join(out)
+
+
+def counter_per_dispatch(path: str, counter: str, kernel: str):
+    """(median over the copy-kernel dispatches, mean over the kernel's) in KiB."""
+    copy, target = [], []
+    for r in _rows(path):
+        if r["Counter_Name"] != counter:
+            continue
+        v = float(r["Counter_Value"])
+        if r["Kernel_Name"].startswith("gf::k_copy_tiles"):
+            copy.append(v)
+        elif kernel in r["Kernel_Name"]:
+            target.append(v)
+    if not copy or not target:
+        raise SystemExit(f"{path}: no {counter} rows for the copy kernel or for {kernel}")
+    return statistics.median(copy), sum(target) / len(target), len(target)
+
+
+def traffic(args) -> dict:
+    fc, fk, nf = counter_per_dispatch(args.fetch, "FETCH_SIZE", args.kernel)
+    wc, wk, nw = counter_per_dispatch(args.write, "WRITE_SIZE", args.kernel)
+    fs = args.copy_bytes / (fc * 1024.0)
+    ws = args.copy_bytes / (wc * 1024.0)
+    fb, wb = fk * 1024.0 * fs, wk * 1024.0 * ws
+    entry = {"source_hash": kernel_source_hash(), "bytes_per_launch": int(round(fb + wb)),
+             "fetch_bytes_per_launch": int(round(fb)), "write_bytes_per_launch": int(round(wb)),
+             "alg_bytes_per_launch": args.alg_bytes, "fetch_scale": round(fs, 6), "write_scale": round(ws, 6),
+             "fetch_kib_raw": round(fk, 1), "write_kib_raw": round(wk, 1), "dispatches": [nf, nw],
+             "kernel": args.kernel}
+    if args.update:
+        try:
+            with open(args.update) as f:
+                db = json.load(f)
+        except (OSError, ValueError):
+            db = {}
+        db[args.workload] = entry
+        with open(args.update, "w") as f:
+            json.dump(db, f, indent=1, sort_keys=True)
+            f.write("\n")
+    return entry
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    sub = ap.add_subparsers(dest="cmd", required=True)
+    s = sub.add_parser("stats")
+    s.add_argument("csv")
+    s.add_argument("--top", type=int, default=8)
+    t = sub.add_parser("traffic")
+    t.add_argument("--fetch", required=True)
+    t.add_argument("--write", required=True)
+    t.add_argument("--workload", required=True)
+    t.add_argument("--kernel", required=True)
+    t.add_argument("--alg-bytes", type=int, required=True)
+    t.add_argument("--copy-bytes", type=int, default=1 << 30)
+    t.add_argument("--update", default=None)
+    args = ap.parse_args()
+    if args.cmd == "stats":
+        print(stats_table(args.csv, args.top))
+        return
+    e = traffic(args)
+    a = args.alg_bytes
+    print("| quantity | per launch | vs algorithmic |\n|---|---|---|")
+    print(f"| FETCH_SIZE raw | {e['fetch_kib_raw']:.0f} KiB | |")
+    print(f"| WRITE_SIZE raw | {e['write_kib_raw']:.0f} KiB | |")
+    print(f"| reads (scaled x{e['fetch_scale']:.4f}) | {e['fetch_bytes_per_launch'] / 1e9:.2f} GB | |")
+    print(f"| writes (scaled x{e['write_scale']:.4f}) | {e['write_bytes_per_launch'] / 1e9:.2f} GB | |")
+    print(f"| total | {e['bytes_per_launch'] / 1e9:.2f} GB | {e['bytes_per_launch'] / a:.3f} x of {a / 1e9:.2f} GB |")
+    print(f"\nKernel source hash: {e['source_hash']}", file=sys.stdout)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,8 +1,8 @@
-"""The XCD-aware grid barrier (one L2 write-back and one L2 invalidate per
-XCD instead of per workgroup) must give the same results as the tree
-barrier: grids bit-exact against the oracle at several grid sizes, and
-persistent runs bit-identical to per-region runs for programs with
-reductions (CG) and with the two-phase histogram."""
+"""Both grid barriers — the XCD-aware one (the default: one L2 write-back
+per XCD) and the tree barrier with per-workgroup publication
+(GF_BARRIER=tree) — give results equal to the oracle's: grids bit-exact at
+several grid sizes, persistent runs bit-identical to per-region runs for
+programs with reductions (CG), exact histogram counts."""
 import os
 
 import numpy as np
@@ -14,11 +14,11 @@ from tests.gpu_helpers import run_jacobi2d, run_jacobi3d, host
 pytestmark = pytest.mark.gpu
 
 
-@pytest.fixture(scope="module")
-def xctx():
+@pytest.fixture(scope="module", params=["xcd", "tree"])
+def xctx(request):
     import paper_2306_11686_amd as gf
     old = os.environ.get("GF_BARRIER")
-    os.environ["GF_BARRIER"] = "xcd"
+    os.environ["GF_BARRIER"] = request.param
     try:
         ctx = gf.Context(0, rpc_capture=True)
     finally:
@@ -31,9 +31,9 @@ def xctx():
 
 
 @pytest.mark.parametrize("nwg", [2, 7, 64, 255, 512])
-def test_jacobi3d_xcd_barrier_grid_sizes(xctx, oracle_lib, nwg):
+def test_jacobi3d_barrier_grid_sizes(xctx, oracle_lib, nwg):
     import paper_2306_11686_amd as gf
-    print(f"xcd barrier jacobi3d n=66 sweeps=30 num_wg={nwg}", flush=True)
+    print(f"barrier jacobi3d n=66 sweeps=30 num_wg={nwg}", flush=True)
     u0 = gi.grid3d(66, seed=7)
     g_ref, r_ref = oracle_lib.jacobi3d(u0, 30)
     launch = gf.Launch.make(tile_y=1, tile_z=4, num_wg=nwg)
@@ -43,10 +43,10 @@ def test_jacobi3d_xcd_barrier_grid_sizes(xctx, oracle_lib, nwg):
     assert np.array_equal(r, r_ref)
 
 
-def test_jacobi2d_xcd_barrier_with_printf(xctx, oracle_lib):
+def test_jacobi2d_barrier_with_printf(xctx, oracle_lib):
     import paper_2306_11686_amd as gf
     from paper_2306_11686_amd import programs
-    print("xcd barrier jacobi2d 256 printf", flush=True)
+    print("barrier jacobi2d 256 printf", flush=True)
     fmt = xctx.register_format(programs.JACOBI2D_FORMAT, "id")
     u0 = gi.grid2d(256, seed=1)
     g_ref, _, r_comp, text = oracle_lib.jacobi2d(u0, 100, print_every=10)
@@ -57,11 +57,11 @@ def test_jacobi2d_xcd_barrier_with_printf(xctx, oracle_lib):
     assert out.count("\n") == 10 and len(out.splitlines()) == len(text.splitlines())
 
 
-def test_cg_xcd_barrier_matches_per_region(xctx):
+def test_cg_barrier_matches_per_region(xctx):
     import torch
     import paper_2306_11686_amd as gf
     from paper_2306_11686_amd import workloads
-    print("xcd barrier cg 24^3", flush=True)
+    print("barrier cg 24^3", flush=True)
     prog, inst, keep, reset = workloads.cg(24, 40)
     outs = []
     for mode in (gf.GF_EXEC_PER_REGION, gf.GF_EXEC_PERSISTENT):
@@ -73,11 +73,11 @@ def test_cg_xcd_barrier_matches_per_region(xctx):
         assert np.array_equal(a, b)
 
 
-def test_histogram_xcd_barrier_exact(xctx):
+def test_histogram_barrier_exact(xctx):
     import torch
     import paper_2306_11686_amd as gf
     from paper_2306_11686_amd import workloads
-    print("xcd barrier histogram 2^22", flush=True)
+    print("barrier histogram 2^22", flush=True)
     prog, inst, keep, reset = workloads.histogram(1 << 22, 65536, "zipf")
     keys = host(keep[0]).view(np.uint32)
     ref = np.bincount(keys & 0xFFFF, minlength=65536)

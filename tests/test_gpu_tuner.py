@@ -96,7 +96,7 @@ def test_region_run_without_launch_uses_installed_predictor(oracle_lib):
         u0 = gi.grid3d(n, seed=5)
         prog = programs.jacobi3d(sweeps)
         g_ref, r_ref = oracle_lib.jacobi3d(u0, sweeps)
-        best = 5 + 16                      # tile_y 2, tile_z ceil(64/3), prefetch 2
+        best = 5 + 16                      # tile_y 2, tile_z ceil(64/3), 3 workgroups per CU
         _constant_predictor(ctx, best)
         u = dev(u0)
         w = u.clone()
