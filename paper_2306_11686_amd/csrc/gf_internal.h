@@ -122,6 +122,8 @@ struct Scratch {
 
 constexpr int kBarrierTree = 0;  // every workgroup writes back and invalidates its L2
 constexpr int kBarrierXcd = 1;   // one write-back and one L2 invalidate per XCD
+// Below this grid size the tree barrier is cheaper (fewer serial hops).
+constexpr int kXcdBarrierMinWg = 96;
 
 constexpr int kHistRowsMax = 512;
 

@@ -752,8 +752,14 @@ __global__ void __launch_bounds__(family_max_threads<KMASK>())
     uint32_t *gline = scr.lines + (int64_t)(kGroupLine0 + be.inst) * kLineWords;
     uint32_t *genw = batched ? gline + 1 : scr.lines + 1;  // generation word
     uint32_t *tree = scr.lines + kTreeLine0 * kLineWords;
-    const bool xmode = !batched && scr.barrier_kind == kBarrierXcd && G > 1;
+    const bool xmode = !batched && scr.barrier_kind == kBarrierXcd && G >= kXcdBarrierMinWg;
     auto barrier = [&]() -> bool {
+        if (G == 1) {
+            // a group of one workgroup: a workgroup-scope barrier suffices
+            __builtin_amdgcn_s_waitcnt(0x0F70);
+            __syncthreads();
+            return true;
+        }
         if (batched)
             return flat_barrier(gline, (uint32_t)G, &s_bar, scr.error, scr.barrier_timeout_ticks);
         if (xmode && s_xcd.use)
