@@ -170,7 +170,8 @@ typedef struct {
     int32_t num_wg;      /* workgroups (persistent: <= co-resident capacity) */
     int32_t tile_y;      /* stencil rows per tile (1..16) */
     int32_t tile_z;      /* 3D stencil z-segment length */
-    int32_t items;       /* elements per thread for streaming regions */
+    int32_t items;       /* elements per thread for streaming regions (histogram:
+                          * groups of four keys per thread per chunk, 1, 2, 4 or 8) */
     int32_t xcd_remap;   /* 1: map consecutive tiles to one XCD (8 XCDs) */
     int32_t prefetch;    /* 3D stencil: planes loaded ahead of the one computed, 1 or 2
                           * (2 needs tile_y <= 8); ignored by other regions */

@@ -254,7 +254,7 @@ gf_status gf_ctx_create(int32_t hip_device, const gf_ctx_opts *opts, gf_ctx **ou
     const int64_t cap = 1 << 20;
     const size_t part_bytes = 2 * cap * sizeof(double);
     const size_t line_bytes = (size_t)kNumLines * 128;
-    const size_t hist_bytes = (size_t)kHistRowsMax * 65536 * sizeof(uint32_t);
+    const size_t hist_bytes = (size_t)kHistRowsMax * 65536 * sizeof(uint16_t);
     const size_t total = part_bytes + line_bytes + 256 + hist_bytes;
     char *base = nullptr;
     if ((e = hipMalloc((void **)&base, total)) != hipSuccess) {
@@ -587,6 +587,8 @@ gf_status check_tiling(gf_ctx *ctx, const DProg &p, const Tiling &t)
         return fail(ctx, GF_EINVAL, "prefetch must be 1 or 2");
     if (t.prefetch == 2 && t.tile_y > 8)
         return fail(ctx, GF_EINVAL, "prefetch 2 needs tile_y <= 8");
+    if (program_is_hist_family(p) && !(t.items == 1 || t.items == 2 || t.items == 4 || t.items == 8))
+        return fail(ctx, GF_EINVAL, "histogram items must be 1, 2, 4 or 8");
     if (program_is_hist_family(p) && (int64_t)t.wg_size * t.items * 4 > 32768)
         return fail(ctx, GF_EINVAL, "histogram chunks hold at most 32768 keys (wg_size * items * 4)");
     return GF_OK;

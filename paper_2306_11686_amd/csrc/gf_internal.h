@@ -115,7 +115,7 @@ struct Scratch {
     uint32_t *lines;         // counters: line i = lines + 32*i
     int32_t *error;          // sticky device error word
     int64_t barrier_timeout_ticks;
-    uint32_t *hist_rows;     // histogram partial rows (kHistRowsMax rows of 65536 u32)
+    uint32_t *hist_rows;     // histogram partial rows (kHistRowsMax rows of 65536 u16)
     uint32_t epoch;          // persistent-launch sequence number (XCD registration)
     int32_t barrier_kind;    // kBarrierTree or kBarrierXcd
 };

@@ -523,11 +523,12 @@ __device__ __forceinline__ void axpby_item(double *out_, const double *x_, doubl
 // falls in its part (all of a worker's items share one part because the
 // worker stride is a multiple of the part count) into 16-bit counters packed
 // two per 32-bit LDS word, with non-returning LDS atomics, then writes them
-// as its partial row. After every chunk (at most 32768 keys, checked on the
-// host) the workgroup moves 0x8000 of every counter that reached 0x8000 into
-// the global bin: a counter is below 0x8000 after a scan and grows by at most
-// 32768 before the next one, so it never wraps and no carry crosses into the
-// neighbouring counter. Integer counts are exact in any order.
+// as its partial row of 16-bit counts. After every chunk (at most 32768
+// keys, checked on the host) the workgroup moves 0x8000 of every counter
+// that reached 0x8000 into the global bin: a counter is below 0x8000 after a
+// scan and grows by at most 32768 before the next one, so it never wraps and
+// no carry crosses into the neighbouring counter; the final counters fit in
+// 16 bits. Integer counts are exact in any order.
 __device__ __forceinline__ void hist_count(uint32_t *s_h, uint32_t key, uint32_t mask, uint32_t lo, uint32_t span)
 {
     const uint32_t b = (key & mask) - lo;
@@ -556,10 +557,69 @@ __device__ __forceinline__ void hist_escape(uint32_t *s_h, GF_GLOBAL uint32_t *b
     __syncthreads();
 }
 
-__device__ __forceinline__ void hist_phase1(const uint32_t *keys_, uint32_t *bins_, uint32_t *rows_, uint32_t mask,
-                                            int64_t n, int64_t worker, int64_t G, const Tiling &t)
+typedef uint32_t gf_u4 __attribute__((ext_vector_type(4)));
+
+// The keys of one chunk for this thread: ITEMS groups of four consecutive
+// keys, group k at base + (k * blockDim.x + threadIdx.x) * 4. Every chunk
+// but the one holding the end of the array is whole (no guards); in that
+// one, missing keys are left out of the count.
+template <int ITEMS>
+__device__ __forceinline__ void hist_load(GF_GLOBAL const uint32_t *keys, int64_t n, int64_t base, gf_u4 (&v)[ITEMS])
 {
-    __shared__ uint32_t s_h[kHistPart / 2];
+    const uint32_t B4 = blockDim.x * 4u;
+    GF_GLOBAL const uint32_t *p = keys + base + threadIdx.x * 4u;
+    if (base + (int64_t)ITEMS * B4 <= n) {
+#pragma unroll
+        for (int k = 0; k < ITEMS; ++k)
+            v[k] = *(GF_GLOBAL const gf_u4 *)(p + k * B4);
+        return;
+    }
+    const int64_t left0 = n - base - threadIdx.x * 4;
+#pragma unroll
+    for (int k = 0; k < ITEMS; ++k) {
+        const int64_t left = left0 - (int64_t)k * B4;
+        v[k] = gf_u4{0u, 0u, 0u, 0u};
+        if (left >= 4)
+            v[k] = *(GF_GLOBAL const gf_u4 *)(p + k * B4);
+        else
+            for (int j = 0; j < left; ++j)
+                v[k][j] = p[k * B4 + j];
+    }
+}
+
+template <int ITEMS>
+__device__ __forceinline__ void hist_count_all(uint32_t *s_h, const gf_u4 (&v)[ITEMS], int64_t n, int64_t base,
+                                               uint32_t mask, uint32_t lo, uint32_t span)
+{
+    const uint32_t B4 = blockDim.x * 4u;
+    if (base + (int64_t)ITEMS * B4 <= n) {
+#pragma unroll
+        for (int k = 0; k < ITEMS; ++k) {
+            hist_count(s_h, v[k].x, mask, lo, span);
+            hist_count(s_h, v[k].y, mask, lo, span);
+            hist_count(s_h, v[k].z, mask, lo, span);
+            hist_count(s_h, v[k].w, mask, lo, span);
+        }
+        return;
+    }
+    const int64_t left0 = n - base - threadIdx.x * 4;
+    for (int k = 0; k < ITEMS; ++k) {
+        const int64_t left = left0 - (int64_t)k * B4;
+        for (int j = 0; j < 4 && j < left; ++j)
+            hist_count(s_h, v[k][j], mask, lo, span);
+    }
+}
+
+// Up to four groups per thread, the next chunk's keys are requested before
+// this chunk is counted, so their latency hides behind the LDS atomics and
+// the escape scan (eight groups double-buffered would not fit the 128
+// registers of a 1024-thread workgroup). s_h: the workgroup's
+// kHistPart / 2 LDS words.
+template <int ITEMS>
+__device__ __forceinline__ void hist_phase1_t(uint32_t *s_h, const uint32_t *keys_, uint32_t *bins_,
+                                              uint32_t *rows_, uint32_t mask, int64_t n, int64_t worker, int64_t G,
+                                              const Tiling &t)
+{
     GF_GLOBAL const uint32_t *__restrict__ keys = gptr(keys_);
     GF_GLOBAL uint32_t *bins = gptr(bins_);
     const HistGeom g = hist_geom(n, mask, t);
@@ -570,45 +630,89 @@ __device__ __forceinline__ void hist_phase1(const uint32_t *keys_, uint32_t *bin
     for (int i = threadIdx.x; i < kHistPart / 2; i += blockDim.x)
         s_h[i] = 0u;
     __syncthreads();
+    constexpr bool kAhead = ITEMS <= 4;
+    gf_u4 cur[ITEMS], nxt[kAhead ? ITEMS : 1];
+    if (kAhead && worker < g.nitems)
+        hist_load<ITEMS>(keys, n, (worker / g.parts) * g.chunk_keys, cur);
     for (int64_t it = worker; it < g.nitems; it += G) {
         const int64_t base = (it / g.parts) * g.chunk_keys;
-        for (int k = 0; k < t.items; ++k) {
-            const int64_t i4 = base + ((int64_t)k * blockDim.x + threadIdx.x) * 4;
-            if (i4 + 3 < n) {
-                typedef uint32_t gf_u4 __attribute__((ext_vector_type(4)));
-                const gf_u4 v = *(GF_GLOBAL const gf_u4 *)(keys + i4);
-                hist_count(s_h, v.x, mask, lo, span);
-                hist_count(s_h, v.y, mask, lo, span);
-                hist_count(s_h, v.z, mask, lo, span);
-                hist_count(s_h, v.w, mask, lo, span);
-            } else {
-                for (int64_t i = i4; i < n && i < i4 + 4; ++i)
-                    hist_count(s_h, keys[i], mask, lo, span);
+        if constexpr (kAhead) {
+            const bool more = it + G < g.nitems;
+            if (more)
+                hist_load<ITEMS>(keys, n, ((it + G) / g.parts) * g.chunk_keys, nxt);
+            hist_count_all<ITEMS>(s_h, cur, n, base, mask, lo, span);
+            hist_escape(s_h, bins, lo, span);
+            if (more) {
+#pragma unroll
+                for (int k = 0; k < ITEMS; ++k)
+                    cur[k] = nxt[k];
             }
+        } else {
+            hist_load<ITEMS>(keys, n, base, cur);
+            hist_count_all<ITEMS>(s_h, cur, n, base, mask, lo, span);
+            hist_escape(s_h, bins, lo, span);
         }
-        hist_escape(s_h, bins, lo, span);
     }
-    GF_GLOBAL uint32_t *row = gptr(rows_) + worker * kHistPart;
-    for (uint32_t i = threadIdx.x; i < span; i += blockDim.x)
-        row[i] = (s_h[i >> 1] >> ((i & 1u) * 16u)) & 0xFFFFu;
+    // the packed LDS word holds bins 2w (low half) and 2w+1 (high half): as
+    // a 32-bit store it lays down the two 16-bit row entries in order
+    GF_GLOBAL uint32_t *row = gptr(rows_) + worker * (kHistPart / 2);
+    for (uint32_t wd = threadIdx.x; wd < (span + 1) / 2; wd += blockDim.x)
+        row[wd] = s_h[wd];
 }
 
-// Histogram, phase 2: bins[b] += sum over the workers of b's part of their
-// partial rows, in ascending worker order. Bins [b0, b1) by stride.
-__device__ __forceinline__ void hist_merge(uint32_t *bins_, const uint32_t *rows_, uint32_t mask, int64_t G,
+__device__ __forceinline__ void hist_phase1(const uint32_t *keys, uint32_t *bins, uint32_t *rows, uint32_t mask,
+                                            int64_t n, int64_t worker, int64_t G, const Tiling &t)
+{
+    __shared__ uint32_t s_h[kHistPart / 2];
+    switch (t.items) {
+    case 1: hist_phase1_t<1>(s_h, keys, bins, rows, mask, n, worker, G, t); break;
+    case 2: hist_phase1_t<2>(s_h, keys, bins, rows, mask, n, worker, G, t); break;
+    case 4: hist_phase1_t<4>(s_h, keys, bins, rows, mask, n, worker, G, t); break;
+    default: hist_phase1_t<8>(s_h, keys, bins, rows, mask, n, worker, G, t); break;
+    }
+}
+
+// Histogram, phase 2: bins[b] += the sum of b's entries over the `rows_used`
+// partial rows (row w holds part w % parts). A work unit is four adjacent
+// bins times one slice of the rows (every S-th row of the part, S chosen so
+// the units cover the threads); its four sums go to the bins with integer
+// atomics, exact in any order. Threads [first, first + stride) share the
+// units.
+__device__ __forceinline__ void hist_merge(uint32_t *bins_, const uint32_t *rows_, uint32_t mask, int64_t rows_used,
                                            int64_t first, int64_t stride)
 {
     GF_GLOBAL uint32_t *bins = gptr(bins_);
-    GF_GLOBAL const uint32_t *rows = gptr(rows_);
+    GF_GLOBAL const uint16_t *rows = (GF_GLOBAL const uint16_t *)gptr(rows_);
     const int64_t nbins = (int64_t)mask + 1;
     const int64_t parts = cdiv(nbins, kHistPart);
-    for (int64_t b = first; b < nbins; b += stride) {
-        const int64_t part = b / kHistPart;
-        const int64_t off = b - part * kHistPart;
-        uint32_t sum = 0;
-        for (int64_t w = part; w < G; w += parts)
-            sum += rows[w * kHistPart + off];
-        bins[b] += sum;
+    const int64_t quads = cdiv(nbins, 4);
+    const int64_t per_part = rows_used / parts;  // rows of each part
+    int64_t S = stride / quads;
+    S = S < 1 ? 1 : (S > per_part ? per_part : S);
+    for (int64_t u = first; u < quads * S; u += stride) {
+        const int64_t q = u % quads;
+        const int64_t sl = u / quads;
+        const int64_t b0 = q * 4;
+        const int64_t part = b0 / kHistPart;
+        const int64_t off = b0 - part * kHistPart;
+        uint32_t s0 = 0, s1 = 0, s2 = 0, s3 = 0;
+        for (int64_t j = sl; j < per_part; j += S) {
+            const int64_t w = part + j * parts;
+            typedef uint16_t gf_h4 __attribute__((ext_vector_type(4)));
+            const gf_h4 r = *(GF_GLOBAL const gf_h4 *)(rows + w * kHistPart + off);
+            s0 += r.x;
+            s1 += r.y;
+            s2 += r.z;
+            s3 += r.w;
+        }
+        if (s0)
+            __hip_atomic_fetch_add(&bins[b0], s0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        if (s1 && b0 + 1 < nbins)
+            __hip_atomic_fetch_add(&bins[b0 + 1], s1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        if (s2 && b0 + 2 < nbins)
+            __hip_atomic_fetch_add(&bins[b0 + 2], s2, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        if (s3 && b0 + 3 < nbins)
+            __hip_atomic_fetch_add(&bins[b0 + 3], s3, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     }
 }
 
@@ -1104,10 +1208,13 @@ int64_t hist_parts(uint32_t mask) { return cdiv((int64_t)mask + 1, kHistPart); }
 hipError_t launch_hist_merge(const RegionLaunch &rl, int64_t rows_used, const Scratch &scr, const RpcRing &rpc,
                              int num_cu, hipStream_t s)
 {
+    // one thread per (four bins, slice of up to 16 rows of the part)
     const int64_t nbins = (int64_t)rl.step.mask + 1;
-    int64_t g = cdiv(nbins, kMaxWg);
-    if (g > (int64_t)num_cu * 4)
-        g = (int64_t)num_cu * 4;
+    const int64_t per_part = rows_used / cdiv(nbins, kHistPart);
+    const int64_t slices = per_part < 16 ? (per_part < 1 ? 1 : per_part) : 16;
+    int64_t g = cdiv(cdiv(nbins, 4) * slices, kMaxWg);
+    if (g > (int64_t)num_cu * 16)
+        g = (int64_t)num_cu * 16;
     hipLaunchKernelGGL(k_hist_merge, dim3((unsigned)g), dim3(kMaxWg), 0, s, rl, rows_used, scr, rpc);
     return hipGetLastError();
 }

@@ -203,7 +203,7 @@ def _hist_run(gfx, keys, nbins, mode, launch=None, init=None):
 
 @pytest.mark.parametrize("mode", ["persistent", "per_region", "graph"])
 @pytest.mark.parametrize("n,nbins", [(0, 65536), (1, 65536), (13, 256), (100003, 65536), (1 << 20, 1024),
-                                      ((1 << 20) + 7, 65536), (3 << 18, 1 << 20)])
+                                      ((1 << 20) + 7, 65536), (3 << 18, 1 << 20), (1001, 1), (1001, 2), (5, 4)])
 def test_hist_uniform_bit_exact(gfx, oracle_lib, mode, n, nbins):
     import paper_2306_11686_amd as gf
     print(f"hist n={n} nbins={nbins} mode={mode}", flush=True)
