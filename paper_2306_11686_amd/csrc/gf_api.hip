@@ -621,6 +621,34 @@ gf_status build_program(gf_ctx *ctx, const gf_program *prog, DProg *out)
     }
     if (program_mixes_hist(*out))
         return fail(ctx, GF_EUNSUPPORTED, "a histogram region can only share a program with schedule regions");
+    // last region in execution order and the number of grid barriers (a
+    // histogram region has one inside it)
+    out->last_region = -1;
+    int64_t bar_pro = 0, bar_body = 0;
+    for (int i = 0; i < out->n_steps; ++i) {
+        if (!is_region(out->steps[i].kind))
+            continue;
+        const int64_t b = out->steps[i].kind == GF_R_HIST ? 2 : 1;
+        if (i < out->n_pro) {
+            bar_pro += b;
+            out->last_region = i;
+        } else {
+            bar_body += b;
+        }
+    }
+    if (out->iters > 0)
+        for (int i = out->n_pro; i < out->n_steps; ++i)
+            if (is_region(out->steps[i].kind))
+                out->last_region = (int64_t)out->n_pro + (int64_t)(out->iters - 1) * out->n_body + (i - out->n_pro);
+    out->barriers = bar_pro + bar_body * out->iters;
+    if (out->last_region >= 0) {
+        // the persistent kernel skips the barrier after the last region
+        // when that region has no reduction
+        const int64_t lr = out->last_region;
+        const int si = lr < out->n_pro ? (int)lr : out->n_pro + (int)((lr - out->n_pro) % out->n_body);
+        if (out->steps[si].red_op == GF_OP_NONE)
+            out->barriers -= 1;
+    }
     return GF_OK;
 }
 
@@ -922,7 +950,7 @@ gf_status run_batched(gf_ctx *ctx, const DProg &p, const gf_instance *inst, int 
         for (int k = p.n_pro; k < p.n_steps; ++k)
             nb += is_region(p.steps[k].kind);
         stats->regions = n_inst * nb * p.iters;
-        stats->barriers = nb * p.iters;
+        stats->barriers = (int32_t)p.barriers;
     }
     return GF_OK;
 }
@@ -1031,7 +1059,12 @@ gf_status gf_region_run(gf_ctx *ctx, const gf_program *prog, const gf_instance *
             di.scal = inst[i].scal;
             std::memcpy(di.ip, inst[i].ip, sizeof di.ip);
             ctx->scr.epoch += 1;
-            hipError_t e = launch_persistent(p, di, t, grid, ctx->scr, ring_of(ctx), stream);
+            // the XCD barrier's per-launch registration costs a tree barrier:
+            // programs with few barriers keep the tree barrier
+            Scratch scr = ctx->scr;
+            if (p.barriers < kXcdBarrierMinBarriers)
+                scr.barrier_kind = kBarrierTree;
+            hipError_t e = launch_persistent(p, di, t, grid, scr, ring_of(ctx), stream);
             if (e != hipSuccess)
                 return hipfail(ctx, e, "persistent launch");
             if (stats) {
@@ -1045,7 +1078,7 @@ gf_status gf_region_run(gf_ctx *ctx, const gf_program *prog, const gf_instance *
                 for (int k = p.n_pro; k < p.n_steps; ++k)
                     nbody += is_region(p.steps[k].kind);
                 stats->regions += nreg + nbody * p.iters;
-                stats->barriers = nreg + nbody * p.iters;
+                stats->barriers = (int32_t)p.barriers;
             }
         }
         return GF_OK;

@@ -117,6 +117,13 @@ __device__ __forceinline__ void *uniform_ptr(void *p)
     return (void *)(((uint64_t)hi << 32) | lo);
 }
 
+__device__ __forceinline__ int64_t uniform_i64(int64_t v)
+{
+    const int lo = __builtin_amdgcn_readfirstlane((int)(uint32_t)v);
+    const int hi = __builtin_amdgcn_readfirstlane((int)(uint32_t)((uint64_t)v >> 32));
+    return (int64_t)(((uint64_t)(uint32_t)hi << 32) | (uint32_t)lo);
+}
+
 __device__ __forceinline__ double uniform_f64(double d)
 {
     const int lo = __builtin_amdgcn_readfirstlane(__double2loint(d));

@@ -36,7 +36,9 @@ struct DProg {
     int32_t n_pro;
     int32_t n_body;
     int32_t iters;
-    int32_t n_steps;  // n_pro + n_body
+    int32_t n_steps;      // n_pro + n_body
+    int64_t last_region;  // flattened step index of the last region executed (-1: none)
+    int64_t barriers;     // grid barriers one run executes
     DStep steps[kMaxDevSteps];
 };
 
@@ -124,6 +126,9 @@ constexpr int kBarrierTree = 0;  // every workgroup writes back and invalidates 
 constexpr int kBarrierXcd = 1;   // one write-back and one L2 invalidate per XCD
 // Below this grid size the tree barrier is cheaper (fewer serial hops).
 constexpr int kXcdBarrierMinWg = 96;
+// ... and for programs with fewer barriers than this (its per-launch
+// registration costs one tree barrier).
+constexpr int64_t kXcdBarrierMinBarriers = 8;
 
 constexpr int kHistRowsMax = 512;
 

@@ -696,6 +696,9 @@ __device__ __forceinline__ void hist_merge(uint32_t *bins_, const uint32_t *rows
         const int64_t part = b0 / kHistPart;
         const int64_t off = b0 - part * kHistPart;
         uint32_t s0 = 0, s1 = 0, s2 = 0, s3 = 0;
+        // unrolled so that several row loads are in flight per thread (the
+        // persistent kernel runs this with one workgroup per CU)
+#pragma unroll 8
         for (int64_t j = sl; j < per_part; j += S) {
             const int64_t w = part + j * parts;
             typedef uint16_t gf_h4 __attribute__((ext_vector_type(4)));
@@ -850,9 +853,10 @@ __global__ void __launch_bounds__(family_max_threads<KMASK>())
         be.part_off = 0;
     }
     const DInst &inst = batched ? batch.inst[be.inst] : inst_arg;
-    const int64_t G = be.gsize;
-    const int64_t member = be.member;
-    const int64_t worker = batched ? member : worker_id(blockIdx.x, G, t.xcd_remap);
+    // workgroup-uniform: kept in scalar registers
+    const int64_t G = uniform_i64(be.gsize);
+    const int64_t member = uniform_i64(be.member);
+    const int64_t worker = uniform_i64(batched ? member : worker_id(blockIdx.x, G, t.xcd_remap));
     uint32_t *gline = scr.lines + (int64_t)(kGroupLine0 + be.inst) * kLineWords;
     uint32_t *genw = batched ? gline + 1 : scr.lines + 1;  // generation word
     uint32_t *tree = scr.lines + kTreeLine0 * kLineWords;
@@ -907,6 +911,9 @@ __global__ void __launch_bounds__(family_max_threads<KMASK>())
         if (st.kind < 32) {
             const int64_t n = inst.ip[st.np];
             const bool red = st.red_op != GF_OP_NONE;
+            // after the last region, a region without a reduction needs no
+            // barrier: the serial steps that may follow touch no region data
+            const bool need_bar = red || si != prog.last_region;
             double *part = scr.partials + (parity ? scr.partials_cap : 0) + be.part_off;
             void *op[5];
 #pragma unroll
@@ -933,7 +940,7 @@ __global__ void __launch_bounds__(family_max_threads<KMASK>())
                             part[it] = v;
                     }
                 }
-                if (!barrier())
+                if (need_bar && !barrier())
                     return;
                 if (red) {
                     const double v = reduce_partials(st.red_op, part, nitems, s_red);
@@ -944,7 +951,7 @@ __global__ void __launch_bounds__(family_max_threads<KMASK>())
                 __syncthreads();
                 continue;
             }
-            if (!barrier())
+            if (need_bar && !barrier())
                 return;
         } else if (threadIdx.x == 0) {
             if (st.kind == GF_S_SWAP) {
