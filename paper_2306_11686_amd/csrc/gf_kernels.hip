@@ -878,6 +878,8 @@ __global__ void __launch_bounds__(family_max_threads<KMASK>())
         s_scal[threadIdx.x] = inst.scal[threadIdx.x];
     if (threadIdx.x < GF_MAX_ARRAYS)
         s_arr[threadIdx.x] = inst.arr[threadIdx.x];
+    const int n_pro = prog.n_pro, n_steps = prog.n_steps;
+    const int64_t last_region = prog.last_region;
     if (threadIdx.x == 0) {
         s_bar.gen = __hip_atomic_load(genw, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         s_bar.ok = 1;
@@ -895,17 +897,20 @@ __global__ void __launch_bounds__(family_max_threads<KMASK>())
     }
 
     int parity = 0;
-    const int64_t total = (int64_t)prog.n_pro + (int64_t)prog.iters * prog.n_body;
+    const int64_t total = (int64_t)n_pro + (int64_t)prog.iters * prog.n_body;
+    // (sidx, iter): the step and the body iteration of flattened step si,
+    // advanced incrementally
+    int sidx = 0;
+    int32_t iter = n_pro > 0 ? -1 : 0;
     for (int64_t si = 0; si < total; ++si) {
-        int sidx;
-        int32_t iter;
-        if (si < prog.n_pro) {
-            sidx = (int)si;
-            iter = -1;
-        } else {
-            const int64_t k = si - prog.n_pro;
-            sidx = prog.n_pro + (int)(k % prog.n_body);
-            iter = (int32_t)(k / prog.n_body);
+        if (si > 0) {
+            ++sidx;
+            if (sidx == n_steps) {
+                sidx = n_pro;
+                ++iter;
+            } else if (sidx == n_pro) {
+                iter = 0;
+            }
         }
         const DStep &st = prog.steps[sidx];
         if (st.kind < 32) {
@@ -913,7 +918,7 @@ __global__ void __launch_bounds__(family_max_threads<KMASK>())
             const bool red = st.red_op != GF_OP_NONE;
             // after the last region, a region without a reduction needs no
             // barrier: the serial steps that may follow touch no region data
-            const bool need_bar = red || si != prog.last_region;
+            const bool need_bar = red || si != last_region;
             double *part = scr.partials + (parity ? scr.partials_cap : 0) + be.part_off;
             void *op[5];
 #pragma unroll
@@ -968,7 +973,10 @@ __global__ void __launch_bounds__(family_max_threads<KMASK>())
                 serial_scalar(st.kind, st.sc, st.c, s_scal);
             }
         }
-        __syncthreads();
+        // consecutive serial steps run back to back on thread 0; the
+        // workgroup synchronises before the next region reads their results
+        if (st.kind < 32 || si + 1 == total || prog.steps[sidx + 1 == n_steps ? n_pro : sidx + 1].kind < 32)
+            __syncthreads();
     }
     if (member == 0 && threadIdx.x < GF_MAX_SCALARS)
         inst.scal[threadIdx.x] = s_scal[threadIdx.x];
