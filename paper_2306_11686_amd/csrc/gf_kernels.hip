@@ -451,8 +451,11 @@ __device__ __forceinline__ void spmv_item(const int32_t *rowptr_, const int32_t 
     const int64_t r1 = r0 + R < n ? r0 + R : n;
     const int64_t row = r0 + threadIdx.x;
     const bool mine = threadIdx.x < R && row < r1;
+    // the block's extent and this thread's row extent, requested together
     const int32_t k0 = rowptr[r0];
     const int32_t nnz = rowptr[r1] - k0;
+    const int32_t rb = mine ? rowptr[row] : 0;
+    const int32_t re = mine ? rowptr[row + 1] : 0;
     if (nnz <= kSpmvLds) {
         const int32_t B = (int32_t)blockDim.x;
         for (int32_t base = (int32_t)threadIdx.x; base < nnz; base += kSpmvUnroll * B) {
@@ -474,20 +477,51 @@ __device__ __forceinline__ void spmv_item(const int32_t *rowptr_, const int32_t 
         }
         __syncthreads();
         if (mine) {
-            const int32_t b = rowptr[row] - k0, e = rowptr[row + 1] - k0;
+            // column order, as the serial loop; products read eight at a time
+            const int32_t b = rb - k0, e = re - k0;
             double acc = 0.0;
-            for (int32_t k = b; k < e; ++k)
+            int32_t k = b;
+            for (; k + 8 <= e; k += 8) {
+                double p[8];
+#pragma unroll
+                for (int j = 0; j < 8; ++j)
+                    p[j] = s_prod[k + j];
+#pragma unroll
+                for (int j = 0; j < 8; ++j)
+                    acc = acc + p[j];
+            }
+            for (; k < e; ++k)
                 acc = acc + s_prod[k];
             y[row] = acc;
         }
         __syncthreads();
     } else if (mine) {
         double acc = 0.0;
-        const int32_t e = rowptr[row + 1];
-        for (int32_t k = rowptr[row]; k < e; ++k)
+        for (int32_t k = rb; k < re; ++k)
             acc = acc + val[k] * x[col[k]];
         y[row] = acc;
     }
+}
+
+// dot and axpby: a work item is `items` rows of blockDim.x consecutive
+// elements; each thread requests all of its elements before using them.
+template <int ITEMS>
+__device__ __forceinline__ double dot_item_t(GF_GLOBAL const double *__restrict__ a,
+                                             GF_GLOBAL const double *__restrict__ b, int64_t n, int64_t base)
+{
+    double av[ITEMS], bv[ITEMS];
+#pragma unroll
+    for (int k = 0; k < ITEMS; ++k) {
+        const int64_t i = base + (int64_t)k * blockDim.x + threadIdx.x;
+        av[k] = i < n ? a[i] : 0.0;
+        bv[k] = i < n ? b[i] : 0.0;
+    }
+    double acc = 0.0;
+#pragma unroll
+    for (int k = 0; k < ITEMS; ++k)
+        if (base + (int64_t)k * blockDim.x + threadIdx.x < n)
+            acc = acc + av[k] * bv[k];
+    return acc;
 }
 
 __device__ __forceinline__ double dot_item(const double *a_, const double *b_, int64_t n, int64_t item,
@@ -496,6 +530,13 @@ __device__ __forceinline__ double dot_item(const double *a_, const double *b_, i
     GF_GLOBAL const double *__restrict__ a = gptr(a_);
     GF_GLOBAL const double *__restrict__ b = gptr(b_);
     const int64_t base = item * chunk_elems(t);
+    switch (t.items) {
+    case 1: return dot_item_t<1>(a, b, n, base);
+    case 2: return dot_item_t<2>(a, b, n, base);
+    case 4: return dot_item_t<4>(a, b, n, base);
+    case 8: return dot_item_t<8>(a, b, n, base);
+    default: break;
+    }
     double acc = 0.0;
     for (int k = 0; k < t.items; ++k) {
         const int64_t i = base + (int64_t)k * blockDim.x + threadIdx.x;
@@ -505,6 +546,27 @@ __device__ __forceinline__ double dot_item(const double *a_, const double *b_, i
     return acc;
 }
 
+template <int ITEMS>
+__device__ __forceinline__ void axpby_item_t(GF_GLOBAL double *out, GF_GLOBAL const double *x, double s,
+                                             GF_GLOBAL const double *y, int64_t n, int64_t base)
+{
+    double xv[ITEMS], yv[ITEMS];
+#pragma unroll
+    for (int k = 0; k < ITEMS; ++k) {
+        const int64_t i = base + (int64_t)k * blockDim.x + threadIdx.x;
+        xv[k] = i < n ? x[i] : 0.0;
+        yv[k] = i < n ? y[i] : 0.0;
+    }
+#pragma unroll
+    for (int k = 0; k < ITEMS; ++k) {
+        const int64_t i = base + (int64_t)k * blockDim.x + threadIdx.x;
+        if (i < n)
+            out[i] = xv[k] + s * yv[k];
+    }
+}
+
+// out may alias x or y: every element is read before it is written, by the
+// same thread.
 __device__ __forceinline__ void axpby_item(double *out_, const double *x_, double s, const double *y_, int64_t n,
                                            int64_t item, const Tiling &t)
 {
@@ -512,6 +574,13 @@ __device__ __forceinline__ void axpby_item(double *out_, const double *x_, doubl
     GF_GLOBAL const double *x = gptr(x_);
     GF_GLOBAL const double *y = gptr(y_);
     const int64_t base = item * chunk_elems(t);
+    switch (t.items) {
+    case 1: axpby_item_t<1>(out, x, s, y, n, base); return;
+    case 2: axpby_item_t<2>(out, x, s, y, n, base); return;
+    case 4: axpby_item_t<4>(out, x, s, y, n, base); return;
+    case 8: axpby_item_t<8>(out, x, s, y, n, base); return;
+    default: break;
+    }
     for (int k = 0; k < t.items; ++k) {
         const int64_t i = base + (int64_t)k * blockDim.x + threadIdx.x;
         if (i < n)
