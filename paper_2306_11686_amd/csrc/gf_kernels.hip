@@ -435,9 +435,19 @@ __device__ __forceinline__ double j2_item(const double *u_, double *w_, int64_t 
 // sums its own row serially in stored column order, exactly as the legacy
 // loop does (same products, same order, no contraction). Blocks with more
 // nonzeros than the LDS tile fall back to one thread per row.
-constexpr int kSpmvLds = 4096;  // doubles (32 KiB)
+constexpr int kSpmvLds = 4096;        // doubles (32 KiB) per workgroup
+constexpr int kSpmvWaveRows = 32;     // rows per wavefront
+constexpr int kSpmvWaveLds = kSpmvLds / (kMaxWg / kWave);  // product slots per wavefront
 constexpr int kSpmvUnroll = 8;
 
+// CSR SpMV, one work item = wg_size / 2 consecutive rows, split into
+// 32-row slices, one per wavefront. A wavefront streams its slice's
+// nonzeros (coalesced col/val loads, eight in flight per lane, then the x
+// gathers) into its own LDS slice as products val * x[col]; then lane r sums
+// row r's products serially in column order (the serial loop's order, so y
+// is bit-exact). Wavefronts share no LDS and never wait for each other. A
+// slice whose nonzeros exceed its LDS share takes the direct row loop (same
+// order).
 __device__ __forceinline__ void spmv_item(const int32_t *rowptr_, const int32_t *col_, const double *val_,
                                           const double *x_, double *y_, int64_t n, int64_t item, int64_t R)
 {
@@ -447,54 +457,63 @@ __device__ __forceinline__ void spmv_item(const int32_t *rowptr_, const int32_t 
     GF_GLOBAL const double *__restrict__ val = gptr(val_);
     GF_GLOBAL const double *__restrict__ x = gptr(x_);
     GF_GLOBAL double *__restrict__ y = gptr(y_);
-    const int64_t r0 = item * R;
-    const int64_t r1 = r0 + R < n ? r0 + R : n;
-    const int64_t row = r0 + threadIdx.x;
-    const bool mine = threadIdx.x < R && row < r1;
-    // the block's extent and this thread's row extent, requested together
-    const int32_t k0 = rowptr[r0];
-    const int32_t nnz = rowptr[r1] - k0;
+    const int lane = threadIdx.x & (kWave - 1);
+    const int wv = threadIdx.x / kWave;
+    double *slot = s_prod + wv * kSpmvWaveLds;
+    const int64_t blk = item * R;
+    const int64_t blk_end = blk + R < n ? blk + R : n;
+    const int64_t a = blk + (int64_t)wv * kSpmvWaveRows;
+    if (a >= blk_end)
+        return;
+    const int64_t b = a + kSpmvWaveRows < blk_end ? a + kSpmvWaveRows : blk_end;
+    const int64_t row = a + lane;
+    const bool mine = row < b;
+    // the slice's extent and this lane's row extent, requested together
+    const int32_t k0 = rowptr[a];
+    const int32_t nnz = rowptr[b] - k0;
     const int32_t rb = mine ? rowptr[row] : 0;
     const int32_t re = mine ? rowptr[row + 1] : 0;
-    if (nnz <= kSpmvLds) {
-        const int32_t B = (int32_t)blockDim.x;
-        for (int32_t base = (int32_t)threadIdx.x; base < nnz; base += kSpmvUnroll * B) {
+    if (nnz <= kSpmvWaveLds) {
+        for (int32_t base = lane; base < nnz; base += kSpmvUnroll * kWave) {
             int32_t c[kSpmvUnroll];
             double v[kSpmvUnroll], xv[kSpmvUnroll];
 #pragma unroll
             for (int j = 0; j < kSpmvUnroll; ++j) {
-                const int32_t kk = base + j * B;
+                const int32_t kk = base + j * kWave;
                 c[j] = kk < nnz ? col[k0 + kk] : 0;
                 v[j] = kk < nnz ? val[k0 + kk] : 0.0;
             }
 #pragma unroll
             for (int j = 0; j < kSpmvUnroll; ++j)
-                xv[j] = base + j * B < nnz ? x[c[j]] : 0.0;
+                xv[j] = base + j * kWave < nnz ? x[c[j]] : 0.0;
 #pragma unroll
             for (int j = 0; j < kSpmvUnroll; ++j)
-                if (base + j * B < nnz)
-                    s_prod[base + j * B] = v[j] * xv[j];
+                if (base + j * kWave < nnz)
+                    slot[base + j * kWave] = v[j] * xv[j];
         }
-        __syncthreads();
+        // the wavefront's LDS writes complete before its lanes read them
+        __builtin_amdgcn_s_waitcnt(0xC07F);  // lgkmcnt(0)
+        __builtin_amdgcn_wave_barrier();
         if (mine) {
-            // column order, as the serial loop; products read eight at a time
-            const int32_t b = rb - k0, e = re - k0;
+            const int32_t e = re - k0;
             double acc = 0.0;
-            int32_t k = b;
+            int32_t k = rb - k0;
             for (; k + 8 <= e; k += 8) {
                 double p[8];
 #pragma unroll
                 for (int j = 0; j < 8; ++j)
-                    p[j] = s_prod[k + j];
+                    p[j] = slot[k + j];
 #pragma unroll
                 for (int j = 0; j < 8; ++j)
                     acc = acc + p[j];
             }
             for (; k < e; ++k)
-                acc = acc + s_prod[k];
+                acc = acc + slot[k];
             y[row] = acc;
         }
-        __syncthreads();
+        // the next item's writes to this slice wait for these reads
+        __builtin_amdgcn_s_waitcnt(0xC07F);
+        __builtin_amdgcn_wave_barrier();
     } else if (mine) {
         double acc = 0.0;
         for (int32_t k = rb; k < re; ++k)
