@@ -54,7 +54,7 @@ __host__ __device__ inline int64_t chunk_elems(const Tiling &t) { return (int64_
 
 // SpMV rows per work item: half the workgroup, so a block of a stencil-like
 // matrix (<= 32 nonzeros per row) fits the 4096-product LDS tile.
-__host__ __device__ inline int64_t spmv_rows(const Tiling &t) { return t.wg_size / 4; }
+__host__ __device__ inline int64_t spmv_rows(const Tiling &t) { return t.wg_size / 2; }
 
 // Histogram work: chunks of wg_size * items * 4 keys (each thread reads
 // `items` 16-byte groups of four keys); every chunk is counted once per part
@@ -435,14 +435,13 @@ __device__ __forceinline__ double j2_item(const double *u_, double *w_, int64_t 
 // sums its own row serially in stored column order, exactly as the legacy
 // loop does (same products, same order, no contraction). Blocks with more
 // nonzeros than the LDS tile fall back to one thread per row.
-constexpr int kSpmvLds = 2048;        // doubles (16 KiB) per workgroup
-constexpr int kSpmvWaveRows = 16;     // rows per wavefront
+constexpr int kSpmvLds = 4096;        // doubles (32 KiB) per workgroup
+constexpr int kSpmvWaveRows = 32;     // rows per wavefront
 constexpr int kSpmvWaveLds = kSpmvLds / (kMaxWg / kWave);  // product slots per wavefront
 constexpr int kSpmvUnroll = 8;
 
-// CSR SpMV, one work item = wg_size / 4 consecutive rows, split into
-// 16-row slices, one per wavefront (small LDS slots keep more wavefronts per
-// CU: the kernel is latency-bound). A wavefront streams its slice's
+// CSR SpMV, one work item = wg_size / 2 consecutive rows, split into
+// 32-row slices, one per wavefront. A wavefront streams its slice's
 // nonzeros (coalesced col/val loads, eight in flight per lane, then the x
 // gathers) into its own LDS slice as products val * x[col]; then lane r sums
 // row r's products serially in column order (the serial loop's order, so y
