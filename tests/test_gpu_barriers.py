@@ -85,3 +85,21 @@ def test_histogram_barrier_exact(xctx):
     xctx.run(prog, inst, mode=gf.GF_EXEC_PERSISTENT)
     xctx.sync()
     assert np.array_equal(host(keep[1]).view(np.uint32).astype(np.int64), ref)
+
+
+def test_barrier_stress_many_sweeps(xctx, oracle_lib):
+    """40,000 barriers in one persistent launch with 1,024 work items over
+    256 workgroups: every sweep reads planes other workgroups wrote in the
+    previous one, so a barrier that let a workgroup through early would break
+    bit-exactness against the serial oracle (the grid decays as
+    cos(pi/33)^k and stays far from underflow)."""
+    import paper_2306_11686_amd as gf
+    n, sweeps = 34, 40000
+    print(f"barrier stress jacobi3d n={n} sweeps={sweeps}", flush=True)
+    u0 = gi.grid3d(n, seed=9)
+    g_ref, r_ref = oracle_lib.jacobi3d(u0, sweeps)
+    launch = gf.Launch.make(tile_y=1, tile_z=1, num_wg=256)
+    g, r, st = run_jacobi3d(xctx, u0, sweeps, gf.GF_EXEC_PERSISTENT, launch=launch)
+    assert st["num_wg"] == 256 and st["barriers"] == sweeps
+    assert np.array_equal(r, r_ref)
+    assert np.array_equal(g, g_ref)

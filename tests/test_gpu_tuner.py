@@ -127,3 +127,50 @@ def test_region_run_without_launch_uses_installed_predictor(oracle_lib):
         assert st["candidate"] == -1
     finally:
         ctx.close()
+
+
+def test_nest_features_dot_axpby(gfx):
+    import paper_2306_11686_amd as gf
+    import torch
+    sc = scalars()
+    x = torch.zeros(1000, dtype=torch.float64, device="cuda")
+    dot = gf.Program.make([gf.Step.make(gf.GF_R_DOT, arr=(0, 1), sc=(0,), red_op=gf.GF_OP_SUM, np=0)], [], 0)
+    axpby = gf.Program.make([gf.Step.make(gf.GF_R_AXPBY, arr=(0, 0, 1), sc=(-1, 1), c=1.0, np=0)], [], 0)
+    inst = gf.Instance.make({0: x, 1: x}, sc, ip=(1000,))
+    assert gfx.nest_features(dot, inst) == [1000, 16, 2, 0, 1, 0, 1, 8]
+    assert gfx.nest_features(axpby, inst) == [1000, 24, 2, 0, 0, 0, 1, 8]
+    # instance count is the seventh feature
+    assert gfx.nest_features(dot, [inst, inst, inst])[6] == 3
+
+
+def test_predict_launch_skips_candidates_that_cannot_run():
+    """The predictor's favourite (tile_y 8 with three workgroups per CU)
+    exceeds the persistent kernel's co-resident capacity at that tile
+    height; the launch-time choice takes the best runnable candidate."""
+    import torch
+    import paper_2306_11686_amd as gf
+    from paper_2306_11686_amd import programs
+    ctx = gf.Context(0)
+    try:
+        n = 66
+        u = dev(np.zeros((n, n, n)))
+        w = u.clone()
+        res = torch.zeros(2, dtype=torch.float64, device="cuda")
+        sc = scalars()
+        inst = gf.Instance.make({0: u, 1: w, 2: res}, sc, ip=(n,))
+        prog = programs.jacobi3d(2)
+        cap = ctx.capacity(prog, 0)           # default tile_y 8
+        assert cap < 3 * 256
+        p = np.zeros(gf.GF_MLP_NPARAMS, np.float32)
+        b3 = np.linspace(1.0, 2.0, gf.GF_MLP_OUT).astype(np.float32)
+        b3[3 + 16] = 0.0                      # tile_y 8, 3 workgroups per CU: cannot run
+        b3[3] = 0.5                           # tile_y 8, default grid: runs
+        p[-gf.GF_MLP_OUT:] = b3
+        ctx.predictor_set(p, np.zeros(gf.GF_MLP_IN), np.full(gf.GF_MLP_IN, 1e3))
+        k, launch = ctx.predict_launch(prog, inst, mode=gf.GF_EXEC_PERSISTENT)
+        assert k == 3 and launch.tile_y == 8 and launch.num_wg == 0
+        # per-region launches need no co-residency: the favourite runs there
+        k, _ = ctx.predict_launch(prog, inst, mode=gf.GF_EXEC_PER_REGION)
+        assert k == 3 + 16
+    finally:
+        ctx.close()
