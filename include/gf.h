@@ -60,7 +60,7 @@ typedef enum {
     GF_ETIMEOUT = -4,     /* a device watchdog (barrier or RPC wait) expired */
     GF_ERPC = -5,         /* malformed RPC request */
     GF_EDEVICE = -6,      /* device reported an error (bad step, ring overflow) */
-    GF_EUNSUPPORTED = -7  /* valid request this build does not implement */
+    GF_EUNSUPPORTED = -7  /* valid request the library does not implement */
 } gf_status;
 
 typedef enum { GF_OP_SUM = 0, GF_OP_MAX = 1, GF_OP_NONE = -1 } gf_op;
@@ -75,7 +75,7 @@ typedef enum {
 #define GF_MAX_ARRAYS 16
 #define GF_MAX_SCALARS 16
 #define GF_MAX_IPARAMS 8
-#define GF_MAX_STEPS 64
+#define GF_MAX_STEPS 24    /* prologue + body steps of one program */
 #define GF_MAX_INSTANCES 4096
 
 /* ---- step kinds --------------------------------------------------------

@@ -12,7 +12,7 @@ namespace gf {
 // Persistent kernels receive the whole program by value as a kernel
 // argument (copied by the runtime at enqueue time, so the caller's structs
 // are free on return). 24 steps keep the argument block under 4 KiB.
-constexpr int kMaxDevSteps = 24;
+constexpr int kMaxDevSteps = GF_MAX_STEPS;
 constexpr int kMaxGlue = 8;
 constexpr int kWave = 64;
 constexpr int kNumXcd = 8;
