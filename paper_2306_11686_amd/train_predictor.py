@@ -33,6 +33,9 @@ def main():
     ap.add_argument("--seed", type=int, default=1)
     ap.add_argument("--out", default=None)
     ap.add_argument("--dataset", default=None, help="save/load the tuned dataset (.npz)")
+    ap.add_argument("--recheck", action="store_true",
+                    help="time the held-out nests again and score the predictor and the tuner's own choice "
+                         "on the fresh timings (the tuner's re-measurement floor)")
     args = ap.parse_args()
 
     import torch  # noqa: F401
@@ -88,9 +91,20 @@ def main():
         e = predictor.evaluate([pred_te[i] for i in idx], ms_te[idx], default_idx=[fixed_te[i] for i in idx])
         per_kind[k] = {"n": e["n"], "geomean_ratio": round(e["geomean_ratio"], 4),
                        "fixed_geomean_ratio": round(e.get("default_geomean_ratio", float("nan")), 4)}
+    recheck = None
+    if args.recheck:
+        _, ms_te2 = predictor.collect(ctx, specs_te, reps=args.reps, log=log)
+        tuner_pick = [int(np.argmin(np.where(np.isfinite(r), r, np.inf))) for r in ms_te]
+        ev_pred2 = predictor.evaluate(pred_te, ms_te2)
+        ev_tuner2 = predictor.evaluate(tuner_pick, ms_te2)
+        recheck = {"predictor_geomean_ratio": round(ev_pred2["geomean_ratio"], 4),
+                   "predictor_frac_within_1_10": round(ev_pred2["frac_within_1_10"], 4),
+                   "tuner_geomean_ratio": round(ev_tuner2["geomean_ratio"], 4),
+                   "tuner_frac_within_1_10": round(ev_tuner2["frac_within_1_10"], 4)}
     tune_per_nest_ms = tune_s / max(1, len(specs_tr) + len(specs_te)) * 1e3
     model.update({"train_nests": args.train, "test_nests": args.test, "epochs": args.epochs, "lr": args.lr,
-                  "heldout": ev_te, "train_fit": ev_tr, "per_kind": per_kind, "fixed_shapes": fixed})
+                  "heldout": ev_te, "train_fit": ev_tr, "per_kind": per_kind, "fixed_shapes": fixed,
+                  "heldout_retimed": recheck})
     out = args.out or predictor.WEIGHTS
     predictor.save(model, out)
     line = {"metric": "launch-config predictor: geomean t(pred)/t(best) on held-out nests",
@@ -102,6 +116,8 @@ def main():
             "loss_first": round(hist[0], 5), "loss_last": round(hist[-1], 5),
             "train_seconds": round(train_s, 3), "inference_us_per_nest_host": round(infer_us, 2),
             "tuning_ms_per_nest": round(tune_per_nest_ms, 2)}
+    if recheck:
+        line["heldout_retimed"] = recheck
     print(json.dumps(line), flush=True)
     ctx.close()
 
