@@ -139,16 +139,38 @@ def measure_sync(ctx, gf, programs, tuner, torch, reps):
     return out
 
 
+def measure_rpc(ctx, gf, programs, tuner, torch, reps):
+    """RPC round trips: a persistent program whose body is one printf of an
+    int and a double, run 1000 times by one workgroup, posted (the device
+    continues at once) and blocking (the device waits until the host has
+    printed and marked the slot done); a server thread polls the ring."""
+    calls = 1000
+    fmt = ctx.register_format("call %d value %.6e\n", "id")
+    sc = torch.zeros(16, dtype=torch.float64, device="cuda")
+    inst = gf.Instance.make({}, sc, ip=())
+    out = {"config": "rpc_printf_1000_calls", "calls": calls}
+    for name, flags in (("posted", 0), ("blocking", gf.GF_STEP_BLOCKING)):
+        body = [gf.Step.make(gf.GF_S_SET, sc=(0,), c=3.25),
+                gf.Step.make(gf.GF_S_PRINTF, sc=(0,), every=1, fmt_id=fmt, nargs=2, flags=flags)]
+        prog = gf.Program.make([], body, calls)
+        launch = gf.Launch.make(num_wg=1)
+        ms = _time(ctx, torch, lambda: ctx.run(prog, inst, mode=gf.GF_EXEC_PERSISTENT, launch=launch), reps)
+        text = ctx.take_output()
+        out[name] = {"ms_per_run": round(ms, 3), "us_per_call": round(ms * 1e3 / calls, 2),
+                     "lines_captured": text.count("\n")}
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
-    ap.add_argument("--configs", default="sync,2d,cg,hist,batched")
+    ap.add_argument("--configs", default="sync,2d,rpc,cg,hist,batched")
     ap.add_argument("--reps", type=int, default=3)
     args = ap.parse_args()
     import torch
     import paper_2306_11686_amd as gf
     from paper_2306_11686_amd import programs, tuner
-    ctx = gf.Context(0, rpc_capture=True)
-    fns = {"sync": measure_sync, "2d": measure_2d, "cg": measure_cg, "hist": measure_hist,
+    ctx = gf.Context(0, rpc_capture=True, rpc_thread=True)
+    fns = {"sync": measure_sync, "2d": measure_2d, "rpc": measure_rpc, "cg": measure_cg, "hist": measure_hist,
            "batched": measure_batched}
     for c in args.configs.split(","):
         log(f"[measure] {c}")
