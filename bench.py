@@ -191,7 +191,8 @@ def main():
     per_region = None
     if not args.no_per_region:
         out = {}
-        for name, mode in (("per_region", gf.GF_EXEC_PER_REGION), ("per_region_graph", gf.GF_EXEC_PER_REGION_GRAPH)):
+        for name, mode in (("per_region", gf.GF_EXEC_PER_REGION), ("per_region_graph", gf.GF_EXEC_PER_REGION_GRAPH),
+                           ("kernel_split", gf.GF_EXEC_KERNEL_SPLIT)):
             log(f"[bench] {name}")
             pms, _, pst = time_mode(ctx, gf, torch, prog, inst, mode, launch, args.steps, args.warmup)
             out[name] = {"ms_per_step": round(pms, 3),

@@ -69,7 +69,11 @@ typedef enum { GF_F64 = 0, GF_U32 = 1, GF_U64 = 2, GF_I64 = 3 } gf_dtype;
 typedef enum {
     GF_EXEC_PER_REGION = 0,       /* one kernel launch per region (host walks the steps) */
     GF_EXEC_PERSISTENT = 1,       /* one cooperative launch; grid barrier between regions */
-    GF_EXEC_PER_REGION_GRAPH = 2  /* per-region launches captured once into a HIP graph */
+    GF_EXEC_PER_REGION_GRAPH = 2, /* per-region launches captured once into a HIP graph */
+    GF_EXEC_KERNEL_SPLIT = 3      /* the paper's kernel split (Section 3.3): a one-thread main
+                                     kernel runs the serial steps and asks the host by RPC to
+                                     launch each region, waiting for it; one instance; the call
+                                     returns when the program has finished */
 } gf_exec;
 
 #define GF_MAX_ARRAYS 16

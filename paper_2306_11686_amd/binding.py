@@ -13,7 +13,7 @@ _STATUS = {0: "GF_OK", -1: "GF_EINVAL", -2: "GF_ENOMEM", -3: "GF_EHIP", -4: "GF_
 
 GF_OP_SUM, GF_OP_MAX, GF_OP_NONE = 0, 1, -1
 GF_F64, GF_U32, GF_U64, GF_I64 = 0, 1, 2, 3
-GF_EXEC_PER_REGION, GF_EXEC_PERSISTENT, GF_EXEC_PER_REGION_GRAPH = 0, 1, 2
+GF_EXEC_PER_REGION, GF_EXEC_PERSISTENT, GF_EXEC_PER_REGION_GRAPH, GF_EXEC_KERNEL_SPLIT = 0, 1, 2, 3
 
 GF_R_JACOBI2D, GF_R_JACOBI3D, GF_R_SPMV, GF_R_DOT, GF_R_AXPBY, GF_R_HIST, GF_R_OWNER = 1, 2, 3, 4, 5, 6, 7
 GF_S_SET, GF_S_COPY, GF_S_DIV, GF_S_SQRT, GF_S_SWAP, GF_S_RECORD, GF_S_PRINTF = 32, 33, 34, 35, 36, 37, 38

@@ -125,6 +125,18 @@ struct gf_ctx {
     std::atomic<bool> stop{false};
 
     hipStream_t capture_stream = nullptr;
+    // kernel split: the run whose regions the main kernel requests by RPC
+    // (valid while `active`), launched on split_stream
+    hipStream_t split_stream = nullptr;
+    struct {
+        bool active = false;
+        DProg p;
+        gf_instance in;
+        Tiling t;
+        gf_launch l;
+        bool has_l = false;
+        int regions = 0, launches = 0, max_grid = 0;
+    } split;
     std::unordered_map<std::string, GraphEntry> graphs;
 
     // batched persistent launches: device table, pinned staging, and an
@@ -180,6 +192,8 @@ int64_t now_us()
         .count();
 }
 
+int64_t split_region(gf_ctx *ctx, int sidx, uint64_t perm);
+
 // Service requests; caller holds rpc_mu.
 int32_t poll_locked(gf_ctx *ctx, int32_t max_requests, int32_t timeout_us)
 {
@@ -191,7 +205,9 @@ int32_t poll_locked(gf_ctx *ctx, int32_t max_requests, int32_t timeout_us)
         const uint64_t seq = __atomic_load_n(&slot->seq, __ATOMIC_ACQUIRE);
         if (seq == ctx->next_ticket + 1) {
             int64_t ret = -1;
-            if (slot->callee == kCalleePrintf && slot->fmt_id < ctx->formats.size()) {
+            if (slot->callee == kCalleeRegion && slot->nargs == 3) {
+                ret = split_region(ctx, (int)slot->args[0], slot->args[2]);
+            } else if (slot->callee == kCalleePrintf && slot->fmt_id < ctx->formats.size()) {
                 const Format &f = ctx->formats[slot->fmt_id];
                 if (slot->nargs == f.sig.size()) {
                     int k = f.pad(buf, sizeof buf, f.fmt.c_str(), slot->args);
@@ -305,6 +321,8 @@ gf_status gf_ctx_create(int32_t hip_device, const gf_ctx_opts *opts, gf_ctx **ou
     ctx->capture = o.rpc_capture != 0;
     if (hipStreamCreateWithFlags(&ctx->capture_stream, hipStreamNonBlocking) != hipSuccess)
         ctx->capture_stream = nullptr;
+    if (hipStreamCreateWithFlags(&ctx->split_stream, hipStreamNonBlocking) != hipSuccess)
+        ctx->split_stream = nullptr;
     if (hipMalloc(&ctx->d_batch, kBatchBytes) != hipSuccess ||
         hipHostMalloc(&ctx->h_batch, kBatchBytes, hipHostMallocDefault) != hipSuccess ||
         hipEventCreateWithFlags(&ctx->batch_copied, hipEventDisableTiming) != hipSuccess) {
@@ -356,6 +374,8 @@ gf_status gf_ctx_destroy(gf_ctx *ctx)
     }
     if (ctx->capture_stream)
         hipStreamDestroy(ctx->capture_stream);
+    if (ctx->split_stream)
+        hipStreamDestroy(ctx->split_stream);
     if (ctx->batch_copied)
         hipEventDestroy(ctx->batch_copied);
     if (ctx->h_batch)
@@ -725,12 +745,70 @@ int region_grid(const gf_ctx *ctx, const DStep &s, int64_t items, const Tiling &
 // Walk the flattened step sequence of one instance, enqueueing one launch per
 // region; the serial steps that follow a region ride along as its glue (run
 // by its last workgroup); SWAPs are applied to the host's binding table.
+// Enqueue one region launch (a histogram region is two launches: counting,
+// then the merge that also runs the glue) with the per-region grid.
+gf_status launch_one(gf_ctx *ctx, const RegionLaunch &cur, const Tiling &t, const gf_launch *l, hipStream_t stream,
+                     int *launches, int *max_grid)
+{
+    const RpcRing rpc = ring_of(ctx);
+    int grid = 1;
+    if (is_region(cur.step.kind)) {
+        grid = region_grid(ctx, cur.step, cur.n_items, t);
+        if (l && l->num_wg > 0)
+            grid = cur.step.kind == GF_R_HIST ? hist_grid(l->num_wg, cur.step.mask) : l->num_wg;
+    }
+    if (cur.step.kind == GF_R_HIST) {
+        RegionLaunch p1 = cur;
+        p1.n_glue = 0;
+        hipError_t e = launch_region(p1, t, grid, ctx->scr, rpc, stream);
+        if (e == hipSuccess)
+            e = launch_hist_merge(cur, grid, ctx->scr, rpc, ctx->num_cu, stream);
+        if (e != hipSuccess)
+            return hipfail(ctx, e, "histogram launch");
+        *launches += 2;
+    } else {
+        hipError_t e = launch_region(cur, t, grid, ctx->scr, rpc, stream);
+        if (e != hipSuccess)
+            return hipfail(ctx, e, "region launch");
+        *launches += 1;
+    }
+    *max_grid = std::max(*max_grid, grid);
+    return GF_OK;
+}
+
+// Kernel split: launch region step `sidx` of the active run for the main
+// kernel, with the array slots permuted by `perm` (4 bits per slot), and
+// wait for it. Returns 0, or -1 if nothing could be launched. Runs on the
+// thread that polls the RPC ring (rpc_mu held).
+int64_t split_region(gf_ctx *ctx, int sidx, uint64_t perm)
+{
+    auto &sp = ctx->split;
+    if (!sp.active || sidx < 0 || sidx >= sp.p.n_steps || !is_region(sp.p.steps[sidx].kind) || !ctx->split_stream)
+        return -1;
+    const DStep &s = sp.p.steps[sidx];
+    RegionLaunch cur;
+    std::memset(&cur, 0, sizeof cur);
+    cur.step = s;
+    for (int k = 0; k < 5; ++k)
+        cur.arr[k] = s.arr[k] >= 0 ? sp.in.arr[(perm >> (4 * s.arr[k])) & 15u] : nullptr;
+    cur.scal = sp.in.scal;
+    cur.n = sp.in.ip[s.np];
+    cur.n_items = (int32_t)region_items(s, cur.n, sp.t);
+    cur.inst = 0;
+    if (launch_one(ctx, cur, sp.t, sp.has_l ? &sp.l : nullptr, ctx->split_stream, &sp.launches, &sp.max_grid) !=
+        GF_OK)
+        return -1;
+    if (hipStreamSynchronize(ctx->split_stream) != hipSuccess)
+        return -1;
+    sp.regions += 1;
+    return 0;
+}
+
 gf_status enqueue_per_region(gf_ctx *ctx, const DProg &p, const gf_instance &in, int inst_idx, const Tiling &t,
                              const gf_launch *l, hipStream_t stream, gf_run_stats *stats)
 {
     void *arr[GF_MAX_ARRAYS];
     std::memcpy(arr, in.arr, sizeof arr);
-    const RpcRing rpc = ring_of(ctx);
     RegionLaunch cur;
     bool pending = false;
     int launches = 0, regions = 0, max_grid = 0;
@@ -738,32 +816,8 @@ gf_status enqueue_per_region(gf_ctx *ctx, const DProg &p, const gf_instance &in,
     auto flush = [&]() -> gf_status {
         if (!pending)
             return GF_OK;
-        int grid = 1;
-        if (is_region(cur.step.kind)) {
-            grid = region_grid(ctx, cur.step, cur.n_items, t);
-            if (l && l->num_wg > 0)
-                grid = cur.step.kind == GF_R_HIST ? hist_grid(l->num_wg, cur.step.mask) : l->num_wg;
-        }
-        if (cur.step.kind == GF_R_HIST) {
-            RegionLaunch p1 = cur;
-            p1.n_glue = 0;
-            hipError_t e = launch_region(p1, t, grid, ctx->scr, rpc, stream);
-            if (e == hipSuccess)
-                e = launch_hist_merge(cur, grid, ctx->scr, rpc, ctx->num_cu, stream);
-            if (e != hipSuccess)
-                return hipfail(ctx, e, "histogram launch");
-            launches += 2;
-            max_grid = std::max(max_grid, grid);
-            pending = false;
-            return GF_OK;
-        }
-        hipError_t e = launch_region(cur, t, grid, ctx->scr, rpc, stream);
-        if (e != hipSuccess)
-            return hipfail(ctx, e, "region launch");
-        ++launches;
-        max_grid = std::max(max_grid, grid);
         pending = false;
-        return GF_OK;
+        return launch_one(ctx, cur, t, l, stream, &launches, &max_grid);
     };
     auto start_serial_only = [&]() {
         std::memset(&cur, 0, sizeof cur);
@@ -982,6 +1036,75 @@ struct CandidateNote {
 };
 }  // namespace
 
+// Kernel split: the main kernel (one thread) runs on `stream`; its region
+// requests are serviced by whoever polls the RPC ring — the library's server
+// thread, else this call, which polls until the main kernel has finished.
+gf_status run_kernel_split(gf_ctx *ctx, const DProg &p, const gf_instance &in, int n_inst, const Tiling &t,
+                           const gf_launch *launch, gf_run_stats *stats, hipStream_t stream)
+{
+    if (n_inst != 1)
+        return fail(ctx, GF_EUNSUPPORTED, "the kernel split runs one instance");
+    if (!ctx->split_stream)
+        return fail(ctx, GF_EHIP, "no stream for the split regions");
+    hipEvent_t ev = nullptr;
+    hipError_t e = hipEventCreateWithFlags(&ev, hipEventDisableTiming);
+    if (e != hipSuccess)
+        return hipfail(ctx, e, "event create");
+    {
+        std::lock_guard<std::mutex> g(ctx->rpc_mu);
+        auto &sp = ctx->split;
+        sp.active = true;
+        sp.p = p;
+        sp.in = in;
+        sp.t = t;
+        sp.has_l = launch != nullptr;
+        if (launch)
+            sp.l = *launch;
+        sp.regions = sp.launches = sp.max_grid = 0;
+    }
+    DInst di;
+    std::memcpy(di.arr, in.arr, sizeof di.arr);
+    di.scal = in.scal;
+    std::memcpy(di.ip, in.ip, sizeof di.ip);
+    e = launch_main(p, di, ring_of(ctx), ctx->scr, stream);
+    if (e == hipSuccess)
+        e = hipEventRecord(ev, stream);
+    if (e == hipSuccess) {
+        const bool serve = !ctx->server.joinable();
+        for (;;) {
+            const hipError_t q = hipEventQuery(ev);
+            if (q == hipSuccess)
+                break;
+            if (q != hipErrorNotReady) {
+                e = q;
+                break;
+            }
+            if (serve) {
+                std::lock_guard<std::mutex> g(ctx->rpc_mu);
+                poll_locked(ctx, 1 << 20, 0);
+            } else {
+                std::this_thread::yield();
+            }
+        }
+    }
+    {
+        std::lock_guard<std::mutex> g(ctx->rpc_mu);
+        // remaining posted requests (printf) are serviced before the run is released
+        poll_locked(ctx, 1 << 20, 0);
+        ctx->split.active = false;
+        if (stats) {
+            stats->regions = ctx->split.regions;
+            stats->launches = ctx->split.launches + 1;
+            stats->num_wg = ctx->split.max_grid;
+            stats->wg_size = t.wg_size;
+        }
+    }
+    hipEventDestroy(ev);
+    if (e != hipSuccess)
+        return hipfail(ctx, e, "kernel split run");
+    return GF_OK;
+}
+
 extern "C" {
 
 int32_t gf_persistent_capacity(gf_ctx *ctx, const gf_program *prog, int32_t wg_size)
@@ -1007,7 +1130,8 @@ gf_status gf_region_run(gf_ctx *ctx, const gf_program *prog, const gf_instance *
         return GF_EINVAL;
     if (!inst || n_inst < 1 || n_inst > GF_MAX_INSTANCES)
         return fail(ctx, GF_EINVAL, "need 1..%d instances", GF_MAX_INSTANCES);
-    if (mode != GF_EXEC_PER_REGION && mode != GF_EXEC_PERSISTENT && mode != GF_EXEC_PER_REGION_GRAPH)
+    if (mode != GF_EXEC_PER_REGION && mode != GF_EXEC_PERSISTENT && mode != GF_EXEC_PER_REGION_GRAPH &&
+        mode != GF_EXEC_KERNEL_SPLIT)
         return fail(ctx, GF_EINVAL, "unknown execution mode %d", mode);
     DProg p;
     gf_status st = build_program(ctx, prog, &p);
@@ -1094,6 +1218,9 @@ gf_status gf_region_run(gf_ctx *ctx, const gf_program *prog, const gf_instance *
         }
         return GF_OK;
     }
+
+    if (mode == GF_EXEC_KERNEL_SPLIT)
+        return run_kernel_split(ctx, p, inst[0], n_inst, t, launch, stats, stream);
 
     if (mode == GF_EXEC_PER_REGION) {
         for (int i = 0; i < n_inst; ++i)
@@ -1199,6 +1326,8 @@ gf_status gf_sync(gf_ctx *ctx, void *hip_stream, gf_run_stats *stats)
         hipMemcpy(ctx->scr.error, &zero, sizeof zero, hipMemcpyHostToDevice);
         if (code == kErrBarrierTimeout)
             return fail(ctx, GF_ETIMEOUT, "device: grid barrier watchdog expired");
+        if (code == kErrRegionLaunch)
+            return fail(ctx, GF_EHIP, "device: the host could not launch a region the main kernel requested");
         if (code == kErrRpcTimeout)
             return fail(ctx, GF_ETIMEOUT, "device: RPC wait watchdog expired (is a server polling?)");
         return fail(ctx, GF_EDEVICE, "device error code %d", code);

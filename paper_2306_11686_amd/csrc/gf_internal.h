@@ -91,7 +91,7 @@ struct alignas(128) RpcSlot {
 };
 static_assert(sizeof(RpcSlot) == 128, "RPC slot is one 128-byte line");
 
-enum : uint32_t { kCalleePrintf = 1 };
+enum : uint32_t { kCalleePrintf = 1, kCalleeRegion = 2 };
 
 // Device error word codes (sticky; first writer wins).
 enum : int32_t {
@@ -99,6 +99,7 @@ enum : int32_t {
     kErrBarrierTimeout = 1,
     kErrRpcTimeout = 2,
     kErrBadStep = 3,
+    kErrRegionLaunch = 4,  // the host could not launch a region requested by the main kernel
 };
 
 struct RpcRing {
@@ -198,6 +199,8 @@ hipError_t launch_persistent(const DProg &prog, const DInst &inst, const Tiling 
                              const Scratch &scr, const RpcRing &rpc, hipStream_t s,
                              const BatchTable *batch = nullptr);
 int persistent_capacity(const DProg &prog, const Tiling &t, int num_cu);
+hipError_t launch_main(const DProg &prog, const DInst &inst, const RpcRing &rpc, const Scratch &scr,
+                       hipStream_t s);
 hipError_t launch_region(const RegionLaunch &rl, const Tiling &t, int num_wg, const Scratch &scr,
                          const RpcRing &rpc, hipStream_t s);
 hipError_t launch_reduce(int op, int dt, const void *in, int64_t n, void *out, const Scratch &scr,

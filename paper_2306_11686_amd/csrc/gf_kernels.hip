@@ -1149,6 +1149,73 @@ __global__ void __launch_bounds__(family_max_threads<KMASK>()) k_region(RegionLa
     }
 }
 
+// ---------------------------------------------------------------------------
+// Kernel split (paper, Section 3.3): the main program runs on one thread of
+// a one-wavefront kernel; a region is a blocking RPC asking the host to
+// launch the region kernel and wait for it. Serial steps act directly on the
+// instance's scalar variables in device memory; SWAPs permute a table of the
+// array slots (4 bits per slot) that travels with each request. The RPC's
+// system-scope release and acquire order the main thread's scalar writes
+// before the region and the region's results before the next serial step.
+// ---------------------------------------------------------------------------
+
+__global__ void __launch_bounds__(kWave) k_main(DProg prog, DInst inst, RpcRing rpc, Scratch scr)
+{
+    if (threadIdx.x != 0)
+        return;
+    uint64_t perm = 0;
+    for (int k = 0; k < GF_MAX_ARRAYS; ++k)
+        perm |= (uint64_t)k << (4 * k);
+    auto slot_of = [&](int a) -> int { return (int)((perm >> (4 * a)) & 15u); };
+    double *scal = inst.scal;
+    const int64_t total = (int64_t)prog.n_pro + (int64_t)prog.iters * prog.n_body;
+    int sidx = 0;
+    int32_t iter = prog.n_pro > 0 ? -1 : 0;
+    for (int64_t si = 0; si < total; ++si) {
+        if (si > 0) {
+            ++sidx;
+            if (sidx == prog.n_steps) {
+                sidx = prog.n_pro;
+                ++iter;
+            } else if (sidx == prog.n_pro) {
+                iter = 0;
+            }
+        }
+        const DStep &st = prog.steps[sidx];
+        if (st.kind < 32) {
+            uint64_t args[3] = {(uint64_t)sidx, (uint64_t)(int64_t)iter, perm};
+            int64_t ret = -1;
+            if (!rpc_call(rpc, kCalleeRegion, 0, 3, args, GF_STEP_BLOCKING, &ret, scr.error))
+                return;
+            if (ret != 0) {
+                set_error(scr.error, kErrRegionLaunch);
+                return;
+            }
+        } else if (st.kind == GF_S_SWAP) {
+            const int a = st.arr[0], b = st.arr[1];
+            const uint64_t va = (perm >> (4 * a)) & 15u, vb = (perm >> (4 * b)) & 15u;
+            perm &= ~((uint64_t)15 << (4 * a)) & ~((uint64_t)15 << (4 * b));
+            perm |= (vb << (4 * a)) | (va << (4 * b));
+        } else if (st.kind == GF_S_RECORD) {
+            if (iter >= 0)
+                ((double *)inst.arr[slot_of(st.arr[0])])[iter] = scal[st.sc[0]];
+        } else if (st.kind == GF_S_PRINTF) {
+            if (iter >= 0 && st.every > 0 && (iter + 1) % st.every == 0)
+                serial_printf(rpc, st.fmt_id, st.nargs, st.flags, st.sc, iter, scal, scr.error);
+        } else {
+            serial_scalar(st.kind, st.sc, st.c, scal);
+        }
+    }
+    // the region kernels and the host read the scalars after the kernel ends
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "");
+}
+
+hipError_t launch_main(const DProg &prog, const DInst &inst, const RpcRing &rpc, const Scratch &scr, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_main, dim3(1), dim3(kWave), 0, s, prog, inst, rpc, scr);
+    return hipGetLastError();
+}
+
 // Histogram phase 2 of the per-region mode: merge the `rows_used` partial
 // rows of phase 1 into the bins; the last workgroup runs the glue.
 __global__ void __launch_bounds__(kMaxWg) k_hist_merge(RegionLaunch rl, int64_t rows_used, Scratch scr, RpcRing rpc)

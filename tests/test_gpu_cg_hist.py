@@ -21,7 +21,7 @@ pytestmark = pytest.mark.gpu
 
 def _mode(gf, name):
     return {"persistent": gf.GF_EXEC_PERSISTENT, "per_region": gf.GF_EXEC_PER_REGION,
-            "graph": gf.GF_EXEC_PER_REGION_GRAPH}[name]
+            "graph": gf.GF_EXEC_PER_REGION_GRAPH, "split": gf.GF_EXEC_KERNEL_SPLIT}[name]
 
 
 _MATS = {}
@@ -106,7 +106,7 @@ def test_dot_and_axpby_regions(gfx, oracle_lib, n, items):
         assert np.array_equal(host(tout), oracle_lib.axpby(a, -0.8125, b))
 
 
-@pytest.mark.parametrize("mode", ["persistent", "per_region", "graph"])
+@pytest.mark.parametrize("mode", ["persistent", "per_region", "graph", "split"])
 @pytest.mark.parametrize("m,iters", [(3, 20), (6, 40), (11, 30)])
 def test_cg_small_systems(gfx, oracle_lib, mode, m, iters):
     """Whole CG runs on small systems: the GPU rho history stays within the
@@ -201,7 +201,7 @@ def _hist_run(gfx, keys, nbins, mode, launch=None, init=None):
     return host(bins)
 
 
-@pytest.mark.parametrize("mode", ["persistent", "per_region", "graph"])
+@pytest.mark.parametrize("mode", ["persistent", "per_region", "graph", "split"])
 @pytest.mark.parametrize("n,nbins", [(0, 65536), (1, 65536), (13, 256), (100003, 65536), (1 << 20, 1024),
                                       ((1 << 20) + 7, 65536), (3 << 18, 1 << 20), (1001, 1), (1001, 2), (5, 4)])
 def test_hist_uniform_bit_exact(gfx, oracle_lib, mode, n, nbins):

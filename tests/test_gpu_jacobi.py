@@ -13,12 +13,12 @@ from tests.gpu_helpers import run_jacobi2d, run_jacobi3d
 
 pytestmark = pytest.mark.gpu
 
-MODES = ["persistent", "per_region", "graph"]
+MODES = ["persistent", "per_region", "graph", "split"]
 
 
 def _mode(gf, name):
     return {"persistent": gf.GF_EXEC_PERSISTENT, "per_region": gf.GF_EXEC_PER_REGION,
-            "graph": gf.GF_EXEC_PER_REGION_GRAPH}[name]
+            "graph": gf.GF_EXEC_PER_REGION_GRAPH, "split": gf.GF_EXEC_KERNEL_SPLIT}[name]
 
 
 @pytest.mark.parametrize("mode", MODES)
