@@ -115,6 +115,17 @@ typedef enum {
  *                RPC with arguments (int)(iter+1), scal[sc[0]] .. scal[sc[nargs-2]]
  *                (nargs counts the iteration argument). Posted (fire and
  *                forget) unless flags & GF_STEP_BLOCKING.
+ * GF_S_CALL      a host library call through RPC at call site fmt_id (from
+ *                gf_rpc_register_call). It fires once in the prologue, and
+ *                in the body when (iter+1) % every == 0. Reference arguments
+ *                are copied into the request and back by their access mode.
+ *                If sc[0] >= 0, scal[sc[0]] = the callee's return value (as a
+ *                double). A call with write or read-write references or a
+ *                return slot must be blocking (GF_STEP_BLOCKING).
+ *                GF_STEP_TIMED adds per-stage timing (gf_rpc_call_stats).
+ *                Persistent mode: the call runs on the first workgroup,
+ *                then a grid barrier publishes its writes to every
+ *                workgroup.
  */
 typedef enum {
     GF_R_JACOBI2D = 1,
@@ -130,10 +141,12 @@ typedef enum {
     GF_S_SQRT = 35,
     GF_S_SWAP = 36,
     GF_S_RECORD = 37,
-    GF_S_PRINTF = 38
+    GF_S_PRINTF = 38,
+    GF_S_CALL = 39
 } gf_step_kind;
 
 #define GF_STEP_BLOCKING 1u
+#define GF_STEP_TIMED 2u   /* GF_S_CALL: accumulate per-stage times */
 
 typedef struct {
     int32_t kind;      /* gf_step_kind */
@@ -142,9 +155,10 @@ typedef struct {
     int32_t red_op;    /* reduction clause of a region: GF_OP_SUM / GF_OP_MAX / GF_OP_NONE */
     int32_t np;        /* index into gf_instance.ip of the region's size */
     int32_t every;     /* GF_S_PRINTF period (iterations) */
-    int32_t fmt_id;    /* GF_S_PRINTF format id from gf_rpc_register_format */
+    int32_t fmt_id;    /* GF_S_PRINTF format id from gf_rpc_register_format;
+                          GF_S_CALL call-site id from gf_rpc_register_call */
     int32_t nargs;     /* GF_S_PRINTF argument count incl. the iteration number */
-    uint32_t flags;    /* GF_STEP_BLOCKING */
+    uint32_t flags;    /* GF_STEP_BLOCKING, GF_STEP_TIMED */
     uint32_t mask;     /* GF_R_HIST bin mask (nbins - 1, nbins a power of two) */
     int64_t chunk;     /* GF_R_OWNER schedule(static, chunk); 0 = schedule(static) */
     double c;          /* constant of GF_S_SET / GF_R_AXPBY */
@@ -195,10 +209,14 @@ typedef struct {
 typedef struct {
     int32_t rpc_slots;        /* ring slots (power of two, 8..4096); 0 = 256 */
     int32_t rpc_capture;      /* 1: landing pads append output to a buffer read by
-                                 gf_rpc_take_output instead of writing stdout */
+                                 gf_rpc_take_output instead of writing stdout (and,
+                                 for GF_S_CALL fprintf / fwrite, stdout or stderr) */
     int32_t rpc_thread;       /* 1: libgf runs the RPC server thread itself */
     int64_t rpc_timeout_us;   /* device watchdog for RPC slot waits; 0 = 2 s */
     int64_t barrier_timeout_us; /* device watchdog for grid barriers; 0 = 10 s */
+    int64_t rpc_payload;      /* payload bytes per ring slot for the objects of
+                                 GF_S_CALL references (multiple of 16, 16..65536);
+                                 0 = 1024 */
 } gf_ctx_opts;
 
 /* Create a context on HIP device `hip_device`: allocates the pinned RPC ring
@@ -243,6 +261,84 @@ int32_t gf_rpc_poll(gf_ctx *ctx, int32_t max_requests, int32_t timeout_us);
  * types: 'i' (64-bit int) or 'd' (double), e.g. "id". Returns id >= 0 or a
  * negative gf_status. The host landing pad is selected by (callee, sig). */
 int32_t gf_rpc_register_format(gf_ctx *ctx, const char *fmt, const char *sig);
+
+/* ---- general host calls (Section 3.2, "Generating Remote Procedural Calls")
+ * A call site names a host callee and describes each argument the way the
+ * device-side argument record of the paper does. Value arguments travel as
+ * 64-bit words; an opaque host pointer (such as a FILE *) is a value and is
+ * used by the host unchanged. A reference argument points into an object in
+ * device memory: the object (start, size) inside array slot `slot` of the
+ * instance, and the pointer's byte offset into it. Objects of read and
+ * read-write references are copied into the request's payload before the
+ * call; the host passes the callee a pointer at the same offset into its
+ * copy; objects of write and read-write references are copied back after
+ * the call (a write-only object is zero-filled on the host first, so bytes
+ * the callee does not write come back as zero). The host wrapper that makes
+ * the call is selected by (callee, argument types): one non-variadic landing
+ * pad per type signature of a variadic callee. */
+typedef enum {
+    GF_CALLEE_FPRINTF = 1,  /* int fprintf(FILE *f, const char *fmt, ...);
+                               fixed "pp", then up to 4 of 'i' 'd' 'p' */
+    GF_CALLEE_SNPRINTF = 2, /* int snprintf(char *buf, size_t n, const char *fmt, ...);
+                               fixed "pip", then up to 4 of 'i' 'd' 'p' */
+    GF_CALLEE_SSCANF = 3,   /* int sscanf(const char *s, const char *fmt, ...);
+                               fixed "pp", then up to 6 of 'p' */
+    GF_CALLEE_FWRITE = 4,   /* size_t fwrite(const void *p, size_t size, size_t n, FILE *f); "piip" */
+    GF_CALLEE_FREAD = 5     /* size_t fread(void *p, size_t size, size_t n, FILE *f); "piip" */
+} gf_callee;
+
+typedef enum {
+    GF_ARG_CONST = 0,   /* value: the word `value` (an integer, a double's bits, or a host pointer) */
+    GF_ARG_SCALAR = 1,  /* value: scal[slot] as a double ('d') or truncated to int64 ('i') */
+    GF_ARG_ITER = 2,    /* value: iter + 1 (0 in the prologue), type 'i' */
+    GF_ARG_REF = 3      /* reference into array slot `slot`, type 'p' */
+} gf_arg_kind;
+
+typedef enum { GF_REF_READ = 1, GF_REF_WRITE = 2, GF_REF_READWRITE = 3 } gf_ref_mode;
+
+#define GF_CALL_MAX_ARGS 8
+#define GF_CALL_MAX_REFS 4
+#define GF_CALL_MAX_SITES 64
+
+typedef struct {
+    int32_t kind;     /* gf_arg_kind */
+    int32_t type;     /* 'i' (int64), 'd' (double) or 'p' (pointer) */
+    int32_t slot;     /* GF_ARG_SCALAR: scalar slot; GF_ARG_REF: array slot */
+    int32_t mode;     /* GF_ARG_REF: gf_ref_mode */
+    int64_t value;    /* GF_ARG_CONST: the 64-bit word */
+    int64_t start;    /* GF_ARG_REF: byte offset of the object in the array */
+    int64_t size;     /* GF_ARG_REF: object bytes (>= 1) */
+    int64_t offset;   /* GF_ARG_REF: byte offset of the pointer into the object (0..size) */
+} gf_call_arg;
+
+/* Register a call site: callee (gf_callee) and nargs argument records.
+ * Checks the types against the callee's parameters, at most
+ * GF_CALL_MAX_REFS references, and that the objects (each rounded up to 16
+ * bytes) fit the slot payload. Returns the call-site id >= 0 or a negative
+ * gf_status (GF_EINVAL; GF_EUNSUPPORTED for a signature without a landing
+ * pad). The caller guarantees that each referenced object lies inside its
+ * array, and that host pointer values are valid on the host. */
+int32_t gf_rpc_register_call(gf_ctx *ctx, int32_t callee, const gf_call_arg *args, int32_t nargs);
+
+/* Average per-call stage times in microseconds of the GF_STEP_TIMED calls at
+ * one call site (paper, Section 5, RPC performance). The device stages use
+ * the GPU's 100 MHz constant clock; the host stages the host's monotonic
+ * clock. Valid after gf_sync. */
+typedef struct {
+    int64_t calls;           /* timed calls */
+    double dev_args_us;      /* device: take a ticket, wait for a free slot, build the argument words */
+    double dev_copy_in_us;   /* device: copy read and read-write objects into the payload */
+    double dev_wait_us;      /* device: publish the request until the completion flag is seen */
+    double dev_copy_out_us;  /* device: copy write and read-write objects back */
+    double host_decode_us;   /* host: read the request, translate references into payload pointers */
+    double host_call_us;     /* host: the landing pad (the library call) */
+    double host_reply_us;    /* host: store the return value and the completion flag */
+    double transit_us;       /* dev_wait_us minus the host stages: request and reply in flight
+                                plus the server's pickup delay */
+} gf_call_stats;
+
+/* Fill *out for call site `call_id`; reset != 0 clears its counters. */
+gf_status gf_rpc_call_stats(gf_ctx *ctx, int32_t call_id, gf_call_stats *out, int32_t reset);
 
 /* Copy captured landing-pad output (rpc_capture=1) into buf (NUL-terminated,
  * at most cap-1 bytes) and clear it. Returns bytes copied or gf_status. */

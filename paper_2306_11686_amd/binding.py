@@ -16,8 +16,14 @@ GF_F64, GF_U32, GF_U64, GF_I64 = 0, 1, 2, 3
 GF_EXEC_PER_REGION, GF_EXEC_PERSISTENT, GF_EXEC_PER_REGION_GRAPH, GF_EXEC_KERNEL_SPLIT = 0, 1, 2, 3
 
 GF_R_JACOBI2D, GF_R_JACOBI3D, GF_R_SPMV, GF_R_DOT, GF_R_AXPBY, GF_R_HIST, GF_R_OWNER = 1, 2, 3, 4, 5, 6, 7
-GF_S_SET, GF_S_COPY, GF_S_DIV, GF_S_SQRT, GF_S_SWAP, GF_S_RECORD, GF_S_PRINTF = 32, 33, 34, 35, 36, 37, 38
-GF_STEP_BLOCKING = 1
+GF_S_SET, GF_S_COPY, GF_S_DIV, GF_S_SQRT, GF_S_SWAP, GF_S_RECORD, GF_S_PRINTF, GF_S_CALL = \
+    32, 33, 34, 35, 36, 37, 38, 39
+GF_STEP_BLOCKING, GF_STEP_TIMED = 1, 2
+
+GF_CALLEE_FPRINTF, GF_CALLEE_SNPRINTF, GF_CALLEE_SSCANF, GF_CALLEE_FWRITE, GF_CALLEE_FREAD = 1, 2, 3, 4, 5
+GF_ARG_CONST, GF_ARG_SCALAR, GF_ARG_ITER, GF_ARG_REF = 0, 1, 2, 3
+GF_REF_READ, GF_REF_WRITE, GF_REF_READWRITE = 1, 2, 3
+GF_CALL_MAX_ARGS, GF_CALL_MAX_REFS, GF_CALL_MAX_SITES = 8, 4, 64
 
 GF_MAX_ARRAYS = 16
 GF_MAX_SCALARS = 16
@@ -104,7 +110,65 @@ class RunStats(ctypes.Structure):
 
 class CtxOpts(ctypes.Structure):
     _fields_ = [("rpc_slots", ctypes.c_int32), ("rpc_capture", ctypes.c_int32), ("rpc_thread", ctypes.c_int32),
-                ("rpc_timeout_us", ctypes.c_int64), ("barrier_timeout_us", ctypes.c_int64)]
+                ("rpc_timeout_us", ctypes.c_int64), ("barrier_timeout_us", ctypes.c_int64),
+                ("rpc_payload", ctypes.c_int64)]
+
+
+class CallArg(ctypes.Structure):
+    """One argument record of a host call site (gf_call_arg)."""
+    _fields_ = [("kind", ctypes.c_int32), ("type", ctypes.c_int32), ("slot", ctypes.c_int32),
+                ("mode", ctypes.c_int32), ("value", ctypes.c_int64), ("start", ctypes.c_int64),
+                ("size", ctypes.c_int64), ("offset", ctypes.c_int64)]
+
+    @classmethod
+    def const(cls, value, type="i"):
+        """A value word: an int ('i'), a float ('d') or a host pointer ('p')."""
+        a = cls()
+        a.kind, a.type = GF_ARG_CONST, ord(type)
+        if type == "d":
+            a.value = ctypes.c_int64.from_buffer_copy(ctypes.c_double(float(value))).value
+        else:
+            a.value = ctypes.c_int64(int(value)).value
+        return a
+
+    @classmethod
+    def scalar(cls, slot, type="d"):
+        a = cls()
+        a.kind, a.type, a.slot = GF_ARG_SCALAR, ord(type), slot
+        return a
+
+    @classmethod
+    def iteration(cls):
+        a = cls()
+        a.kind, a.type = GF_ARG_ITER, ord("i")
+        return a
+
+    @classmethod
+    def ref(cls, slot, size, start=0, offset=0, mode=GF_REF_READWRITE):
+        """A pointer `offset` bytes into the object of `size` bytes at byte
+        `start` of array slot `slot`."""
+        a = cls()
+        a.kind, a.type, a.slot, a.mode = GF_ARG_REF, ord("p"), slot, mode
+        a.start, a.size, a.offset = start, size, offset
+        return a
+
+
+class CallStats(ctypes.Structure):
+    _fields_ = [("calls", ctypes.c_int64), ("dev_args_us", ctypes.c_double), ("dev_copy_in_us", ctypes.c_double),
+                ("dev_wait_us", ctypes.c_double), ("dev_copy_out_us", ctypes.c_double),
+                ("host_decode_us", ctypes.c_double), ("host_call_us", ctypes.c_double),
+                ("host_reply_us", ctypes.c_double), ("transit_us", ctypes.c_double)]
+
+    def as_dict(self):
+        return {f: getattr(self, f) for f, _ in self._fields_}
+
+
+def host_stream(name: str) -> int:
+    """The host FILE * of the process's stdout or stderr (a value argument
+    for fprintf / fwrite call sites)."""
+    if name not in ("stdout", "stderr"):
+        raise ValueError(name)
+    return ctypes.c_void_p.in_dll(ctypes.CDLL(None), name).value
 
 
 def _ptr(v) -> int:
@@ -132,6 +196,10 @@ _SIGS = {
     "gf_rpc_poll": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_int32]),
     "gf_rpc_register_format": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_char_p, ctypes.c_char_p]),
     "gf_rpc_take_output": (ctypes.c_int64, [ctypes.c_void_p, ctypes.c_char_p, ctypes.c_int64]),
+    "gf_rpc_register_call": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_int32, ctypes.POINTER(CallArg),
+                                              ctypes.c_int32]),
+    "gf_rpc_call_stats": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.POINTER(CallStats),
+                                         ctypes.c_int32]),
     "gf_sync": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.POINTER(RunStats)]),
     "gf_persistent_capacity": (ctypes.c_int32, [ctypes.c_void_p, ctypes.POINTER(Program), ctypes.c_int32]),
     "gf_copy": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64, ctypes.c_int32,
@@ -217,10 +285,10 @@ class Context:
     """One libgf context on a HIP device."""
 
     def __init__(self, device: int = 0, rpc_slots: int = 0, rpc_capture: bool = False, rpc_thread: bool = False,
-                 rpc_timeout_us: int = 0, barrier_timeout_us: int = 0):
+                 rpc_timeout_us: int = 0, barrier_timeout_us: int = 0, rpc_payload: int = 0):
         self.lib = load_library()
         opts = CtxOpts(rpc_slots, 1 if rpc_capture else 0, 1 if rpc_thread else 0, rpc_timeout_us,
-                       barrier_timeout_us)
+                       barrier_timeout_us, rpc_payload)
         h = ctypes.c_void_p()
         st = self.lib.gf_ctx_create(device, ctypes.byref(opts), ctypes.byref(h))
         if st != GF_OK:
@@ -273,6 +341,15 @@ class Context:
 
     def register_format(self, fmt: str, sig: str) -> int:
         return self._check(self.lib.gf_rpc_register_format(self.h, fmt.encode(), sig.encode()))
+
+    def register_call(self, callee: int, args) -> int:
+        arr = (CallArg * max(1, len(args)))(*args)
+        return self._check(self.lib.gf_rpc_register_call(self.h, callee, arr, len(args)))
+
+    def call_stats(self, call_id: int, reset: bool = False) -> dict:
+        out = CallStats()
+        self._check(self.lib.gf_rpc_call_stats(self.h, call_id, ctypes.byref(out), 1 if reset else 0))
+        return out.as_dict()
 
     def take_output(self, cap: int = 1 << 20) -> str:
         buf = ctypes.create_string_buffer(cap)

@@ -89,6 +89,136 @@ struct Format {
     Pad pad;
 };
 
+// Landing pads of GF_S_CALL (Section 3.2): one non-variadic wrapper per
+// callee and argument-type signature ('i' long long, 'd' double, 'p' a
+// pointer: an opaque host value or a reference already translated into the
+// request's payload). With output capture on, fprintf and fwrite aimed at
+// stdout or stderr append to the capture buffer instead.
+using CallPad = int64_t (*)(const uint64_t *w, std::string *cap);
+
+template <typename T>
+T word_as(uint64_t w)
+{
+    if constexpr (std::is_same<T, double>::value) {
+        double d;
+        std::memcpy(&d, &w, sizeof d);
+        return d;
+    } else if constexpr (std::is_pointer<T>::value) {
+        return (T)(uintptr_t)w;
+    } else {
+        return (T)(int64_t)w;
+    }
+}
+
+bool captured_stream(const void *f, const std::string *cap)
+{
+    return cap && (f == (const void *)stdout || f == (const void *)stderr);
+}
+
+#pragma clang diagnostic push
+#pragma clang diagnostic ignored "-Wformat-nonliteral"
+#pragma clang diagnostic ignored "-Wformat-security"
+
+template <typename... V>
+struct FprintfPad {
+    template <size_t... I>
+    static int64_t run(const uint64_t *w, std::string *cap, std::index_sequence<I...>)
+    {
+        FILE *f = word_as<FILE *>(w[0]);
+        const char *fmt = word_as<const char *>(w[1]);
+        if (captured_stream(f, cap)) {
+            char buf[4096];
+            const int n = std::snprintf(buf, sizeof buf, fmt, word_as<V>(w[2 + I])...);
+            if (n > 0)
+                cap->append(buf, std::min<size_t>((size_t)n, sizeof buf - 1));
+            return n;
+        }
+        return std::fprintf(f, fmt, word_as<V>(w[2 + I])...);
+    }
+    static int64_t pad(const uint64_t *w, std::string *cap) { return run(w, cap, std::index_sequence_for<V...>{}); }
+};
+
+template <typename... V>
+struct SnprintfPad {
+    template <size_t... I>
+    static int64_t run(const uint64_t *w, std::index_sequence<I...>)
+    {
+        return std::snprintf(word_as<char *>(w[0]), (size_t)w[1], word_as<const char *>(w[2]),
+                             word_as<V>(w[3 + I])...);
+    }
+    static int64_t pad(const uint64_t *w, std::string *) { return run(w, std::index_sequence_for<V...>{}); }
+};
+
+template <typename... V>
+struct SscanfPad {
+    template <size_t... I>
+    static int64_t run(const uint64_t *w, std::index_sequence<I...>)
+    {
+        return std::sscanf(word_as<const char *>(w[0]), word_as<const char *>(w[1]), word_as<V>(w[2 + I])...);
+    }
+    static int64_t pad(const uint64_t *w, std::string *) { return run(w, std::index_sequence_for<V...>{}); }
+};
+
+#pragma clang diagnostic pop
+
+int64_t fwrite_pad(const uint64_t *w, std::string *cap)
+{
+    const char *p = word_as<const char *>(w[0]);
+    const size_t size = (size_t)w[1], n = (size_t)w[2];
+    FILE *f = word_as<FILE *>(w[3]);
+    if (captured_stream(f, cap)) {
+        if (size > 0)
+            cap->append(p, size * n);
+        return (int64_t)n;
+    }
+    return (int64_t)std::fwrite(p, size, n, f);
+}
+
+int64_t fread_pad(const uint64_t *w, std::string *)
+{
+    return (int64_t)std::fread(word_as<void *>(w[0]), (size_t)w[1], (size_t)w[2], word_as<FILE *>(w[3]));
+}
+
+// Variadic tails: every combination of 'i', 'd', 'p' (AnyType) or of 'p'
+// only, up to Depth arguments.
+template <template <typename...> class P, bool AnyType, int Depth, typename... V>
+void gen_call_pads(std::map<std::string, CallPad> &m, const std::string &key)
+{
+    m[key] = &P<V...>::pad;
+    if constexpr (Depth > 0) {
+        gen_call_pads<P, AnyType, Depth - 1, V..., void *>(m, key + "p");
+        if constexpr (AnyType) {
+            gen_call_pads<P, AnyType, Depth - 1, V..., long long>(m, key + "i");
+            gen_call_pads<P, AnyType, Depth - 1, V..., double>(m, key + "d");
+        }
+    }
+}
+
+// key: callee number, ':', full type signature
+const std::map<std::string, CallPad> &call_pads()
+{
+    static const std::map<std::string, CallPad> m = [] {
+        std::map<std::string, CallPad> t;
+        gen_call_pads<FprintfPad, true, 4>(t, std::to_string(GF_CALLEE_FPRINTF) + ":pp");
+        gen_call_pads<SnprintfPad, true, 4>(t, std::to_string(GF_CALLEE_SNPRINTF) + ":pip");
+        gen_call_pads<SscanfPad, false, 6>(t, std::to_string(GF_CALLEE_SSCANF) + ":pp");
+        t[std::to_string(GF_CALLEE_FWRITE) + ":piip"] = &fwrite_pad;
+        t[std::to_string(GF_CALLEE_FREAD) + ":piip"] = &fread_pad;
+        return t;
+    }();
+    return m;
+}
+
+// A registered call site: its device record, landing pad, whether its
+// device side copies objects back, and host stage times of timed calls.
+struct CallSite {
+    DCall dev;
+    CallPad pad;
+    bool copy_out;
+    int64_t host_calls = 0;
+    int64_t host_ns[3] = {0, 0, 0};  // decode, call, reply
+};
+
 }  // namespace
 
 // ---------------------------------------------------------------------------
@@ -118,6 +248,14 @@ struct gf_ctx {
     uint64_t next_ticket = 0;
     std::mutex rpc_mu;
     std::vector<Format> formats;
+    // general host calls: per-slot payloads (pinned), call-site table and
+    // its device copy with the device-side stage counters
+    char *h_payload = nullptr;
+    char *d_payload = nullptr;
+    uint32_t payload_bytes = 0;
+    DCall *d_calls = nullptr;
+    unsigned long long *d_call_stats = nullptr;
+    std::vector<CallSite> calls;  // capacity GF_CALL_MAX_SITES, never reallocated
     bool capture = false;
     std::string captured;
     std::atomic<int64_t> serviced{0};
@@ -180,14 +318,24 @@ RpcRing ring_of(const gf_ctx *ctx)
     r.slots = ctx->d_slots;
     r.ticket = ctx->d_ticket;
     r.mask = ctx->nslots - 1;
-    r.pad_ = 0;
+    r.payload = ctx->payload_bytes;
     r.timeout_ticks = ctx->rpc_timeout_us * 100;  // s_memrealtime runs at 100 MHz
+    r.payloads = ctx->d_payload;
+    r.calls = ctx->d_calls;
+    r.call_stats = ctx->d_call_stats;
     return r;
 }
 
 int64_t now_us()
 {
     return std::chrono::duration_cast<std::chrono::microseconds>(
+               std::chrono::steady_clock::now().time_since_epoch())
+        .count();
+}
+
+int64_t now_ns()
+{
+    return std::chrono::duration_cast<std::chrono::nanoseconds>(
                std::chrono::steady_clock::now().time_since_epoch())
         .count();
 }
@@ -205,7 +353,46 @@ int32_t poll_locked(gf_ctx *ctx, int32_t max_requests, int32_t timeout_us)
         const uint64_t seq = __atomic_load_n(&slot->seq, __ATOMIC_ACQUIRE);
         if (seq == ctx->next_ticket + 1) {
             int64_t ret = -1;
-            if (slot->callee == kCalleeRegion && slot->nargs == 3) {
+            bool device_frees = false;
+            if (slot->callee == kCalleeCall && slot->fmt_id < ctx->calls.size()) {
+                CallSite &cs = ctx->calls[slot->fmt_id];
+                const bool timed = (slot->flags & GF_STEP_TIMED) != 0;
+                const int64_t h0 = timed ? now_ns() : 0;
+                // the device frees the slot itself after copying objects back
+                device_frees = cs.copy_out && (slot->flags & GF_STEP_BLOCKING);
+                if (slot->nargs == (uint32_t)cs.dev.nargs) {
+                    char *pl = ctx->h_payload + (size_t)(ctx->next_ticket & (ctx->nslots - 1)) * ctx->payload_bytes;
+                    uint64_t w[GF_CALL_MAX_ARGS];
+                    for (int k = 0; k < cs.dev.nargs; ++k) {
+                        const DCallArg &a = cs.dev.a[k];
+                        if (a.kind == GF_ARG_REF) {
+                            if (a.mode == GF_REF_WRITE)
+                                std::memset(pl + a.pos, 0, (size_t)a.size);
+                            w[k] = (uint64_t)(uintptr_t)(pl + a.pos + a.offset);
+                        } else {
+                            w[k] = slot->args[k];
+                        }
+                    }
+                    const int64_t h1 = timed ? now_ns() : 0;
+                    ret = cs.pad(w, ctx->capture ? &ctx->captured : nullptr);
+                    const int64_t h2 = timed ? now_ns() : 0;
+                    slot->ret = ret;
+                    if (!device_frees)
+                        __atomic_store_n(&slot->freed, ctx->next_ticket + 1, __ATOMIC_RELAXED);
+                    __atomic_store_n(&slot->done, ctx->next_ticket + 1, __ATOMIC_RELEASE);
+                    if (timed) {
+                        const int64_t h3 = now_ns();
+                        cs.host_calls += 1;
+                        cs.host_ns[0] += h1 - h0;
+                        cs.host_ns[1] += h2 - h1;
+                        cs.host_ns[2] += h3 - h2;
+                    }
+                    ++ctx->next_ticket;
+                    ++done;
+                    ctx->serviced.fetch_add(1);
+                    continue;
+                }
+            } else if (slot->callee == kCalleeRegion && slot->nargs == 3) {
                 ret = split_region(ctx, (int)slot->args[0], slot->args[2]);
             } else if (slot->callee == kCalleePrintf && slot->fmt_id < ctx->formats.size()) {
                 const Format &f = ctx->formats[slot->fmt_id];
@@ -224,6 +411,8 @@ int32_t poll_locked(gf_ctx *ctx, int32_t max_requests, int32_t timeout_us)
                 }
             }
             slot->ret = ret;
+            if (!device_frees)
+                __atomic_store_n(&slot->freed, ctx->next_ticket + 1, __ATOMIC_RELAXED);
             __atomic_store_n(&slot->done, ctx->next_ticket + 1, __ATOMIC_RELEASE);
             ++ctx->next_ticket;
             ++done;
@@ -317,6 +506,30 @@ gf_status gf_ctx_create(int32_t hip_device, const gf_ctx_opts *opts, gf_ctx **ou
         ctx->d_slots = ctx->h_slots;
     // the ticket counter lives in the last scratch line (device memory)
     ctx->d_ticket = (uint64_t *)(base + part_bytes + line_bytes + 128);
+    // payloads of general host calls, and the call-site table
+    const int64_t pb = o.rpc_payload > 0 ? o.rpc_payload : 1024;
+    if (pb < 16 || pb > 65536 || (pb & 15)) {
+        gf_ctx_destroy(ctx);
+        return GF_EINVAL;
+    }
+    ctx->payload_bytes = (uint32_t)pb;
+    ctx->calls.reserve(GF_CALL_MAX_SITES);
+    if (hipHostMalloc((void **)&ctx->h_payload, (size_t)ns * pb, hipHostMallocCoherent | hipHostMallocMapped) !=
+            hipSuccess ||
+        hipMalloc((void **)&ctx->d_calls,
+                  GF_CALL_MAX_SITES * (sizeof(DCall) + kCallStatWords * sizeof(unsigned long long))) != hipSuccess) {
+        gf_ctx_destroy(ctx);
+        return GF_ENOMEM;
+    }
+    std::memset(ctx->h_payload, 0, (size_t)ns * pb);
+    if (hipHostGetDevicePointer((void **)&ctx->d_payload, ctx->h_payload, 0) != hipSuccess)
+        ctx->d_payload = ctx->h_payload;
+    ctx->d_call_stats = (unsigned long long *)(ctx->d_calls + GF_CALL_MAX_SITES);
+    if (hipMemset(ctx->d_calls, 0, GF_CALL_MAX_SITES * (sizeof(DCall) + kCallStatWords * sizeof(unsigned long long))) !=
+        hipSuccess) {
+        gf_ctx_destroy(ctx);
+        return GF_EHIP;
+    }
     ctx->rpc_timeout_us = o.rpc_timeout_us > 0 ? o.rpc_timeout_us : 2 * 1000 * 1000;
     ctx->capture = o.rpc_capture != 0;
     if (hipStreamCreateWithFlags(&ctx->capture_stream, hipStreamNonBlocking) != hipSuccess)
@@ -384,6 +597,10 @@ gf_status gf_ctx_destroy(gf_ctx *ctx)
         hipFree(ctx->d_batch);
     if (ctx->h_slots)
         hipHostFree(ctx->h_slots);
+    if (ctx->h_payload)
+        hipHostFree(ctx->h_payload);
+    if (ctx->d_calls)
+        hipFree(ctx->d_calls);
     if (ctx->d_scratch_lines)
         hipFree(ctx->d_scratch_lines);
     if (ctx->d_mlp)
@@ -407,6 +624,132 @@ int32_t gf_rpc_register_format(gf_ctx *ctx, const char *fmt, const char *sig)
     std::lock_guard<std::mutex> g(ctx->rpc_mu);
     ctx->formats.push_back(Format{fmt, sig, it->second});
     return (int32_t)ctx->formats.size() - 1;
+}
+
+int32_t gf_rpc_register_call(gf_ctx *ctx, int32_t callee, const gf_call_arg *args, int32_t nargs)
+{
+    if (!ctx)
+        return GF_EINVAL;
+    if (nargs < 0 || nargs > GF_CALL_MAX_ARGS || (nargs > 0 && !args))
+        return fail(ctx, GF_EINVAL, "call site needs 0..%d argument records", GF_CALL_MAX_ARGS);
+    if (callee < GF_CALLEE_FPRINTF || callee > GF_CALLEE_FREAD)
+        return fail(ctx, GF_EINVAL, "unknown callee %d", callee);
+    DCall d;
+    std::memset(&d, 0, sizeof d);
+    d.callee = callee;
+    d.nargs = nargs;
+    std::string sig;
+    int64_t pos = 0;
+    bool copy_out = false;
+    for (int k = 0; k < nargs; ++k) {
+        const gf_call_arg &a = args[k];
+        DCallArg &o = d.a[k];
+        o.kind = a.kind;
+        o.type = a.type;
+        o.slot = a.slot;
+        o.mode = a.mode;
+        o.value = a.value;
+        o.ref = -1;
+        switch (a.kind) {
+        case GF_ARG_CONST:
+            if (a.type != 'i' && a.type != 'd' && a.type != 'p')
+                return fail(ctx, GF_EINVAL, "argument %d: type must be 'i', 'd' or 'p'", k);
+            break;
+        case GF_ARG_SCALAR:
+            if (a.type != 'i' && a.type != 'd')
+                return fail(ctx, GF_EINVAL, "argument %d: a scalar passes as 'i' or 'd'", k);
+            if (a.slot < 0 || a.slot >= GF_MAX_SCALARS)
+                return fail(ctx, GF_EINVAL, "argument %d: scalar slot out of range", k);
+            break;
+        case GF_ARG_ITER:
+            if (a.type != 'i')
+                return fail(ctx, GF_EINVAL, "argument %d: the iteration number passes as 'i'", k);
+            break;
+        case GF_ARG_REF:
+            if (a.type != 'p')
+                return fail(ctx, GF_EINVAL, "argument %d: a reference passes as 'p'", k);
+            if (a.slot < 0 || a.slot >= GF_MAX_ARRAYS)
+                return fail(ctx, GF_EINVAL, "argument %d: array slot out of range", k);
+            if (a.mode < GF_REF_READ || a.mode > GF_REF_READWRITE)
+                return fail(ctx, GF_EINVAL, "argument %d: access mode must be read, write or read-write", k);
+            if (a.size < 1 || a.start < 0 || a.offset < 0 || a.offset > a.size)
+                return fail(ctx, GF_EINVAL, "argument %d: object needs size >= 1, start >= 0, 0 <= offset <= size", k);
+            if (d.nrefs == GF_CALL_MAX_REFS)
+                return fail(ctx, GF_EINVAL, "more than %d reference arguments", GF_CALL_MAX_REFS);
+            o.start = a.start;
+            o.size = a.size;
+            o.offset = a.offset;
+            o.pos = (int32_t)pos;
+            o.ref = d.nrefs++;
+            pos += (a.size + 15) / 16 * 16;
+            if (pos > (int64_t)ctx->payload_bytes)
+                return fail(ctx, GF_EINVAL, "referenced objects need %lld payload bytes; the slot payload is %u",
+                            (long long)pos, ctx->payload_bytes);
+            copy_out |= (a.mode & GF_REF_WRITE) != 0;
+            break;
+        default:
+            return fail(ctx, GF_EINVAL, "argument %d: unknown kind %d", k, a.kind);
+        }
+        sig.push_back((char)a.type);
+    }
+    d.payload = (int32_t)pos;
+    auto it = call_pads().find(std::to_string(callee) + ":" + sig);
+    if (it == call_pads().end())
+        return fail(ctx, GF_EUNSUPPORTED, "no landing pad for callee %d with argument types '%s'", callee,
+                    sig.c_str());
+    std::lock_guard<std::mutex> g(ctx->rpc_mu);
+    if ((int)ctx->calls.size() == GF_CALL_MAX_SITES)
+        return fail(ctx, GF_EINVAL, "at most %d call sites", GF_CALL_MAX_SITES);
+    const int id = (int)ctx->calls.size();
+    hipSetDevice(ctx->device);
+    hipError_t e = hipMemcpy(ctx->d_calls + id, &d, sizeof d, hipMemcpyHostToDevice);
+    if (e != hipSuccess)
+        return hipfail(ctx, e, "call-site upload");
+    CallSite cs;
+    cs.dev = d;
+    cs.pad = it->second;
+    cs.copy_out = copy_out;
+    ctx->calls.push_back(cs);
+    return id;
+}
+
+gf_status gf_rpc_call_stats(gf_ctx *ctx, int32_t call_id, gf_call_stats *out, int32_t reset)
+{
+    if (!ctx || !out)
+        return GF_EINVAL;
+    std::lock_guard<std::mutex> g(ctx->rpc_mu);
+    if (call_id < 0 || call_id >= (int)ctx->calls.size())
+        return fail(ctx, GF_EINVAL, "unknown call site %d", call_id);
+    hipSetDevice(ctx->device);
+    unsigned long long dev[kCallStatWords];
+    unsigned long long *dptr = ctx->d_call_stats + (int64_t)call_id * kCallStatWords;
+    hipError_t e = hipMemcpy(dev, dptr, sizeof dev, hipMemcpyDeviceToHost);
+    if (e != hipSuccess)
+        return hipfail(ctx, e, "call statistics");
+    CallSite &cs = ctx->calls[call_id];
+    std::memset(out, 0, sizeof *out);
+    out->calls = (int64_t)dev[0];
+    if (dev[0] > 0) {
+        const double per = 0.01 / (double)dev[0];  // 100 MHz ticks -> us per call
+        out->dev_args_us = (double)dev[1] * per;
+        out->dev_copy_in_us = (double)dev[2] * per;
+        out->dev_wait_us = (double)dev[3] * per;
+        out->dev_copy_out_us = (double)dev[4] * per;
+    }
+    if (cs.host_calls > 0) {
+        const double per = 1e-3 / (double)cs.host_calls;
+        out->host_decode_us = (double)cs.host_ns[0] * per;
+        out->host_call_us = (double)cs.host_ns[1] * per;
+        out->host_reply_us = (double)cs.host_ns[2] * per;
+    }
+    out->transit_us = out->dev_wait_us - (out->host_decode_us + out->host_call_us + out->host_reply_us);
+    if (reset) {
+        if ((e = hipMemset(dptr, 0, sizeof dev)) != hipSuccess)
+            return hipfail(ctx, e, "call statistics reset");
+        cs.host_calls = 0;
+        cs.host_ns[0] = cs.host_ns[1] = cs.host_ns[2] = 0;
+    }
+    return GF_OK;
 }
 
 int32_t gf_rpc_poll(gf_ctx *ctx, int32_t max_requests, int32_t timeout_us)
@@ -438,7 +781,7 @@ int64_t gf_rpc_take_output(gf_ctx *ctx, char *buf, int64_t cap)
 namespace {
 
 bool is_region(int k) { return k >= GF_R_JACOBI2D && k <= GF_R_OWNER; }
-bool is_serial(int k) { return k >= GF_S_SET && k <= GF_S_PRINTF; }
+bool is_serial(int k) { return k >= GF_S_SET && k <= GF_S_CALL; }
 
 int region_nops(int k)
 {
@@ -528,6 +871,21 @@ gf_status check_step(gf_ctx *ctx, const gf_step &s, int idx)
         for (size_t k = 1; k < sig.size(); ++k)
             if (sig[k] != 'd' || !sc_ok(s.sc[k - 1]))
                 return fail(ctx, GF_EINVAL, "step %d: printf argument %zu must be a scalar variable", idx, k);
+        break;
+    }
+    case GF_S_CALL: {
+        if (s.every < 1)
+            return fail(ctx, GF_EINVAL, "step %d: call needs every >= 1", idx);
+        if (s.sc[0] != -1 && !sc_ok(s.sc[0]))
+            return fail(ctx, GF_EINVAL, "step %d: return slot out of range", idx);
+        if (s.flags & ~(GF_STEP_BLOCKING | GF_STEP_TIMED))
+            return fail(ctx, GF_EINVAL, "step %d: unknown flags 0x%x", idx, s.flags);
+        std::lock_guard<std::mutex> g(ctx->rpc_mu);
+        if (s.fmt_id < 0 || s.fmt_id >= (int)ctx->calls.size())
+            return fail(ctx, GF_EINVAL, "step %d: unregistered call site %d", idx, s.fmt_id);
+        if (!(s.flags & GF_STEP_BLOCKING) && (ctx->calls[s.fmt_id].copy_out || s.sc[0] >= 0))
+            return fail(ctx, GF_EINVAL, "step %d: a call that copies objects back or returns a value must be blocking",
+                        idx);
         break;
     }
     default:
@@ -680,6 +1038,25 @@ gf_status build_program(gf_ctx *ctx, const gf_program *prog, DProg *out)
         if (out->steps[si].red_op == GF_OP_NONE)
             out->barriers -= 1;
     }
+    // host calls: a grid barrier after each call that fires; a call that
+    // reads objects may follow the last region, so every region keeps its
+    // barrier
+    bool call_refs = false;
+    for (int i = 0; i < out->n_steps; ++i) {
+        const DStep &st = out->steps[i];
+        if (st.kind != GF_S_CALL)
+            continue;
+        out->barriers += i < out->n_pro ? 1 : (int64_t)(out->iters / st.every);
+        std::lock_guard<std::mutex> g(ctx->rpc_mu);
+        call_refs |= ctx->calls[st.fmt_id].dev.nrefs > 0;
+    }
+    if (call_refs && out->last_region >= 0) {
+        const int64_t lr = out->last_region;
+        const int si = lr < out->n_pro ? (int)lr : out->n_pro + (int)((lr - out->n_pro) % out->n_body);
+        if (out->steps[si].red_op == GF_OP_NONE)
+            out->barriers += 1;
+        out->last_region = -1;
+    }
     return GF_OK;
 }
 
@@ -689,6 +1066,15 @@ gf_status check_instance(gf_ctx *ctx, const DProg &p, const gf_instance &in, con
         return fail(ctx, GF_EINVAL, "instance %d: null scalar array", idx);
     for (int i = 0; i < p.n_steps; ++i) {
         const DStep &s = p.steps[i];
+        if (s.kind == GF_S_CALL) {
+            std::lock_guard<std::mutex> g(ctx->rpc_mu);
+            const DCall &c = ctx->calls[s.fmt_id].dev;
+            for (int k = 0; k < c.nargs; ++k)
+                if (c.a[k].kind == GF_ARG_REF && !in.arr[c.a[k].slot])
+                    return fail(ctx, GF_EINVAL, "instance %d step %d: call references empty array slot %d", idx, i,
+                                c.a[k].slot);
+            continue;
+        }
         if (is_region(s.kind)) {
             for (int k = 0; k < region_nops(s.kind); ++k)
                 if (!in.arr[s.arr[k]])
@@ -878,6 +1264,13 @@ gf_status enqueue_per_region(gf_ctx *ctx, const DProg &p, const gf_instance &in,
             g.flags = s.flags;
             g.c = s.c;
             g.rec = s.kind == GF_S_RECORD ? (double *)arr[s.arr[0]] : nullptr;
+            if (s.kind == GF_S_CALL) {
+                std::lock_guard<std::mutex> lk(ctx->rpc_mu);
+                const DCall &c = ctx->calls[s.fmt_id].dev;
+                for (int k = 0; k < c.nargs; ++k)
+                    if (c.a[k].kind == GF_ARG_REF)
+                        g.obj[c.a[k].ref] = arr[c.a[k].slot];
+            }
         }
     }
     gf_status st = flush();

@@ -417,11 +417,12 @@ __device__ __forceinline__ void static_range(int64_t n, int64_t T, int64_t t, in
 // completion flag in shared memory) and return the host's value.
 // ---------------------------------------------------------------------------
 
-__device__ __forceinline__ bool rpc_wait_done(const RpcSlot *slot, uint64_t want, const RpcRing &rpc, int32_t *err)
+// Wait until a slot word (done or freed) reaches `want`.
+__device__ __forceinline__ bool rpc_wait_word(const uint64_t *word, uint64_t want, const RpcRing &rpc, int32_t *err)
 {
     const uint64_t t0 = now_ticks();
     uint32_t spins = 0;
-    while (__hip_atomic_load(&slot->done, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM) < want) {
+    while (__hip_atomic_load(word, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM) < want) {
         __builtin_amdgcn_s_sleep(2);
         if ((++spins & 15u) == 0 && (int64_t)(now_ticks() - t0) > rpc.timeout_ticks) {
             set_error(err, kErrRpcTimeout);
@@ -439,7 +440,7 @@ __device__ __forceinline__ bool rpc_call(const RpcRing &rpc, uint32_t callee, ui
     const uint64_t t = __hip_atomic_fetch_add(rpc.ticket, (uint64_t)1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     RpcSlot *slot = rpc.slots + (t & rpc.mask);
     const uint64_t nslots = (uint64_t)rpc.mask + 1;
-    if (t >= nslots && !rpc_wait_done(slot, t - nslots + 1, rpc, err))
+    if (t >= nslots && !rpc_wait_word(&slot->freed, t - nslots + 1, rpc, err))
         return false;
     slot->callee = callee;
     slot->fmt_id = fmt_id;
@@ -449,7 +450,7 @@ __device__ __forceinline__ bool rpc_call(const RpcRing &rpc, uint32_t callee, ui
         slot->args[i] = args[i];
     __hip_atomic_store(&slot->seq, t + 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
     if (flags & GF_STEP_BLOCKING) {
-        if (!rpc_wait_done(slot, t + 1, rpc, err))
+        if (!rpc_wait_word(&slot->done, t + 1, rpc, err))
             return false;
         if (ret)
             *ret = __hip_atomic_load(&slot->ret, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);

@@ -79,6 +79,9 @@ struct Tiling {
 // RPCInfo / RPCArgInfo records, Section 3.2): the device fills the body,
 // then publishes `seq` = ticket + 1 with a system-scope release store; the
 // host runs the landing pad, writes `ret` and publishes `done` = ticket + 1.
+// `freed` = ticket + 1 says the slot and its payload may be reused: the host
+// sets it with `done`, except for a blocking call that copies objects back
+// from the payload, whose device side sets it after the copy.
 struct alignas(128) RpcSlot {
     uint64_t seq;
     uint32_t callee;
@@ -88,10 +91,40 @@ struct alignas(128) RpcSlot {
     uint64_t args[8];
     int64_t ret;
     uint64_t done;
+    uint64_t freed;
 };
 static_assert(sizeof(RpcSlot) == 128, "RPC slot is one 128-byte line");
 
-enum : uint32_t { kCalleePrintf = 1, kCalleeRegion = 2 };
+enum : uint32_t { kCalleePrintf = 1, kCalleeRegion = 2, kCalleeCall = 3 };
+
+// Device copy of a registered call site (gf_rpc_register_call): per
+// argument its source and, for a reference, the object and where the
+// object sits in the slot payload (`pos`, 16-byte aligned) and which
+// reference it is (`ref`, the index into the caller's resolved objects).
+struct DCallArg {
+    int32_t kind;
+    int32_t type;
+    int32_t slot;
+    int32_t mode;
+    int64_t value;
+    int64_t start;
+    int64_t size;
+    int64_t offset;
+    int32_t pos;
+    int32_t ref;
+};
+
+struct DCall {
+    int32_t callee;
+    int32_t nargs;
+    int32_t nrefs;
+    int32_t payload;  // payload bytes used
+    DCallArg a[GF_CALL_MAX_ARGS];
+};
+
+// Device-side timing accumulators of one call site (GF_STEP_TIMED), in
+// 100 MHz clock ticks: calls, args, copy-in, wait, copy-out.
+constexpr int kCallStatWords = 5;
 
 // Device error word codes (sticky; first writer wins).
 enum : int32_t {
@@ -106,8 +139,11 @@ struct RpcRing {
     RpcSlot *slots;      // host pinned (device-visible)
     uint64_t *ticket;    // device memory
     uint32_t mask;       // nslots - 1
-    uint32_t pad_;
+    uint32_t payload;    // payload bytes per slot
     int64_t timeout_ticks;  // s_memrealtime ticks (100 MHz)
+    char *payloads;      // host pinned: slot i's payload at i * payload
+    const DCall *calls;  // device: registered call sites
+    unsigned long long *call_stats;  // device: kCallStatWords per call site
 };
 
 // Device scratch owned by a context. Each counter sits on its own 128-byte
@@ -137,7 +173,8 @@ constexpr int kLineWords = 32;  // uint32 words per 128-byte line
 // line 0: generation word of the grid barrier; lines kTreeLine0..: the
 // arrival counters of the barrier's fan-in tree; lines kGroupLine0 + i:
 // per-instance group barriers {count, gen}; lines kFinalizeLine0 + i:
-// per-region last-workgroup counters.
+// per-region last-workgroup counters. Words 4-5 of a group line carry the
+// return value of a GF_S_CALL from the group's first workgroup to the others.
 constexpr int kTreeFanIn = 16;
 constexpr int kTreeLine0 = 1;
 constexpr int kTreeLines = 512;  // >= 4096/16 + 4096/256 + 1
@@ -167,6 +204,7 @@ struct Glue {
     uint32_t pad_;
     double c;
     double *rec;  // GF_S_RECORD destination array
+    void *obj[GF_CALL_MAX_REFS];  // GF_S_CALL: array slots of its references, resolved
 };
 
 struct RegionLaunch {

@@ -900,6 +900,136 @@ __device__ inline void serial_printf(const RpcRing &rpc, int32_t fmt_id, int32_t
 }
 
 // ---------------------------------------------------------------------------
+// General host call (Section 3.2), made by one whole wavefront. Lane 0 takes
+// the ticket, waits until the slot is free and fills the header with the
+// value words; the 64 lanes copy the objects of read and read-write
+// references into the slot's payload (16-byte pieces, or bytes for objects
+// that are not 16-byte aligned); lane 0 publishes the request. A blocking
+// call then waits for completion, the lanes copy the objects of write and
+// read-write references back, and lane 0 frees the slot. base(a) gives the
+// array that holds the object of reference argument a under the caller's
+// current slot bindings. Returns the host's return value (0 when posted, -1
+// after a timeout, which also sets the error word).
+// ---------------------------------------------------------------------------
+
+__device__ __forceinline__ bool call_fires(int32_t iter, int32_t every)
+{
+    return iter < 0 || (every > 0 && (iter + 1) % every == 0);
+}
+
+__device__ __forceinline__ void wave_copy(char *dst, const char *src, int64_t n, int lane)
+{
+    if ((((uintptr_t)dst | (uintptr_t)src | (uint64_t)n) & 15u) == 0) {
+        for (int64_t i = (int64_t)lane * 16; i < n; i += kWave * 16)
+            *(uint4 *)(dst + i) = *(const uint4 *)(src + i);
+    } else {
+        for (int64_t i = lane; i < n; i += kWave)
+            dst[i] = src[i];
+    }
+}
+
+__device__ __forceinline__ uint64_t first_lane_u64(uint64_t v)
+{
+    const uint32_t lo = __builtin_amdgcn_readfirstlane((int)(uint32_t)v);
+    const uint32_t hi = __builtin_amdgcn_readfirstlane((int)(uint32_t)(v >> 32));
+    return ((uint64_t)hi << 32) | lo;
+}
+
+template <typename Base>
+__device__ int64_t serial_call(const RpcRing &rpc, int32_t call_id, uint32_t flags, Base base, const double *scal,
+                               int32_t iter, int32_t *err)
+{
+    const int lane = (int)(threadIdx.x & (kWave - 1));
+    const DCall &cs = rpc.calls[call_id];
+    const bool timed = (flags & GF_STEP_TIMED) != 0;
+    const bool blocking = (flags & GF_STEP_BLOCKING) != 0;
+    const uint64_t c0 = timed ? now_ticks() : 0;
+    const uint64_t nslots = (uint64_t)rpc.mask + 1;
+    uint64_t t = 0;
+    int ok = 1;
+    if (lane == 0) {
+        t = __hip_atomic_fetch_add(rpc.ticket, (uint64_t)1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        if (t >= nslots && !rpc_wait_word(&rpc.slots[t & rpc.mask].freed, t - nslots + 1, rpc, err))
+            ok = 0;
+    }
+    t = first_lane_u64(t);
+    if (!__builtin_amdgcn_readfirstlane(ok))
+        return -1;
+    RpcSlot *slot = rpc.slots + (t & rpc.mask);
+    char *pl = rpc.payloads + (size_t)(t & rpc.mask) * rpc.payload;
+    bool copy_out = false;
+    if (lane == 0) {
+        for (int k = 0; k < cs.nargs; ++k) {
+            const DCallArg &a = cs.a[k];
+            uint64_t w = 0;
+            if (a.kind == GF_ARG_CONST) {
+                w = (uint64_t)a.value;
+            } else if (a.kind == GF_ARG_SCALAR) {
+                const double v = scal[a.slot];
+                w = a.type == 'i' ? (uint64_t)(int64_t)v : (uint64_t)__double_as_longlong(v);
+            } else if (a.kind == GF_ARG_ITER) {
+                w = (uint64_t)(int64_t)(iter + 1);
+            }
+            slot->args[k] = w;
+        }
+        slot->callee = kCalleeCall;
+        slot->fmt_id = (uint32_t)call_id;
+        slot->nargs = (uint32_t)cs.nargs;
+        slot->flags = flags;
+    }
+    const uint64_t c1 = timed ? now_ticks() : 0;
+    // objects that lane 0 may have written just before (history records)
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
+    for (int k = 0; k < cs.nargs; ++k) {
+        const DCallArg &a = cs.a[k];
+        if (a.kind != GF_ARG_REF)
+            continue;
+        if (a.mode & GF_REF_READ)
+            wave_copy(pl + a.pos, (const char *)base(a) + a.start, a.size, lane);
+        copy_out |= (a.mode & GF_REF_WRITE) != 0;
+    }
+    // every lane's payload stores before lane 0's publication
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "");
+    if (lane == 0)
+        __hip_atomic_store(&slot->seq, t + 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
+    const uint64_t c2 = timed ? now_ticks() : 0;
+    uint64_t c3 = c2, c4 = c2;
+    int64_t ret = 0;
+    if (blocking) {
+        if (lane == 0) {
+            ok = rpc_wait_word(&slot->done, t + 1, rpc, err) ? 1 : 0;
+            ret = ok ? __hip_atomic_load(&slot->ret, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM) : -1;
+        }
+        ok = __builtin_amdgcn_readfirstlane(ok);
+        ret = (int64_t)first_lane_u64((uint64_t)ret);
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "");
+        c3 = timed ? now_ticks() : 0;
+        if (copy_out) {
+            if (ok)
+                for (int k = 0; k < cs.nargs; ++k) {
+                    const DCallArg &a = cs.a[k];
+                    if (a.kind == GF_ARG_REF && (a.mode & GF_REF_WRITE))
+                        wave_copy((char *)base(a) + a.start, pl + a.pos, a.size, lane);
+                }
+            // the payload reads are complete before the slot is handed back
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "");
+            if (lane == 0)
+                __hip_atomic_store(&slot->freed, t + 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
+        }
+        c4 = timed ? now_ticks() : 0;
+    }
+    if (timed && lane == 0) {
+        unsigned long long *st = rpc.call_stats + (int64_t)call_id * kCallStatWords;
+        __hip_atomic_fetch_add(st + 0, 1ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        __hip_atomic_fetch_add(st + 1, (unsigned long long)(c1 - c0), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        __hip_atomic_fetch_add(st + 2, (unsigned long long)(c2 - c1), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        __hip_atomic_fetch_add(st + 3, (unsigned long long)(c3 - c2), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        __hip_atomic_fetch_add(st + 4, (unsigned long long)(c4 - c3), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+    return ret;
+}
+
+// ---------------------------------------------------------------------------
 // Persistent program kernel (the whole main loop in one cooperative launch;
 // Section 3.3 with the kernel split replaced by in-kernel grid barriers).
 // Every workgroup walks the step list. Region work items are dealt
@@ -1046,6 +1176,24 @@ __global__ void __launch_bounds__(family_max_threads<KMASK>())
             }
             if (need_bar && !barrier())
                 return;
+        } else if (st.kind == GF_S_CALL) {
+            // the first workgroup's first wavefront makes the call; the
+            // barrier publishes the objects it copied back and the return
+            // value to every workgroup
+            if (call_fires(iter, st.every)) {
+                int64_t *retw = (int64_t *)(gline + 4);
+                if (member == 0 && threadIdx.x < kWave) {
+                    const int64_t r = serial_call(
+                        rpc, st.fmt_id, st.flags, [&](const DCallArg &a) { return (char *)s_arr[a.slot]; }, s_scal,
+                        iter, scr.error);
+                    if (threadIdx.x == 0)
+                        __hip_atomic_store(retw, r, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                }
+                if (!barrier())
+                    return;
+                if (threadIdx.x == 0 && st.sc[0] >= 0)
+                    s_scal[st.sc[0]] = (double)__hip_atomic_load(retw, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            }
         } else if (threadIdx.x == 0) {
             if (st.kind == GF_S_SWAP) {
                 void *tmp = s_arr[st.arr[0]];
@@ -1078,11 +1226,24 @@ __global__ void __launch_bounds__(family_max_threads<KMASK>())
 // glue that follows the region in the program.
 // ---------------------------------------------------------------------------
 
+// Called by the first wavefront of the finishing workgroup: a GF_S_CALL
+// uses all of its lanes, the other serial steps lane 0 alone.
 __device__ inline void run_glue(const RegionLaunch &rl, const RpcRing &rpc, int32_t *err)
 {
+    const bool lane0 = threadIdx.x == 0;
     for (int g = 0; g < rl.n_glue; ++g) {
         const Glue &gl = rl.glue[g];
-        if (gl.kind == GF_S_RECORD) {
+        if (gl.kind == GF_S_CALL) {
+            if (call_fires(gl.iter, gl.every)) {
+                const int64_t r = serial_call(
+                    rpc, gl.fmt_id, gl.flags, [&](const DCallArg &a) { return (char *)gl.obj[a.ref]; }, rl.scal,
+                    gl.iter, err);
+                if (lane0 && gl.sc[0] >= 0)
+                    rl.scal[gl.sc[0]] = (double)r;
+            }
+        } else if (!lane0) {
+            continue;
+        } else if (gl.kind == GF_S_RECORD) {
             if (gl.iter >= 0)
                 gl.rec[gl.iter] = rl.scal[gl.sc[0]];
         } else if (gl.kind == GF_S_PRINTF) {
@@ -1143,10 +1304,10 @@ __global__ void __launch_bounds__(family_max_threads<KMASK>()) k_region(RegionLa
         if (threadIdx.x == 0)
             rl.scal[st.sc[0]] = red_apply(st.red_op, rl.scal[st.sc[0]], v);
     }
-    if (threadIdx.x == 0) {
+    if (threadIdx.x < kWave)
         run_glue(rl, rpc, scr.error);
+    if (threadIdx.x == 0)
         __hip_atomic_store(cnt, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    }
 }
 
 // ---------------------------------------------------------------------------
@@ -1161,8 +1322,9 @@ __global__ void __launch_bounds__(family_max_threads<KMASK>()) k_region(RegionLa
 
 __global__ void __launch_bounds__(kWave) k_main(DProg prog, DInst inst, RpcRing rpc, Scratch scr)
 {
-    if (threadIdx.x != 0)
-        return;
+    // the whole wavefront walks the program (a GF_S_CALL uses every lane);
+    // lane 0 alone performs the other side effects
+    const bool lane0 = threadIdx.x == 0;
     uint64_t perm = 0;
     for (int k = 0; k < GF_MAX_ARRAYS; ++k)
         perm |= (uint64_t)k << (4 * k);
@@ -1183,19 +1345,36 @@ __global__ void __launch_bounds__(kWave) k_main(DProg prog, DInst inst, RpcRing 
         }
         const DStep &st = prog.steps[sidx];
         if (st.kind < 32) {
-            uint64_t args[3] = {(uint64_t)sidx, (uint64_t)(int64_t)iter, perm};
-            int64_t ret = -1;
-            if (!rpc_call(rpc, kCalleeRegion, 0, 3, args, GF_STEP_BLOCKING, &ret, scr.error))
-                return;
-            if (ret != 0) {
-                set_error(scr.error, kErrRegionLaunch);
-                return;
+            int ok = 1;
+            if (lane0) {
+                uint64_t args[3] = {(uint64_t)sidx, (uint64_t)(int64_t)iter, perm};
+                int64_t ret = -1;
+                if (!rpc_call(rpc, kCalleeRegion, 0, 3, args, GF_STEP_BLOCKING, &ret, scr.error)) {
+                    ok = 0;
+                } else if (ret != 0) {
+                    set_error(scr.error, kErrRegionLaunch);
+                    ok = 0;
+                }
             }
+            if (!__builtin_amdgcn_readfirstlane(ok))
+                return;
+            // every lane sees the region's results
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "");
         } else if (st.kind == GF_S_SWAP) {
             const int a = st.arr[0], b = st.arr[1];
             const uint64_t va = (perm >> (4 * a)) & 15u, vb = (perm >> (4 * b)) & 15u;
             perm &= ~((uint64_t)15 << (4 * a)) & ~((uint64_t)15 << (4 * b));
             perm |= (vb << (4 * a)) | (va << (4 * b));
+        } else if (st.kind == GF_S_CALL) {
+            if (call_fires(iter, st.every)) {
+                const int64_t r = serial_call(
+                    rpc, st.fmt_id, st.flags,
+                    [&](const DCallArg &a) { return (char *)inst.arr[slot_of(a.slot)]; }, scal, iter, scr.error);
+                if (lane0 && st.sc[0] >= 0)
+                    scal[st.sc[0]] = (double)r;
+            }
+        } else if (!lane0) {
+            continue;
         } else if (st.kind == GF_S_RECORD) {
             if (iter >= 0)
                 ((double *)inst.arr[slot_of(st.arr[0])])[iter] = scal[st.sc[0]];
@@ -1236,10 +1415,10 @@ __global__ void __launch_bounds__(kMaxWg) k_hist_merge(RegionLaunch rl, int64_t 
     if (!s_last)
         return;
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
-    if (threadIdx.x == 0) {
+    if (threadIdx.x < kWave)
         run_glue(rl, rpc, scr.error);
+    if (threadIdx.x == 0)
         __hip_atomic_store(cnt, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    }
 }
 
 // ---------------------------------------------------------------------------

@@ -40,15 +40,37 @@ def test_binding_struct_layouts_match_header(tmp_path):
     from paper_2306_11686_amd import binding
     src = tmp_path / "sz.c"
     src.write_text('#include <stdio.h>\n#include <stddef.h>\n#include "gf.h"\n'
-                   'int main(void){printf("%zu %zu %zu %zu %zu %zu %zu\\n", sizeof(gf_step), sizeof(gf_instance),'
-                   ' sizeof(gf_launch), sizeof(gf_ctx_opts), sizeof(gf_run_stats), sizeof(gf_program),'
-                   ' offsetof(gf_step, chunk)); return 0;}\n')
+                   'int main(void){printf("%zu %zu %zu %zu %zu %zu %zu %zu %zu %zu\\n", sizeof(gf_step),'
+                   ' sizeof(gf_instance), sizeof(gf_launch), sizeof(gf_ctx_opts), sizeof(gf_run_stats),'
+                   ' sizeof(gf_program), offsetof(gf_step, chunk), sizeof(gf_call_arg), sizeof(gf_call_stats),'
+                   ' offsetof(gf_ctx_opts, rpc_payload)); return 0;}\n')
     exe = tmp_path / "sz"
     subprocess.check_call(["gcc", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)])
     got = [int(v) for v in subprocess.check_output([str(exe)]).split()]
     assert got == [ctypes.sizeof(gf.Step), ctypes.sizeof(gf.Instance), ctypes.sizeof(gf.Launch),
                    ctypes.sizeof(binding.CtxOpts), ctypes.sizeof(binding.RunStats), ctypes.sizeof(gf.Program),
-                   gf.Step.chunk.offset]
+                   gf.Step.chunk.offset, ctypes.sizeof(gf.CallArg), ctypes.sizeof(gf.CallStats),
+                   binding.CtxOpts.rpc_payload.offset]
+
+
+def test_binding_constants_match_header():
+    """Enumerators and limits of the host-call interface agree with the
+    header (compiled with gcc from include/gf.h)."""
+    import subprocess
+    import tempfile
+    import paper_2306_11686_amd as gf
+    names = ["GF_S_CALL", "GF_STEP_TIMED", "GF_CALLEE_FPRINTF", "GF_CALLEE_SNPRINTF", "GF_CALLEE_SSCANF",
+             "GF_CALLEE_FWRITE", "GF_CALLEE_FREAD", "GF_ARG_CONST", "GF_ARG_SCALAR", "GF_ARG_ITER", "GF_ARG_REF",
+             "GF_REF_READ", "GF_REF_WRITE", "GF_REF_READWRITE", "GF_CALL_MAX_ARGS", "GF_CALL_MAX_REFS",
+             "GF_CALL_MAX_SITES", "GF_S_PRINTF", "GF_STEP_BLOCKING"]
+    with tempfile.TemporaryDirectory() as d:
+        src = os.path.join(d, "c.c")
+        body = " ".join(f'printf("%ld\\n", (long)({n}));' for n in names)
+        open(src, "w").write(f'#include <stdio.h>\n#include "gf.h"\nint main(void){{{body} return 0;}}\n')
+        exe = os.path.join(d, "c")
+        subprocess.check_call(["gcc", "-I", os.path.join(ROOT, "include"), src, "-o", exe])
+        got = [int(v) for v in subprocess.check_output([exe]).split()]
+    assert got == [getattr(gf, n) for n in names]
 
 
 def test_programs_are_well_formed():
