@@ -7,16 +7,17 @@
  * run by one initial thread, interleaved with `parallel for` regions. Each
  * region's iterations are spread over every thread of every workgroup with
  * continuous global thread ids, and the implicit barrier at the end of a
- * region spans all workgroups. Host-only library calls (printf) made by the
- * initial thread are forwarded to the host by a synchronous client-server
- * remote procedure call (Section 2.3 "Host Remote Procedural Call",
- * Section 3.2 "Generating Remote Procedural Calls").
+ * region spans all workgroups. Host-only library calls (printf, fprintf,
+ * snprintf, sscanf, fwrite, fread) made by the initial thread are forwarded
+ * to the host by a synchronous client-server remote procedure call
+ * (Section 2.3 "Host Remote Procedural Call", Section 3.2 "Generating Remote
+ * Procedural Calls").
  *
  * A program is given as a step list (gf_program): a prologue run once and a
  * body run `iters` times. A step is either a REGION (a loop body from the
  * region catalogue below, optionally with one reduction clause into a scalar
  * variable) or a SERIAL op of the initial thread (scalar arithmetic, pointer
- * swap, history record, printf through RPC).
+ * swap, history record, printf or another host call through RPC).
  *
  * Reductions: the paper does not rewrite reduction clauses (Section 4.3), so
  * they follow OpenMP semantics: private copies start at the operator's

@@ -1,6 +1,6 @@
 """Measure the legacy-loop workloads other than the benchmark's headline.
 
-    python -m paper_2306_11686_amd.measure [--configs 2d,cg,hist,batched] [--reps 3]
+    python -m paper_2306_11686_amd.measure [--configs sync,2d,rpc,rpc_fprintf,cg,hist,batched] [--reps 3]
 
 Each configuration prints one JSON line: time per run in the persistent,
 per-region and per-region-graph modes, regions per second, and algorithmic
@@ -161,17 +161,64 @@ def measure_rpc(ctx, gf, programs, tuner, torch, reps):
     return out
 
 
+def measure_rpc_fprintf(ctx, gf, programs, tuner, torch, reps):
+    """The paper's RPC benchmark shape (Section 5, "RPC Performance"): 1000
+    blocking fprintf calls whose format string and 128-byte buffer are
+    passed by reference. The buffer goes both ways when its access mode is
+    unknown (read-write, the paper's case), and only to the host when it is
+    known to be read-only. The stream is /dev/null without buffering, so
+    every call makes one write system call, as fprintf to stderr does. The
+    per-stage times are averages over all timed calls."""
+    import ctypes
+    calls = 1000
+    libc = ctypes.CDLL(None)
+    libc.fopen.restype = ctypes.c_void_p
+    f = libc.fopen(b"/dev/null", b"w")
+    if not f:
+        return {"config": "rpc_fprintf_1000_calls_128B_buffer", "error": "cannot open /dev/null"}
+    libc.setvbuf(ctypes.c_void_p(f), None, 2, 0)  # _IONBF
+    fmt = b"buffer holds: %s\n\0"
+    text = (b"legacy program output line " * 5)[:120] + b"\0"
+    fmt_arr = torch.zeros(32, dtype=torch.uint8)
+    fmt_arr[:len(fmt)] = torch.tensor(list(fmt), dtype=torch.uint8)
+    buf = torch.zeros(128, dtype=torch.uint8)
+    buf[:len(text)] = torch.tensor(list(text), dtype=torch.uint8)
+    d_fmt, d_buf = fmt_arr.cuda(), buf.cuda()
+    sc = torch.zeros(16, dtype=torch.float64, device="cuda")
+    out = {"config": "rpc_fprintf_1000_calls_128B_buffer", "calls": calls}
+    with gf.Context(0, rpc_thread=True) as c2:
+        for name, bmode in (("buffer_read_write", gf.GF_REF_READWRITE), ("buffer_read_only", gf.GF_REF_READ)):
+            cid = c2.register_call(gf.GF_CALLEE_FPRINTF, [
+                gf.CallArg.const(f, "p"), gf.CallArg.ref(1, len(fmt), mode=gf.GF_REF_READ),
+                gf.CallArg.ref(0, 128, mode=bmode)])
+            body = [gf.Step.make(gf.GF_S_CALL, fmt_id=cid, every=1, flags=gf.GF_STEP_BLOCKING | gf.GF_STEP_TIMED)]
+            prog = gf.Program.make([], body, calls)
+            inst = gf.Instance.make({0: d_buf, 1: d_fmt}, sc)
+            launch = gf.Launch.make(num_wg=1, wg_size=64)
+            ms = _time(c2, torch, lambda: c2.run(prog, inst, mode=gf.GF_EXEC_PERSISTENT, launch=launch), reps)
+            st = c2.call_stats(cid, reset=True)
+            dev_total = st["dev_args_us"] + st["dev_copy_in_us"] + st["dev_wait_us"] + st["dev_copy_out_us"]
+            out[name] = {"ms_per_run": round(ms, 3), "us_per_call": round(ms * 1e3 / calls, 3),
+                         "stages_us": {k: round(v, 3) for k, v in st.items() if k != "calls"},
+                         "device_stage_share": {k: round(st[k] / dev_total, 4) for k in
+                                                ("dev_args_us", "dev_copy_in_us", "dev_wait_us",
+                                                 "dev_copy_out_us")},
+                         "timed_calls": st["calls"]}
+    libc.fclose(ctypes.c_void_p(f))
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
-    ap.add_argument("--configs", default="sync,2d,rpc,cg,hist,batched")
+    ap.add_argument("--configs", default="sync,2d,rpc,rpc_fprintf,cg,hist,batched")
     ap.add_argument("--reps", type=int, default=3)
     args = ap.parse_args()
     import torch
     import paper_2306_11686_amd as gf
     from paper_2306_11686_amd import programs, tuner
     ctx = gf.Context(0, rpc_capture=True, rpc_thread=True)
-    fns = {"sync": measure_sync, "2d": measure_2d, "rpc": measure_rpc, "cg": measure_cg, "hist": measure_hist,
-           "batched": measure_batched}
+    fns = {"sync": measure_sync, "2d": measure_2d, "rpc": measure_rpc, "rpc_fprintf": measure_rpc_fprintf,
+           "cg": measure_cg, "hist": measure_hist, "batched": measure_batched}
     for c in args.configs.split(","):
         log(f"[measure] {c}")
         print(json.dumps(fns[c](ctx, gf, programs, tuner, torch, args.reps)), flush=True)
