@@ -65,6 +65,7 @@ def _load():
         "or_max_u64": (ctypes.c_uint64, [I64, P]),
         "or_max_i64": (ctypes.c_int64, [I64, P]),
         "or_static_owner": (None, [I64, I64, I64, P]),
+        "or_phases": (None, [I64, P, P, I64, I64]),
     }
     for name, (res, args) in sig.items():
         f = getattr(lib, name)
@@ -210,6 +211,16 @@ def static_owner(n: int, nthreads: int, chunk: int = 0):
     owner = np.empty(n, dtype=np.int32)
     _load().or_static_owner(n, nthreads, chunk, _p(owner))
     return owner
+
+
+def phases(a0: np.ndarray, phases: int, shift: int):
+    """Producer/consumer phases (Section 3.3, manual worksharing with
+    barriers): returns (a, b) after the phases; the result is in b after an
+    odd number of phases, in a after an even one."""
+    a = np.array(a0, dtype=np.float64, copy=True)
+    b = np.zeros_like(a)
+    _load().or_phases(a.size, _p(a), _p(b), phases, shift)
+    return a, b
 
 
 # ----------------------------------------------------------------------------

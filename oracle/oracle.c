@@ -334,3 +334,22 @@ void or_static_owner(int64_t n, int64_t nthreads, int64_t chunk, int32_t *owner)
             owner[i] = (int32_t)t;
     }
 }
+
+/* Producer/consumer phases of a `parallel` region with manual worksharing
+ * and barriers (Section 3.3). Every phase p computes dst[i] = src[i] +
+ * src[(i + shift) % n] for all i and then swaps the roles of the two
+ * arrays. Which thread computes which i, and the barrier that separates the
+ * phases, do not change the values, so the serial program is these loops in
+ * index order. The result ends in a after an even number of phases and in
+ * b after an odd one. */
+void or_phases(int64_t n, double *a, double *b, int64_t phases, int64_t shift)
+{
+    double *src = a, *dst = b;
+    for (int64_t p = 0; p < phases; ++p) {
+        for (int64_t i = 0; i < n; ++i)
+            dst[i] = src[i] + src[(i + shift) % n];
+        double *t = src;
+        src = dst;
+        dst = t;
+    }
+}

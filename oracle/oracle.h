@@ -97,6 +97,7 @@ int64_t or_max_i64(int64_t n, const int64_t *x);
  * contiguous blocks whose sizes differ by at most one (the first n % T get
  * one more); chunk > 0 deals chunks of that size round-robin. */
 void or_static_owner(int64_t n, int64_t nthreads, int64_t chunk, int32_t *owner);
+void or_phases(int64_t n, double *a, double *b, int64_t phases, int64_t shift);
 
 #ifdef __cplusplus
 }

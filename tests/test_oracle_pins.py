@@ -404,3 +404,39 @@ def test_adam_first_step_closed_form(oracle_lib):
     p = np.array([1.0, 1.0, 1.0, 1.0])
     p1, m1, v1 = oracle_lib.adam_step(p, g, np.zeros(4), np.zeros(4), 1, lr=0.01)
     assert np.allclose(p1, p - 0.01 * g / (np.abs(g) + 1e-8), rtol=1e-12, atol=0)
+
+
+# ---------------------------------------------------------------------------
+# Producer/consumer phases (manual worksharing with barriers, Section 3.3)
+# ---------------------------------------------------------------------------
+
+def _phase_result(a, b, phases):
+    return b if phases % 2 else a
+
+
+@pytest.mark.parametrize("n,phases,shift", [(10, 3, 4), (7, 5, 0), (13, 1, 12), (64, 6, 17)])
+def test_phases_of_all_ones_double_every_phase(oracle_lib, n, phases, shift):
+    a, b = oracle_lib.phases(np.ones(n), phases, shift)
+    assert np.array_equal(_phase_result(a, b, phases), np.full(n, 2.0 ** phases))
+
+
+@pytest.mark.parametrize("n,phases,shift,k", [(11, 4, 3, 5), (16, 5, 6, 0), (9, 3, 8, 8), (30, 6, 7, 29)])
+def test_phases_of_a_unit_impulse_count_binomial_paths(oracle_lib, n, phases, shift, k):
+    """Phase p adds the value s places ahead, so after P phases element i
+    holds sum over m of C(P, m) * a0[(i + m*s) mod n]: with a unit impulse at
+    k, the binomial weights of the m with i + m*s = k (mod n)."""
+    import math
+    a0 = np.zeros(n)
+    a0[k] = 1.0
+    a, b = oracle_lib.phases(a0, phases, shift)
+    want = np.array([sum(math.comb(phases, m) for m in range(phases + 1) if (i + m * shift) % n == k)
+                     for i in range(n)], dtype=np.float64)
+    assert np.array_equal(_phase_result(a, b, phases), want)
+
+
+def test_one_phase_adds_the_rotated_array(oracle_lib):
+    rng = np.random.default_rng(3)
+    a0 = rng.standard_normal(101)
+    a, b = oracle_lib.phases(a0, 1, 37)
+    assert np.array_equal(a, a0)                      # the source is only read
+    assert np.array_equal(b, a0 + np.roll(a0, -37))  # b[i] = a[i] + a[(i + 37) % n]
