@@ -103,6 +103,21 @@ typedef enum {
  * GF_R_HIST      arr[0]=keys (u32, n), arr[1]=bins (u32); bins[key & mask] += 1.
  * GF_R_OWNER     arr[0]=owner (i32, n): owner[i] = continuous global thread
  *                id that executed iteration i under schedule(static[,chunk]).
+ * GF_R_PHASES    a `parallel` region with manual worksharing and barriers
+ *                (Section 3.3: thread-id queries and `omp barrier` rewritten
+ *                to span all workgroups). Thread t of T (the global
+ *                omp_get_thread_num / omp_get_num_threads, continuous across
+ *                workgroups) owns the block [t*q + min(t,r), (t+1)*q +
+ *                min(t+1,r)) of [0, n), q = n / T, r = n % T. For phase
+ *                p = 0 .. P-1 (P = chunk >= 1) it computes, over its block,
+ *                dst[i] = src[i] + src[(i + s) % n] with s = mask (< n), then
+ *                all threads meet at an `omp barrier` before the next phase
+ *                reads what other workgroups wrote. src and dst start as
+ *                arr[0] and arr[1] (f64, n) and swap after every phase, so the
+ *                result is in arr[P % 2]. arr[2] (optional, -1 for none; i32,
+ *                n): owner[i] = t. No reduction clause. Per-region launches
+ *                use at most one co-resident wave of workgroups (the in-region
+ *                barrier needs all of them resident).
  *
  * Serial kinds (the initial thread; scal = the instance's scalar variables,
  * `iter` = 0-based body iteration, -1 in the prologue):
@@ -136,6 +151,7 @@ typedef enum {
     GF_R_AXPBY = 5,
     GF_R_HIST = 6,
     GF_R_OWNER = 7,
+    GF_R_PHASES = 8,
     GF_S_SET = 32,
     GF_S_COPY = 33,
     GF_S_DIV = 34,
@@ -160,8 +176,10 @@ typedef struct {
                           GF_S_CALL call-site id from gf_rpc_register_call */
     int32_t nargs;     /* GF_S_PRINTF argument count incl. the iteration number */
     uint32_t flags;    /* GF_STEP_BLOCKING, GF_STEP_TIMED */
-    uint32_t mask;     /* GF_R_HIST bin mask (nbins - 1, nbins a power of two) */
-    int64_t chunk;     /* GF_R_OWNER schedule(static, chunk); 0 = schedule(static) */
+    uint32_t mask;     /* GF_R_HIST bin mask (nbins - 1, nbins a power of two);
+                          GF_R_PHASES shift s */
+    int64_t chunk;     /* GF_R_OWNER schedule(static, chunk), 0 = schedule(static);
+                          GF_R_PHASES phase count */
     double c;          /* constant of GF_S_SET / GF_R_AXPBY */
 } gf_step;
 

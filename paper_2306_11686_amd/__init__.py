@@ -11,7 +11,7 @@ from __future__ import annotations
 from .binding import (  # noqa: F401
     GF_EXEC_PER_REGION, GF_EXEC_PERSISTENT, GF_EXEC_PER_REGION_GRAPH, GF_EXEC_KERNEL_SPLIT,
     GF_OP_SUM, GF_OP_MAX, GF_OP_NONE, GF_F64, GF_U32, GF_U64, GF_I64,
-    GF_R_JACOBI2D, GF_R_JACOBI3D, GF_R_SPMV, GF_R_DOT, GF_R_AXPBY, GF_R_HIST, GF_R_OWNER,
+    GF_R_JACOBI2D, GF_R_JACOBI3D, GF_R_SPMV, GF_R_DOT, GF_R_AXPBY, GF_R_HIST, GF_R_OWNER, GF_R_PHASES,
     GF_S_SET, GF_S_COPY, GF_S_DIV, GF_S_SQRT, GF_S_SWAP, GF_S_RECORD, GF_S_PRINTF, GF_S_CALL,
     GF_STEP_BLOCKING, GF_STEP_TIMED, GF_NUM_CANDIDATES, GF_MLP_IN, GF_MLP_HIDDEN, GF_MLP_OUT, GF_MLP_NPARAMS,
     GF_CALLEE_FPRINTF, GF_CALLEE_SNPRINTF, GF_CALLEE_SSCANF, GF_CALLEE_FWRITE, GF_CALLEE_FREAD,

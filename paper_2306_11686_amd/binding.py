@@ -15,7 +15,8 @@ GF_OP_SUM, GF_OP_MAX, GF_OP_NONE = 0, 1, -1
 GF_F64, GF_U32, GF_U64, GF_I64 = 0, 1, 2, 3
 GF_EXEC_PER_REGION, GF_EXEC_PERSISTENT, GF_EXEC_PER_REGION_GRAPH, GF_EXEC_KERNEL_SPLIT = 0, 1, 2, 3
 
-GF_R_JACOBI2D, GF_R_JACOBI3D, GF_R_SPMV, GF_R_DOT, GF_R_AXPBY, GF_R_HIST, GF_R_OWNER = 1, 2, 3, 4, 5, 6, 7
+GF_R_JACOBI2D, GF_R_JACOBI3D, GF_R_SPMV, GF_R_DOT, GF_R_AXPBY, GF_R_HIST, GF_R_OWNER, GF_R_PHASES = \
+    1, 2, 3, 4, 5, 6, 7, 8
 GF_S_SET, GF_S_COPY, GF_S_DIV, GF_S_SQRT, GF_S_SWAP, GF_S_RECORD, GF_S_PRINTF, GF_S_CALL = \
     32, 33, 34, 35, 36, 37, 38, 39
 GF_STEP_BLOCKING, GF_STEP_TIMED = 1, 2

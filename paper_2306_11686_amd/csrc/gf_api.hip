@@ -780,7 +780,7 @@ int64_t gf_rpc_take_output(gf_ctx *ctx, char *buf, int64_t cap)
 
 namespace {
 
-bool is_region(int k) { return k >= GF_R_JACOBI2D && k <= GF_R_OWNER; }
+bool is_region(int k) { return k >= GF_R_JACOBI2D && k <= GF_R_PHASES; }
 bool is_serial(int k) { return k >= GF_S_SET && k <= GF_S_CALL; }
 
 int region_nops(int k)
@@ -799,10 +799,15 @@ int region_nops(int k)
         return 2;
     case GF_R_OWNER:
         return 1;
+    case GF_R_PHASES:
+        return 3;  // the owner map (operand 2) is optional
     default:
         return 0;
     }
 }
+
+// An operand a region may leave unbound (-1).
+bool optional_operand(int kind, int k) { return kind == GF_R_PHASES && k == 2; }
 
 gf_status check_step(gf_ctx *ctx, const gf_step &s, int idx)
 {
@@ -810,7 +815,7 @@ gf_status check_step(gf_ctx *ctx, const gf_step &s, int idx)
     auto sc_ok = [](int a) { return a >= 0 && a < GF_MAX_SCALARS; };
     if (is_region(s.kind)) {
         for (int k = 0; k < region_nops(s.kind); ++k)
-            if (!slot_ok(s.arr[k]))
+            if (!slot_ok(s.arr[k]) && !(optional_operand(s.kind, k) && s.arr[k] == -1))
                 return fail(ctx, GF_EINVAL, "step %d: array operand %d out of range", idx, k);
         if (s.np < 0 || s.np >= GF_MAX_IPARAMS)
             return fail(ctx, GF_EINVAL, "step %d: size index out of range", idx);
@@ -832,6 +837,11 @@ gf_status check_step(gf_ctx *ctx, const gf_step &s, int idx)
             return fail(ctx, GF_EINVAL, "step %d: histogram mask must be 2^k - 1 with at most 2^20 bins", idx);
         if (s.kind == GF_R_OWNER && s.chunk < 0)
             return fail(ctx, GF_EINVAL, "step %d: negative chunk", idx);
+        if (s.kind == GF_R_PHASES && (s.chunk < 1 || s.chunk > (1 << 20)))
+            return fail(ctx, GF_EINVAL, "step %d: phase count must be 1 .. 2^20", idx);
+        if (s.kind == GF_R_PHASES && (s.arr[0] == s.arr[1] || s.arr[2] == s.arr[0] || s.arr[2] == s.arr[1]))
+            return fail(ctx, GF_EINVAL, "step %d: the two phase buffers and the owner map must be distinct slots",
+                        idx);
         return GF_OK;
     }
     if (!is_serial(s.kind))
@@ -1010,14 +1020,19 @@ gf_status build_program(gf_ctx *ctx, const gf_program *prog, DProg *out)
     }
     if (program_mixes_hist(*out))
         return fail(ctx, GF_EUNSUPPORTED, "a histogram region can only share a program with schedule regions");
-    // last region in execution order and the number of grid barriers (a
-    // histogram region has one inside it)
+    // last region in execution order and the number of grid barriers
     out->last_region = -1;
     int64_t bar_pro = 0, bar_body = 0;
     for (int i = 0; i < out->n_steps; ++i) {
         if (!is_region(out->steps[i].kind))
             continue;
-        const int64_t b = out->steps[i].kind == GF_R_HIST ? 2 : 1;
+        // a histogram region has one barrier inside it, a phase region one
+        // between consecutive phases
+        int64_t b = 1;
+        if (out->steps[i].kind == GF_R_HIST)
+            b = 2;
+        else if (out->steps[i].kind == GF_R_PHASES)
+            b = out->steps[i].chunk;
         if (i < out->n_pro) {
             bar_pro += b;
             out->last_region = i;
@@ -1077,7 +1092,7 @@ gf_status check_instance(gf_ctx *ctx, const DProg &p, const gf_instance &in, con
         }
         if (is_region(s.kind)) {
             for (int k = 0; k < region_nops(s.kind); ++k)
-                if (!in.arr[s.arr[k]])
+                if (s.arr[k] >= 0 && !in.arr[s.arr[k]])
                     return fail(ctx, GF_EINVAL, "instance %d step %d: null array in slot %d", idx, i, s.arr[k]);
             const int64_t n = in.ip[s.np];
             if (n < 0)
@@ -1087,6 +1102,11 @@ gf_status check_instance(gf_ctx *ctx, const DProg &p, const gf_instance &in, con
             if (s.kind == GF_R_HIST && ((uintptr_t)in.arr[s.arr[0]] % 16) != 0)
                 return fail(ctx, GF_EINVAL, "instance %d step %d: histogram keys must be 16-byte aligned", idx, i);
             if (s.kind == GF_R_OWNER && n > INT32_MAX)
+                return fail(ctx, GF_EINVAL, "instance %d step %d: owner map larger than int32", idx, i);
+            if (s.kind == GF_R_PHASES && n > 0 && (int64_t)s.mask >= n)
+                return fail(ctx, GF_EINVAL, "instance %d step %d: phase shift %u must be below n = %lld", idx, i,
+                            s.mask, (long long)n);
+            if (s.kind == GF_R_PHASES && s.arr[2] >= 0 && n > INT32_MAX)
                 return fail(ctx, GF_EINVAL, "instance %d step %d: owner map larger than int32", idx, i);
             if (s.red_op != GF_OP_NONE && region_items(s, n, t) > ctx->scr.partials_cap)
                 return fail(ctx, GF_EINVAL, "instance %d step %d: %lld reduction tiles exceed the partials capacity",
@@ -1122,6 +1142,8 @@ int region_grid(const gf_ctx *ctx, const DStep &s, int64_t items, const Tiling &
 {
     if (s.kind == GF_R_OWNER)
         return std::max(1, ctx->num_cu);
+    if (s.kind == GF_R_PHASES)
+        return std::max(1, std::min(ctx->num_cu, phases_capacity(t.wg_size, ctx->num_cu)));
     if (s.kind == GF_R_HIST)
         return hist_grid(std::min<int64_t>(std::max<int64_t>(items, 1), (int64_t)ctx->num_cu * 2), s.mask);
     const int64_t cap = (int64_t)ctx->num_cu * 16;
@@ -1143,7 +1165,17 @@ gf_status launch_one(gf_ctx *ctx, const RegionLaunch &cur, const Tiling &t, cons
         if (l && l->num_wg > 0)
             grid = cur.step.kind == GF_R_HIST ? hist_grid(l->num_wg, cur.step.mask) : l->num_wg;
     }
-    if (cur.step.kind == GF_R_HIST) {
+    if (cur.step.kind == GF_R_PHASES) {
+        // every workgroup must be resident for the in-region barrier
+        const int cap = phases_capacity(t.wg_size, ctx->num_cu);
+        if (cap < 1)
+            return fail(ctx, GF_EHIP, "phase region: no co-resident capacity");
+        grid = std::max(1, std::min(grid, cap));
+        hipError_t e = launch_phases(cur, t.wg_size, grid, ctx->scr, rpc, stream);
+        if (e != hipSuccess)
+            return hipfail(ctx, e, "phase region launch");
+        *launches += 1;
+    } else if (cur.step.kind == GF_R_HIST) {
         RegionLaunch p1 = cur;
         p1.n_glue = 0;
         hipError_t e = launch_region(p1, t, grid, ctx->scr, rpc, stream);

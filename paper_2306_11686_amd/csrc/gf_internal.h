@@ -253,6 +253,9 @@ int64_t region_items(const DStep &st, int64_t n, const Tiling &t);
 bool program_is_hist_family(const DProg &prog);
 bool program_mixes_hist(const DProg &prog);
 int64_t hist_parts(uint32_t mask);
+hipError_t launch_phases(const RegionLaunch &rl, int wg_size, int num_wg, const Scratch &scr, const RpcRing &rpc,
+                         hipStream_t s);
+int phases_capacity(int wg_size, int num_cu);
 hipError_t launch_hist_merge(const RegionLaunch &rl, int64_t rows_used, const Scratch &scr, const RpcRing &rpc,
                              int num_cu, hipStream_t s);
 

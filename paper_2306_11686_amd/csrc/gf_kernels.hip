@@ -822,6 +822,39 @@ __device__ __forceinline__ void owner_region(int32_t *owner, int64_t n, int64_t 
     }
 }
 
+// GF_R_PHASES: a `parallel` region with manual worksharing (Section 3.3):
+// thread t of T owns a balanced contiguous block of [0, n) and runs P
+// producer/consumer phases, each reading what other threads (and
+// workgroups) wrote in the previous one; `bar` is the `omp barrier` across
+// all workgroups between phases (the region's own end barrier follows the
+// last one). Returns false if a barrier failed.
+template <typename Bar>
+__device__ bool phases_region(GF_GLOBAL double *a, GF_GLOBAL double *b, GF_GLOBAL int32_t *owner, int64_t n,
+                              int64_t P, int64_t shift, int64_t t, int64_t T, Bar bar)
+{
+    int64_t lo, hi;
+    static_range(n, T, t, &lo, &hi);
+    if (owner)
+        for (int64_t i = lo; i < hi; ++i)
+            owner[i] = (int32_t)t;
+    GF_GLOBAL const double *src = a;
+    GF_GLOBAL double *dst = b;
+    for (int64_t p = 0; p < P; ++p) {
+        if (p > 0 && !bar())
+            return false;
+        for (int64_t i = lo; i < hi; ++i) {
+            int64_t k = i + shift;
+            if (k >= n)
+                k -= n;
+            dst[i] = src[i] + src[k];
+        }
+        GF_GLOBAL double *nsrc = dst;
+        dst = (GF_GLOBAL double *)src;
+        src = nsrc;
+    }
+    return true;
+}
+
 // Executes one work item of a region; returns the thread's reduction value.
 // op[i] is the region's i-th array operand (slot st.arr[i] resolved by the
 // caller); s is the AXPBY coefficient scal[st.sc[1]] * st.c.
@@ -1145,6 +1178,13 @@ __global__ void __launch_bounds__(family_max_threads<KMASK>())
             const double coef = uniform_f64((st.kind == GF_R_AXPBY) ? s_scal[st.sc[1]] * st.c : 0.0);
             if (st.kind == GF_R_OWNER) {
                 owner_region((int32_t *)op[0], n, st.chunk, G * blockDim.x, member * blockDim.x + threadIdx.x);
+            } else if (st.kind == GF_R_PHASES) {
+                if constexpr ((KMASK >> GF_R_PHASES) & 1u) {
+                    if (!phases_region(gptr((double *)op[0]), gptr((double *)op[1]), gptr((int32_t *)op[2]), n,
+                                       st.chunk, (int64_t)st.mask, member * blockDim.x + threadIdx.x,
+                                       G * blockDim.x, barrier))
+                        return;
+                }
             } else if (st.kind == GF_R_HIST) {
                 if constexpr ((KMASK >> GF_R_HIST) & 1u) {
                     hist_phase1((const uint32_t *)op[0], (uint32_t *)op[1], scr.hist_rows, st.mask, n, worker, G, t);
@@ -1422,13 +1462,80 @@ __global__ void __launch_bounds__(kMaxWg) k_hist_merge(RegionLaunch rl, int64_t 
 }
 
 // ---------------------------------------------------------------------------
+// Per-region launch of GF_R_PHASES: the in-region barrier is a grid barrier
+// inside the kernel (the persistent kernel's counters, free while no
+// persistent launch of this context runs), so the host launches at most one
+// co-resident wave of workgroups. The last workgroup runs the glue.
+// ---------------------------------------------------------------------------
+
+__global__ void __launch_bounds__(kMaxWg) k_phases(RegionLaunch rl, Scratch scr, RpcRing rpc)
+{
+    __shared__ BarrierState s_bar;
+    __shared__ int s_last;
+    const int64_t G = gridDim.x;
+    uint32_t *genw = scr.lines + 1;
+    uint32_t *tree = scr.lines + kTreeLine0 * kLineWords;
+    if (threadIdx.x == 0) {
+        s_bar.gen = __hip_atomic_load(genw, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        s_bar.ok = 1;
+    }
+    __syncthreads();
+    auto bar = [&]() -> bool {
+        if (G == 1) {
+            __builtin_amdgcn_s_waitcnt(0x0F70);
+            __syncthreads();
+            return true;
+        }
+        return tree_barrier(genw, tree, blockIdx.x, (uint32_t)G, &s_bar, scr.error, scr.barrier_timeout_ticks);
+    };
+    if (!phases_region(gptr((double *)rl.arr[0]), gptr((double *)rl.arr[1]), gptr((int32_t *)rl.arr[2]), rl.n,
+                       rl.step.chunk, (int64_t)rl.step.mask, (int64_t)blockIdx.x * blockDim.x + threadIdx.x,
+                       G * blockDim.x, bar))
+        return;
+    if (rl.n_glue == 0)
+        return;
+    uint32_t *cnt = scr.lines + (int64_t)(kFinalizeLine0 + rl.inst) * kLineWords;
+    wg_publish();
+    if (threadIdx.x == 0) {
+        const uint32_t a = __hip_atomic_fetch_add(cnt, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        s_last = (a == (uint32_t)G - 1);
+    }
+    __syncthreads();
+    if (!s_last)
+        return;
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+    if (threadIdx.x < kWave)
+        run_glue(rl, rpc, scr.error);
+    if (threadIdx.x == 0)
+        __hip_atomic_store(cnt, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+hipError_t launch_phases(const RegionLaunch &rl, int wg_size, int num_wg, const Scratch &scr, const RpcRing &rpc,
+                         hipStream_t s)
+{
+    hipLaunchKernelGGL(k_phases, dim3(num_wg), dim3(wg_size), 0, s, rl, scr, rpc);
+    return hipGetLastError();
+}
+
+int phases_capacity(int wg_size, int num_cu)
+{
+    int per_cu = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, reinterpret_cast<const void *>(k_phases), wg_size, 0) !=
+        hipSuccess)
+        return 0;
+    // one slot per CU is left free (the kernel split's main kernel may hold one)
+    return (per_cu > 1 ? per_cu - 1 : per_cu) * num_cu;
+}
+
+// ---------------------------------------------------------------------------
 // Kernel selection. Families: the bodies a program uses decide which
 // instantiation runs, so a program only pays the registers of its own bodies.
 // ---------------------------------------------------------------------------
 
 constexpr unsigned kFamJ3 = (1u << GF_R_JACOBI3D) | (1u << GF_R_OWNER);
 constexpr unsigned kFamJ2 = (1u << GF_R_JACOBI2D) | (1u << GF_R_OWNER);
-constexpr unsigned kFamVec = (1u << GF_R_SPMV) | (1u << GF_R_DOT) | (1u << GF_R_AXPBY) | (1u << GF_R_OWNER);
+constexpr unsigned kFamVec =
+    (1u << GF_R_SPMV) | (1u << GF_R_DOT) | (1u << GF_R_AXPBY) | (1u << GF_R_OWNER) | (1u << GF_R_PHASES);
 constexpr unsigned kFamAll = kFamJ3 | kFamJ2 | kFamVec;  // the histogram runs only in its own family
 
 static unsigned program_kinds(const DProg &p)

@@ -11,8 +11,8 @@ from __future__ import annotations
 import math
 
 from .binding import (GF_OP_MAX, GF_OP_NONE, GF_OP_SUM, GF_R_AXPBY, GF_R_DOT, GF_R_HIST, GF_R_JACOBI2D,
-                      GF_R_JACOBI3D, GF_R_OWNER, GF_R_SPMV, GF_S_COPY, GF_S_DIV, GF_S_PRINTF, GF_S_RECORD,
-                      GF_S_SET, GF_S_SQRT, GF_S_SWAP, Program, Step)
+                      GF_R_JACOBI3D, GF_R_OWNER, GF_R_PHASES, GF_R_SPMV, GF_S_COPY, GF_S_DIV, GF_S_PRINTF,
+                      GF_S_RECORD, GF_S_SET, GF_S_SQRT, GF_S_SWAP, Program, Step)
 
 JACOBI2D_FORMAT = "sweep %d residual %.10e\n"
 
@@ -96,3 +96,13 @@ def histogram(nbins: int = 65536) -> Program:
 def owner_map(chunk: int = 0) -> Program:
     """One schedule(static[,chunk]) region writing the executing global thread id."""
     return Program.make([Step.make(GF_R_OWNER, arr=(0,), np=0, chunk=chunk)], [], 0)
+
+
+def phases(n_phases: int, shift: int, owner: bool = True) -> Program:
+    """One `parallel` region with manual worksharing: each thread's block of
+    [0, n) goes through n_phases producer/consumer phases separated by
+    barriers across all workgroups (arrays 0 and 1 = the two buffers, 2 = the
+    owner map when requested; ip[0] = n). The result is in array
+    n_phases % 2."""
+    return Program.make([Step.make(GF_R_PHASES, arr=(0, 1, 2 if owner else -1), np=0, chunk=n_phases,
+                                   mask=shift)], [], 0)
