@@ -20,13 +20,19 @@ LIB = os.path.join(HERE, "libgf.so")
 ARCH = "gfx950"
 
 
+# The sources the region kernels (persistent and per-region) are compiled
+# from: the device code, its headers and the public header it includes.
+KERNEL_SOURCES = ("csrc/gf_kernels.hip", "csrc/gf_device.h", "csrc/gf_internal.h", "../include/gf.h")
+
+
 def kernel_source_hash() -> str:
-    """Short hash of every kernel source under csrc/:
-    measurements tied to the kernels record it and lapse when it changes."""
+    """Short hash of the sources of the region kernels: measurements tied
+    to those kernels (HBM traffic counters) record it and lapse when it
+    changes."""
     import hashlib
     h = hashlib.sha256()
-    for fn in sorted(os.listdir(CSRC)):
-        with open(os.path.join(CSRC, fn), "rb") as f:
+    for rel in KERNEL_SOURCES:
+        with open(os.path.normpath(os.path.join(HERE, rel)), "rb") as f:
             h.update(f.read())
     return h.hexdigest()[:16]
 

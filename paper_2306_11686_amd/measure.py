@@ -1,6 +1,6 @@
 """Measure the legacy-loop workloads other than the benchmark's headline.
 
-    python -m paper_2306_11686_amd.measure [--configs sync,2d,rpc,rpc_fprintf,cg,hist,batched] [--reps 3]
+    python -m paper_2306_11686_amd.measure [--configs sync,2d,rpc,rpc_fprintf,phases,cg,hist,batched] [--reps 3]
 
 Each configuration prints one JSON line: time per run in the persistent,
 per-region and per-region-graph modes, regions per second, and algorithmic
@@ -208,9 +208,38 @@ def measure_rpc_fprintf(ctx, gf, programs, tuner, torch, reps):
     return out
 
 
+def measure_phases(ctx, gf, programs, tuner, torch, reps):
+    """A `parallel` region with manual worksharing: 2^22 doubles, 100
+    producer/consumer phases separated by barriers across all workgroups
+    (the persistent kernel's barrier, or the per-region kernel's own).
+    Each thread walks its own contiguous block, as the legacy code does, so
+    a wavefront's accesses are strided by the block length. Algorithmic
+    bytes per phase: one read of the source and one write of the
+    destination, 16 n."""
+    n, P, shift = 1 << 22, 100, (1 << 22) // 3
+    a = torch.rand(n, dtype=torch.float64, device="cuda")
+    b = torch.zeros_like(a)
+    sc = torch.zeros(16, dtype=torch.float64, device="cuda")
+    inst = gf.Instance.make({0: a, 1: b}, sc, ip=(n,))
+    prog = programs.phases(P, shift, owner=False)
+    out = {"config": "phases_2^22_f64_100phases", "alg_bytes_per_phase": 16 * n}
+    for name, mode in MODES[:2]:
+        for nwg in (256, 1024):
+            launch = gf.Launch.make(wg_size=256, num_wg=nwg)
+            try:
+                ms = _time(ctx, torch, lambda: ctx.run(prog, inst, mode=mode, launch=launch), reps)
+            except gf.GfError:
+                continue
+            st = ctx.run(prog, inst, mode=mode, launch=launch)
+            ctx.sync()
+            out[f"{name}_wg{nwg}"] = {"ms_per_run": round(ms, 3), "us_per_phase": round(ms * 1e3 / P, 2),
+                                      "GBps": round(16 * n * P / (ms * 1e-3) / 1e9, 1), "grid": st["num_wg"]}
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
-    ap.add_argument("--configs", default="sync,2d,rpc,rpc_fprintf,cg,hist,batched")
+    ap.add_argument("--configs", default="sync,2d,rpc,rpc_fprintf,phases,cg,hist,batched")
     ap.add_argument("--reps", type=int, default=3)
     args = ap.parse_args()
     import torch
@@ -218,7 +247,7 @@ def main():
     from paper_2306_11686_amd import programs, tuner
     ctx = gf.Context(0, rpc_capture=True, rpc_thread=True)
     fns = {"sync": measure_sync, "2d": measure_2d, "rpc": measure_rpc, "rpc_fprintf": measure_rpc_fprintf,
-           "cg": measure_cg, "hist": measure_hist, "batched": measure_batched}
+           "phases": measure_phases, "cg": measure_cg, "hist": measure_hist, "batched": measure_batched}
     for c in args.configs.split(","):
         log(f"[measure] {c}")
         print(json.dumps(fns[c](ctx, gf, programs, tuner, torch, args.reps)), flush=True)
