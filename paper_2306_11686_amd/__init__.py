@@ -17,6 +17,8 @@ from .binding import (  # noqa: F401
     GF_CALLEE_FPRINTF, GF_CALLEE_SNPRINTF, GF_CALLEE_SSCANF, GF_CALLEE_FWRITE, GF_CALLEE_FREAD,
     GF_ARG_CONST, GF_ARG_SCALAR, GF_ARG_ITER, GF_ARG_REF, GF_REF_READ, GF_REF_WRITE, GF_REF_READWRITE,
     GF_CALL_MAX_ARGS, GF_CALL_MAX_REFS, GF_CALL_MAX_SITES,
+    GF_HEAP_OP_MALLOC, GF_HEAP_OP_FREE, GF_HEAP_OP_FIND, GF_HEAP_BENCH_ROUNDTRIP, GF_HEAP_BENCH_HOLD,
+    GF_HEAP_BENCH_RELEASE, Heap,
     GfError, Context, Step, Launch, Program, Instance, CallArg, CallStats, host_stream, lib_path, load_library,
     exported_symbols, tune_pick,
 )

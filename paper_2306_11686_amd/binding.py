@@ -154,6 +154,15 @@ class CallArg(ctypes.Structure):
         return a
 
 
+class HeapOpts(ctypes.Structure):
+    _fields_ = [("bytes", ctypes.c_int64), ("thread_slots", ctypes.c_int32), ("team_slots", ctypes.c_int32),
+                ("first_ratio", ctypes.c_int32), ("vendor", ctypes.c_int32), ("lock_timeout_us", ctypes.c_int64)]
+
+
+GF_HEAP_OP_MALLOC, GF_HEAP_OP_FREE, GF_HEAP_OP_FIND = 1, 2, 3
+GF_HEAP_BENCH_ROUNDTRIP, GF_HEAP_BENCH_HOLD, GF_HEAP_BENCH_RELEASE = 0, 1, 2
+
+
 class CallStats(ctypes.Structure):
     _fields_ = [("calls", ctypes.c_int64), ("dev_args_us", ctypes.c_double), ("dev_copy_in_us", ctypes.c_double),
                 ("dev_wait_us", ctypes.c_double), ("dev_copy_out_us", ctypes.c_double),
@@ -201,6 +210,15 @@ _SIGS = {
                                               ctypes.c_int32]),
     "gf_rpc_call_stats": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.POINTER(CallStats),
                                          ctypes.c_int32]),
+    "gf_heap_create": (ctypes.c_int, [ctypes.c_int32, ctypes.POINTER(HeapOpts), ctypes.POINTER(ctypes.c_void_p)]),
+    "gf_heap_destroy": (ctypes.c_int, [ctypes.c_void_p]),
+    "gf_heap_reset": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p]),
+    "gf_heap_script": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int32, ctypes.c_void_p,
+                                      ctypes.c_void_p]),
+    "gf_heap_bench": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_int32, ctypes.c_int64,
+                                     ctypes.c_int32, ctypes.c_void_p, ctypes.c_void_p]),
+    "gf_heap_counts": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_uint64), ctypes.c_int32]),
+    "gf_heap_tops": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_uint32), ctypes.c_int32]),
     "gf_sync": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.POINTER(RunStats)]),
     "gf_persistent_capacity": (ctypes.c_int32, [ctypes.c_void_p, ctypes.POINTER(Program), ctypes.c_int32]),
     "gf_copy": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64, ctypes.c_int32,
@@ -447,3 +465,61 @@ class Context:
 
     def copy(self, dst, src, nbytes: int, num_wg: int = 0, stream=None):
         self._check(self.lib.gf_copy(self.h, _ptr(dst), _ptr(src), nbytes, num_wg, _stream_handle(stream)))
+
+
+class Heap:
+    """The balanced device heap (include/gf_heap.h)."""
+
+    def __init__(self, device: int = 0, nbytes: int = 1 << 26, thread_slots: int = 32, team_slots: int = 16,
+                 first_ratio: int = 4, vendor: bool = False, lock_timeout_us: int = 0):
+        self.lib = load_library()
+        self.opts = HeapOpts(nbytes, thread_slots, team_slots, first_ratio, 1 if vendor else 0, lock_timeout_us)
+        h = ctypes.c_void_p()
+        st = self.lib.gf_heap_create(device, ctypes.byref(self.opts), ctypes.byref(h))
+        if st != GF_OK:
+            raise GfError(st, "gf_heap_create failed")
+        self.h = h
+
+    def close(self):
+        if getattr(self, "h", None):
+            self.lib.gf_heap_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()
+
+    def _check(self, st, what):
+        if st != GF_OK:
+            raise GfError(st, what)
+
+    def reset(self, stream=None):
+        self._check(self.lib.gf_heap_reset(self.h, _stream_handle(stream)), "gf_heap_reset")
+
+    def script(self, d_ops, n_ops: int, d_res, stream=None):
+        self._check(self.lib.gf_heap_script(self.h, _ptr(d_ops), n_ops, _ptr(d_res), _stream_handle(stream)),
+                    "gf_heap_script")
+
+    def bench(self, teams: int, threads: int, nbytes: int, mode: int = GF_HEAP_BENCH_ROUNDTRIP, d_ptrs=None,
+              stream=None):
+        self._check(self.lib.gf_heap_bench(self.h, teams, threads, nbytes, mode, _ptr(d_ptrs),
+                                           _stream_handle(stream)), "gf_heap_bench")
+
+    def counts(self, reset: bool = False) -> dict:
+        out = (ctypes.c_uint64 * 4)()
+        self._check(self.lib.gf_heap_counts(self.h, out, 1 if reset else 0), "gf_heap_counts")
+        return {"null": out[0], "corrupt": out[1], "timeouts": out[2], "bad_frees": out[3]}
+
+    def tops(self):
+        n = self.opts.thread_slots * self.opts.team_slots
+        out = (ctypes.c_uint32 * n)()
+        self._check(self.lib.gf_heap_tops(self.h, out, n), "gf_heap_tops")
+        return list(out)

@@ -44,13 +44,16 @@ def test_binding_struct_layouts_match_header(tmp_path):
                    ' sizeof(gf_instance), sizeof(gf_launch), sizeof(gf_ctx_opts), sizeof(gf_run_stats),'
                    ' sizeof(gf_program), offsetof(gf_step, chunk), sizeof(gf_call_arg), sizeof(gf_call_stats),'
                    ' offsetof(gf_ctx_opts, rpc_payload)); return 0;}\n')
+    src.write_text(src.read_text().replace('#include "gf.h"', '#include "gf.h"\n#include "gf_heap.h"')
+                   .replace('offsetof(gf_ctx_opts, rpc_payload));', 'offsetof(gf_ctx_opts, rpc_payload));'
+                            ' printf("%zu\\n", sizeof(gf_heap_opts));'))
     exe = tmp_path / "sz"
     subprocess.check_call(["gcc", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)])
     got = [int(v) for v in subprocess.check_output([str(exe)]).split()]
     assert got == [ctypes.sizeof(gf.Step), ctypes.sizeof(gf.Instance), ctypes.sizeof(gf.Launch),
                    ctypes.sizeof(binding.CtxOpts), ctypes.sizeof(binding.RunStats), ctypes.sizeof(gf.Program),
                    gf.Step.chunk.offset, ctypes.sizeof(gf.CallArg), ctypes.sizeof(gf.CallStats),
-                   binding.CtxOpts.rpc_payload.offset]
+                   binding.CtxOpts.rpc_payload.offset, ctypes.sizeof(binding.HeapOpts)]
 
 
 def test_binding_constants_match_header():
@@ -62,11 +65,14 @@ def test_binding_constants_match_header():
     names = ["GF_S_CALL", "GF_STEP_TIMED", "GF_CALLEE_FPRINTF", "GF_CALLEE_SNPRINTF", "GF_CALLEE_SSCANF",
              "GF_CALLEE_FWRITE", "GF_CALLEE_FREAD", "GF_ARG_CONST", "GF_ARG_SCALAR", "GF_ARG_ITER", "GF_ARG_REF",
              "GF_REF_READ", "GF_REF_WRITE", "GF_REF_READWRITE", "GF_CALL_MAX_ARGS", "GF_CALL_MAX_REFS",
-             "GF_CALL_MAX_SITES", "GF_S_PRINTF", "GF_STEP_BLOCKING", "GF_R_OWNER", "GF_R_PHASES"]
+             "GF_CALL_MAX_SITES", "GF_S_PRINTF", "GF_STEP_BLOCKING", "GF_R_OWNER", "GF_R_PHASES",
+             "GF_HEAP_OP_MALLOC", "GF_HEAP_OP_FREE", "GF_HEAP_OP_FIND", "GF_HEAP_BENCH_ROUNDTRIP",
+             "GF_HEAP_BENCH_HOLD", "GF_HEAP_BENCH_RELEASE"]
     with tempfile.TemporaryDirectory() as d:
         src = os.path.join(d, "c.c")
         body = " ".join(f'printf("%ld\\n", (long)({n}));' for n in names)
-        open(src, "w").write(f'#include <stdio.h>\n#include "gf.h"\nint main(void){{{body} return 0;}}\n')
+        open(src, "w").write(f'#include <stdio.h>\n#include "gf.h"\n#include "gf_heap.h"\n'
+                             f'int main(void){{{body} return 0;}}\n')
         exe = os.path.join(d, "c")
         subprocess.check_call(["gcc", "-I", os.path.join(ROOT, "include"), src, "-o", exe])
         got = [int(v) for v in subprocess.check_output([exe]).split()]
