@@ -1,6 +1,7 @@
 """Measure the legacy-loop workloads other than the benchmark's headline.
 
-    python -m paper_2306_11686_amd.measure [--configs sync,2d,rpc,rpc_fprintf,phases,cg,hist,batched] [--reps 3]
+    python -m paper_2306_11686_amd.measure [--configs sync,2d,rpc,rpc_fprintf,phases,heap,cg,hist,batched]
+                                           [--reps 3]
 
 Each configuration prints one JSON line: time per run in the persistent,
 per-region and per-region-graph modes, regions per second, and algorithmic
@@ -237,9 +238,38 @@ def measure_phases(ctx, gf, programs, tuner, torch, reps):
     return out
 
 
+def measure_heap(ctx, gf, programs, tuner, torch, reps):
+    """The allocator benchmark's shape (Section 5.1, "Allocator Performance"):
+    every thread of every team allocates a block at the start of the kernel,
+    uses it (writes and checks 128 bytes) and frees it. The balanced heap runs
+    with 32 thread slots and 16 team slots (the configuration the paper
+    measures) and with 64 x 32 (one thread slot per lane of a 64-wide
+    wavefront), beside the HIP runtime's device malloc."""
+    out = {"config": "heap_roundtrip_128B", "bytes": 128}
+    heaps = {"balanced": gf.Heap(0, 1 << 28, 32, 16, 4), "balanced64x32": gf.Heap(0, 1 << 28, 64, 32, 4),
+             "hip_malloc": gf.Heap(0, 1 << 28, vendor=True)}
+    try:
+        for teams in (1, 32, 64, 128, 256):
+            for threads in (1, 32, 64, 128, 256):
+                row = {}
+                for name, h in heaps.items():
+                    ms = _time(ctx, torch, lambda: h.bench(teams, threads, 128), reps)
+                    row[name + "_us"] = round(ms * 1e3, 2)
+                    c = h.counts(reset=True)
+                    if any(c.values()):
+                        row[name + "_errors"] = c
+                row["speedup"] = round(row["hip_malloc_us"] / row["balanced_us"], 2)
+                row["speedup64x32"] = round(row["hip_malloc_us"] / row["balanced64x32_us"], 2)
+                out[f"teams{teams}_threads{threads}"] = row
+    finally:
+        for h in heaps.values():
+            h.close()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
-    ap.add_argument("--configs", default="sync,2d,rpc,rpc_fprintf,phases,cg,hist,batched")
+    ap.add_argument("--configs", default="sync,2d,rpc,rpc_fprintf,phases,heap,cg,hist,batched")
     ap.add_argument("--reps", type=int, default=3)
     args = ap.parse_args()
     import torch
@@ -247,7 +277,8 @@ def main():
     from paper_2306_11686_amd import programs, tuner
     ctx = gf.Context(0, rpc_capture=True, rpc_thread=True)
     fns = {"sync": measure_sync, "2d": measure_2d, "rpc": measure_rpc, "rpc_fprintf": measure_rpc_fprintf,
-           "phases": measure_phases, "cg": measure_cg, "hist": measure_hist, "batched": measure_batched}
+           "phases": measure_phases, "heap": measure_heap, "cg": measure_cg, "hist": measure_hist,
+           "batched": measure_batched}
     for c in args.configs.split(","):
         log(f"[measure] {c}")
         print(json.dumps(fns[c](ctx, gf, programs, tuner, torch, args.reps)), flush=True)
