@@ -3,7 +3,7 @@
 TEST INFRASTRUCTURE ONLY, like the rest of this package: the tests compare
 the device allocator with it, and nothing here is shared with the library.
 
-Follows the paper's description of its balanced allocator (Section 3,
+Follows the paper's description of its balanced allocator (Section 3.4,
 "Heap Allocators and Allocation Tracking", and the chunk figure). The heap is
 cut into N x M chunks, and a thread allocates from chunk (thread id mod N,
 team id mod M). Within each team slot, the chunk of thread slot 0 is
