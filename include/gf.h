@@ -310,7 +310,16 @@ typedef enum {
     GF_ARG_CONST = 0,   /* value: the word `value` (an integer, a double's bits, or a host pointer) */
     GF_ARG_SCALAR = 1,  /* value: scal[slot] as a double ('d') or truncated to int64 ('i') */
     GF_ARG_ITER = 2,    /* value: iter + 1 (0 in the prologue), type 'i' */
-    GF_ARG_REF = 3      /* reference into array slot `slot`, type 'p' */
+    GF_ARG_REF = 3,     /* reference into array slot `slot`, type 'p' */
+    GF_ARG_HEAPREF = 4  /* reference through a heap pointer, type 'p': the pointer is the
+                           64-bit word at element `start` of array slot `slot`. At the call
+                           the context's heap (gf_ctx_set_heap) looks up the live allocation
+                           that holds it (the paper's run-time lookup of an object the
+                           compiler cannot name); that whole object, at most `size` bytes,
+                           is copied in and back by `mode`, and the callee gets the pointer
+                           at the same offset into the copy. A pointer the heap does not
+                           hold, or an object larger than `size`, is passed unchanged as a
+                           value (Section 3.2) */
 } gf_arg_kind;
 
 typedef enum { GF_REF_READ = 1, GF_REF_WRITE = 2, GF_REF_READWRITE = 3 } gf_ref_mode;
@@ -322,11 +331,13 @@ typedef enum { GF_REF_READ = 1, GF_REF_WRITE = 2, GF_REF_READWRITE = 3 } gf_ref_
 typedef struct {
     int32_t kind;     /* gf_arg_kind */
     int32_t type;     /* 'i' (int64), 'd' (double) or 'p' (pointer) */
-    int32_t slot;     /* GF_ARG_SCALAR: scalar slot; GF_ARG_REF: array slot */
-    int32_t mode;     /* GF_ARG_REF: gf_ref_mode */
+    int32_t slot;     /* GF_ARG_SCALAR: scalar slot; GF_ARG_REF, GF_ARG_HEAPREF: array slot */
+    int32_t mode;     /* GF_ARG_REF, GF_ARG_HEAPREF: gf_ref_mode */
     int64_t value;    /* GF_ARG_CONST: the 64-bit word */
-    int64_t start;    /* GF_ARG_REF: byte offset of the object in the array */
-    int64_t size;     /* GF_ARG_REF: object bytes (>= 1) */
+    int64_t start;    /* GF_ARG_REF: byte offset of the object in the array;
+                         GF_ARG_HEAPREF: index of the pointer word in the array */
+    int64_t size;     /* GF_ARG_REF: object bytes (>= 1); GF_ARG_HEAPREF: the largest
+                         object shipped (>= 16) */
     int64_t offset;   /* GF_ARG_REF: byte offset of the pointer into the object (0..size) */
 } gf_call_arg;
 

@@ -104,6 +104,15 @@ gf_status gf_heap_bench(gf_heap *heap, int32_t teams, int32_t threads, int64_t b
  * counts; reset != 0 clears them. */
 gf_status gf_heap_counts(gf_heap *heap, uint64_t out[4], int32_t reset);
 
+/* Device address of the heap's first byte (NULL for a vendor heap): the
+ * offsets of gf_heap_script are relative to it. */
+void *gf_heap_base(const gf_heap *heap);
+
+/* Let ctx's host calls look up GF_ARG_HEAPREF pointers in `heap` (NULL:
+ * none; every such pointer then travels as a value). The heap must outlive
+ * the runs that use it. Not a vendor heap. */
+gf_status gf_ctx_set_heap(gf_ctx *ctx, gf_heap *heap);
+
 /* Synchronous: the watermark (units above the chunk's start in use or
  * reserved) of each chunk, N*M values into tops (host), n >= N*M. */
 gf_status gf_heap_tops(gf_heap *heap, uint32_t *tops, int32_t n);

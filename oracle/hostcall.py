@@ -23,6 +23,16 @@ Argument descriptors:
 * ``("ref", slot, start, size, offset, mode)``: a pointer ``offset`` bytes
   into the object ``arrays[slot]`` bytes ``[start, start + size)``. ``mode``
   is ``"r"``, ``"w"`` or ``"rw"``.
+* ``("heapref", slot, element, max_bytes, mode)``: a pointer held in element
+  ``element`` of the int64 array ``arrays[slot]``, whose object is not known
+  in advance. The object is found at call time in the record the heap
+  allocator keeps (Section 3.2, with the allocator of Section 3.4). That
+  record is the ``heap=(address, memory, model)`` argument: the heap's
+  device address, a uint8 array mirroring its bytes, and the
+  ``oracle.heap.BalancedHeap`` model of its allocations. The object is
+  shipped like a reference, with the pointer at the same offset into it. A
+  pointer outside every live object, or an object larger than ``max_bytes``,
+  is passed as a value.
 
 Reading of write-only objects: the paper marks an object write-only when its
 value at the call is unspecified, so it is not copied to the host. Here the
@@ -65,7 +75,7 @@ def _word(kind_type, value):
     raise ValueError(f"argument type {kind_type!r}")
 
 
-def call(callee: str, args, arrays: dict, scal=None, it: int = -1):
+def call(callee: str, args, arrays: dict, scal=None, it: int = -1, heap=None):
     """Make one call. ``arrays`` maps slot -> numpy array, and the objects of
     write and read-write references in it are updated in place. ``it`` is the
     0-based body iteration (-1 in the prologue). Returns ``(ret, out)``,
@@ -96,6 +106,25 @@ def call(callee: str, args, arrays: dict, scal=None, it: int = -1):
                 ctypes.memmove(host, view.tobytes(), size)
             objects.append((view, host, mode))
             cargs.append(ctypes.c_void_p(ctypes.addressof(host) + offset))
+        elif kind == "heapref":
+            _, slot, element, max_bytes, mode = a
+            p = int(np.asarray(arrays[slot]).reshape(-1).view(np.uint64)[element])
+            found = None
+            if heap is not None:
+                addr, mem, model = heap
+                off = p - addr
+                if 0 <= off < mem.size:
+                    found = model.find(off)
+            if found is None or found[1] > max_bytes:
+                cargs.append(ctypes.c_void_p(p))
+                continue
+            start, size = found
+            view = mem[start:start + size]
+            host = ctypes.create_string_buffer(size)
+            if "r" in mode:
+                ctypes.memmove(host, view.tobytes(), size)
+            objects.append((view, host, mode))
+            cargs.append(ctypes.c_void_p(ctypes.addressof(host) + (p - addr - start)))
         else:
             raise ValueError(f"argument kind {kind!r}")
 

@@ -22,7 +22,7 @@ GF_S_SET, GF_S_COPY, GF_S_DIV, GF_S_SQRT, GF_S_SWAP, GF_S_RECORD, GF_S_PRINTF, G
 GF_STEP_BLOCKING, GF_STEP_TIMED = 1, 2
 
 GF_CALLEE_FPRINTF, GF_CALLEE_SNPRINTF, GF_CALLEE_SSCANF, GF_CALLEE_FWRITE, GF_CALLEE_FREAD = 1, 2, 3, 4, 5
-GF_ARG_CONST, GF_ARG_SCALAR, GF_ARG_ITER, GF_ARG_REF = 0, 1, 2, 3
+GF_ARG_CONST, GF_ARG_SCALAR, GF_ARG_ITER, GF_ARG_REF, GF_ARG_HEAPREF = 0, 1, 2, 3, 4
 GF_REF_READ, GF_REF_WRITE, GF_REF_READWRITE = 1, 2, 3
 GF_CALL_MAX_ARGS, GF_CALL_MAX_REFS, GF_CALL_MAX_SITES = 8, 4, 64
 
@@ -153,6 +153,15 @@ class CallArg(ctypes.Structure):
         a.start, a.size, a.offset = start, size, offset
         return a
 
+    @classmethod
+    def heapref(cls, slot, element, max_bytes, mode=GF_REF_READWRITE):
+        """A heap pointer held in element `element` of int64 array slot
+        `slot`: its object is found in the context's heap at call time."""
+        a = cls()
+        a.kind, a.type, a.slot, a.mode = GF_ARG_HEAPREF, ord("p"), slot, mode
+        a.start, a.size, a.offset = element, max_bytes, 0
+        return a
+
 
 class HeapOpts(ctypes.Structure):
     _fields_ = [("bytes", ctypes.c_int64), ("thread_slots", ctypes.c_int32), ("team_slots", ctypes.c_int32),
@@ -219,6 +228,8 @@ _SIGS = {
                                      ctypes.c_int32, ctypes.c_void_p, ctypes.c_void_p]),
     "gf_heap_counts": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_uint64), ctypes.c_int32]),
     "gf_heap_tops": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_uint32), ctypes.c_int32]),
+    "gf_heap_base": (ctypes.c_void_p, [ctypes.c_void_p]),
+    "gf_ctx_set_heap": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p]),
     "gf_sync": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.POINTER(RunStats)]),
     "gf_persistent_capacity": (ctypes.c_int32, [ctypes.c_void_p, ctypes.POINTER(Program), ctypes.c_int32]),
     "gf_copy": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64, ctypes.c_int32,
@@ -364,6 +375,10 @@ class Context:
     def register_call(self, callee: int, args) -> int:
         arr = (CallArg * max(1, len(args)))(*args)
         return self._check(self.lib.gf_rpc_register_call(self.h, callee, arr, len(args)))
+
+    def set_heap(self, heap):
+        """Let host calls look up GF_ARG_HEAPREF pointers in `heap` (None: no heap)."""
+        self._check(self.lib.gf_ctx_set_heap(self.h, heap.h if heap is not None else None))
 
     def call_stats(self, call_id: int, reset: bool = False) -> dict:
         out = CallStats()
@@ -517,6 +532,10 @@ class Heap:
         out = (ctypes.c_uint64 * 4)()
         self._check(self.lib.gf_heap_counts(self.h, out, 1 if reset else 0), "gf_heap_counts")
         return {"null": out[0], "corrupt": out[1], "timeouts": out[2], "bad_frees": out[3]}
+
+    def base(self) -> int:
+        """Device address of the heap's first byte."""
+        return self.lib.gf_heap_base(self.h) or 0
 
     def tops(self):
         n = self.opts.thread_slots * self.opts.team_slots

@@ -24,6 +24,7 @@
 #include <vector>
 
 #include "gf_internal.h"
+#include "gf_heap.h"
 
 using namespace gf;
 
@@ -256,6 +257,7 @@ struct gf_ctx {
     DCall *d_calls = nullptr;
     unsigned long long *d_call_stats = nullptr;
     std::vector<CallSite> calls;  // capacity GF_CALL_MAX_SITES, never reallocated
+    heapdev::DHeap heap{};        // heap for GF_ARG_HEAPREF lookups (base NULL: none)
     bool capture = false;
     std::string captured;
     std::atomic<int64_t> serviced{0};
@@ -323,6 +325,7 @@ RpcRing ring_of(const gf_ctx *ctx)
     r.payloads = ctx->d_payload;
     r.calls = ctx->d_calls;
     r.call_stats = ctx->d_call_stats;
+    r.heap = ctx->heap;
     return r;
 }
 
@@ -369,6 +372,12 @@ int32_t poll_locked(gf_ctx *ctx, int32_t max_requests, int32_t timeout_us)
                             if (a.mode == GF_REF_WRITE)
                                 std::memset(pl + a.pos, 0, (size_t)a.size);
                             w[k] = (uint64_t)(uintptr_t)(pl + a.pos + a.offset);
+                        } else if (a.kind == GF_ARG_HEAPREF && !(slot->flags & (kHeapValueFlag0 << k))) {
+                            // the heap found the object: {bytes << 32 | offset of the pointer}
+                            const uint64_t bytes = slot->args[k] >> 32, off = slot->args[k] & 0xFFFFFFFFu;
+                            if (a.mode == GF_REF_WRITE)
+                                std::memset(pl + a.pos, 0, (size_t)bytes);
+                            w[k] = (uint64_t)(uintptr_t)(pl + a.pos + off);
                         } else {
                             w[k] = slot->args[k];
                         }
@@ -626,6 +635,18 @@ int32_t gf_rpc_register_format(gf_ctx *ctx, const char *fmt, const char *sig)
     return (int32_t)ctx->formats.size() - 1;
 }
 
+gf_status gf_ctx_set_heap(gf_ctx *ctx, gf_heap *heap)
+{
+    if (!ctx)
+        return GF_EINVAL;
+    heapdev::DHeap d{};
+    if (heap && !heapdev::heap_view(heap, &d))
+        return fail(ctx, GF_EINVAL, "a vendor heap keeps no record of its objects");
+    std::lock_guard<std::mutex> g(ctx->rpc_mu);
+    ctx->heap = d;
+    return GF_OK;
+}
+
 int32_t gf_rpc_register_call(gf_ctx *ctx, int32_t callee, const gf_call_arg *args, int32_t nargs)
 {
     if (!ctx)
@@ -664,6 +685,28 @@ int32_t gf_rpc_register_call(gf_ctx *ctx, int32_t callee, const gf_call_arg *arg
         case GF_ARG_ITER:
             if (a.type != 'i')
                 return fail(ctx, GF_EINVAL, "argument %d: the iteration number passes as 'i'", k);
+            break;
+        case GF_ARG_HEAPREF:
+            if (a.type != 'p')
+                return fail(ctx, GF_EINVAL, "argument %d: a reference passes as 'p'", k);
+            if (a.slot < 0 || a.slot >= GF_MAX_ARRAYS)
+                return fail(ctx, GF_EINVAL, "argument %d: array slot out of range", k);
+            if (a.mode < GF_REF_READ || a.mode > GF_REF_READWRITE)
+                return fail(ctx, GF_EINVAL, "argument %d: access mode must be read, write or read-write", k);
+            if (a.size < 16 || a.start < 0)
+                return fail(ctx, GF_EINVAL, "argument %d: heap reference needs size >= 16 and start >= 0", k);
+            if (d.nrefs == GF_CALL_MAX_REFS)
+                return fail(ctx, GF_EINVAL, "more than %d reference arguments", GF_CALL_MAX_REFS);
+            o.start = a.start;
+            o.size = (a.size + 15) / 16 * 16;
+            o.offset = 0;
+            o.pos = (int32_t)pos;
+            o.ref = d.nrefs++;
+            pos += o.size;
+            if (pos > (int64_t)ctx->payload_bytes)
+                return fail(ctx, GF_EINVAL, "referenced objects need %lld payload bytes; the slot payload is %u",
+                            (long long)pos, ctx->payload_bytes);
+            copy_out |= (a.mode & GF_REF_WRITE) != 0;
             break;
         case GF_ARG_REF:
             if (a.type != 'p')
@@ -1085,7 +1128,7 @@ gf_status check_instance(gf_ctx *ctx, const DProg &p, const gf_instance &in, con
             std::lock_guard<std::mutex> g(ctx->rpc_mu);
             const DCall &c = ctx->calls[s.fmt_id].dev;
             for (int k = 0; k < c.nargs; ++k)
-                if (c.a[k].kind == GF_ARG_REF && !in.arr[c.a[k].slot])
+                if ((c.a[k].kind == GF_ARG_REF || c.a[k].kind == GF_ARG_HEAPREF) && !in.arr[c.a[k].slot])
                     return fail(ctx, GF_EINVAL, "instance %d step %d: call references empty array slot %d", idx, i,
                                 c.a[k].slot);
             continue;
@@ -1300,7 +1343,7 @@ gf_status enqueue_per_region(gf_ctx *ctx, const DProg &p, const gf_instance &in,
                 std::lock_guard<std::mutex> lk(ctx->rpc_mu);
                 const DCall &c = ctx->calls[s.fmt_id].dev;
                 for (int k = 0; k < c.nargs; ++k)
-                    if (c.a[k].kind == GF_ARG_REF)
+                    if ((c.a[k].kind == GF_ARG_REF || c.a[k].kind == GF_ARG_HEAPREF))
                         g.obj[c.a[k].ref] = arr[c.a[k].slot];
             }
         }

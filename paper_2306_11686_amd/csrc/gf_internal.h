@@ -6,6 +6,7 @@
 #include <stdint.h>
 
 #include "gf.h"
+#include "gf_heap_dev.h"
 
 namespace gf {
 
@@ -122,6 +123,10 @@ struct DCall {
     DCallArg a[GF_CALL_MAX_ARGS];
 };
 
+// Slot flag bit (kHeapValueFlag0 << k): heap reference argument k was not
+// found in the heap and travels as a plain value.
+constexpr uint32_t kHeapValueFlag0 = 1u << 8;
+
 // Device-side timing accumulators of one call site (GF_STEP_TIMED), in
 // 100 MHz clock ticks: calls, args, copy-in, wait, copy-out.
 constexpr int kCallStatWords = 5;
@@ -144,6 +149,7 @@ struct RpcRing {
     char *payloads;      // host pinned: slot i's payload at i * payload
     const DCall *calls;  // device: registered call sites
     unsigned long long *call_stats;  // device: kCallStatWords per call site
+    heapdev::DHeap heap;  // heap for GF_ARG_HEAPREF lookups (base NULL: none)
 };
 
 // Device scratch owned by a context. Each counter sits on its own 128-byte

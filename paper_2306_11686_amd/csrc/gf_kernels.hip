@@ -1013,14 +1013,38 @@ __device__ int64_t serial_call(const RpcRing &rpc, int32_t call_id, uint32_t fla
     const uint64_t c1 = timed ? now_ticks() : 0;
     // objects that lane 0 may have written just before (history records)
     __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
+    // heap references not found in the heap travel as values
+    uint32_t hflags = 0;
     for (int k = 0; k < cs.nargs; ++k) {
         const DCallArg &a = cs.a[k];
-        if (a.kind != GF_ARG_REF)
-            continue;
-        if (a.mode & GF_REF_READ)
-            wave_copy(pl + a.pos, (const char *)base(a) + a.start, a.size, lane);
-        copy_out |= (a.mode & GF_REF_WRITE) != 0;
+        if (a.kind == GF_ARG_REF) {
+            if (a.mode & GF_REF_READ)
+                wave_copy(pl + a.pos, (const char *)base(a) + a.start, a.size, lane);
+            copy_out |= (a.mode & GF_REF_WRITE) != 0;
+        } else if (a.kind == GF_ARG_HEAPREF) {
+            // lane 0 looks the pointer up in the heap's record of live objects
+            uint64_t st = 0, by = 0;
+            if (lane == 0) {
+                const uint64_t p = ((const uint64_t *)base(a))[a.start];
+                if (!rpc.heap.base || !heapdev::heap_find(rpc.heap, (const void *)p, &st, &by) ||
+                    by > (uint64_t)a.size)
+                    by = 0;
+                slot->args[k] = by ? (by << 32) | (p - ((uint64_t)(uintptr_t)rpc.heap.base + st)) : p;
+            }
+            st = first_lane_u64(st);
+            by = first_lane_u64(by);
+            if (by == 0)
+                hflags |= kHeapValueFlag0 << k;
+            else if (a.mode & GF_REF_READ)
+                wave_copy(pl + a.pos, rpc.heap.base + st, (int64_t)by, lane);
+            // the slot is freed by the device whenever the call site copies back
+            copy_out |= (a.mode & GF_REF_WRITE) != 0;
+        }
     }
+    // rewritten only when a heap pointer travels as a value (a late store to
+    // host memory would add a PCIe write to the publication's wait)
+    if (hflags && lane == 0)
+        slot->flags = flags | hflags;
     // every lane's payload stores before lane 0's publication
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "");
     if (lane == 0)
@@ -1041,8 +1065,26 @@ __device__ int64_t serial_call(const RpcRing &rpc, int32_t call_id, uint32_t fla
             if (ok)
                 for (int k = 0; k < cs.nargs; ++k) {
                     const DCallArg &a = cs.a[k];
-                    if (a.kind == GF_ARG_REF && (a.mode & GF_REF_WRITE))
+                    if (!(a.mode & GF_REF_WRITE))
+                        continue;
+                    if (a.kind == GF_ARG_REF) {
                         wave_copy((char *)base(a) + a.start, pl + a.pos, a.size, lane);
+                    } else if (a.kind == GF_ARG_HEAPREF) {
+                        // the caller's object is the one found at the start of the call
+                        // (it cannot be freed meanwhile); look it up again rather than
+                        // keep it in registers across the wait
+                        uint64_t st = 0, by = 0;
+                        if (lane == 0) {
+                            const uint64_t p = ((const uint64_t *)base(a))[a.start];
+                            if (!rpc.heap.base || !heapdev::heap_find(rpc.heap, (const void *)p, &st, &by) ||
+                                by > (uint64_t)a.size)
+                                by = 0;
+                        }
+                        st = first_lane_u64(st);
+                        by = first_lane_u64(by);
+                        if (by)
+                            wave_copy(rpc.heap.base + st, pl + a.pos, (int64_t)by, lane);
+                    }
                 }
             // the payload reads are complete before the slot is handed back
             __builtin_amdgcn_fence(__ATOMIC_RELEASE, "");

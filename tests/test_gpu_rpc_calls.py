@@ -345,3 +345,53 @@ def test_call_site_and_step_errors(cctx):
                                                    flags=gf.GF_STEP_BLOCKING)], 1),
                  gf.Instance.make({0: d0}, sc))
     cctx.sync()
+
+
+@pytest.mark.parametrize("mode", MODES)
+def test_heap_references_are_found_at_call_time(mode):
+    """Pointers held in an array and not known when the call site is
+    registered: the context's heap finds the live object behind each one and
+    the whole object travels (read-write, write-only, read-only). Pointers
+    it does not hold travel as values."""
+    import torch
+    import paper_2306_11686_amd as gf
+    from oracle.heap import BalancedHeap
+    print(f"call heap references mode={mode}", flush=True)
+    with gf.Context(0, rpc_capture=True, rpc_thread=True) as ctx, gf.Heap(0, 65536, 1, 1, 1) as heap:
+        ctx.set_heap(heap)
+        model = BalancedHeap(65536, 1, 1, 1)
+        ops = torch.tensor([1, 40, 0, 1, 20, 0], dtype=torch.int64, device="cuda")
+        res = torch.zeros(4, dtype=torch.int64, device="cuda")
+        heap.script(ops, 2, res)
+        a, b = (int(v) for v in res.cpu().numpy()[::2])
+        assert (a, b) == (model.malloc(0, 0, 40), model.malloc(0, 0, 20))
+        base = heap.base()
+        ptrs = dev(np.array([base + a + 10, base + b, base + 4000, 0x1234], dtype=np.int64))
+        fmt1, fmt2, fmt3 = _cstr(b"<%lld>", 8), _cstr(b"%p|", 8), _cstr(b"\n", 8)
+        d1, d2, d3 = dev(fmt1), dev(fmt2), dev(fmt3)
+        A = gf.CallArg
+        out = gf.host_stream("stdout")
+        calls = [
+            (gf.GF_CALLEE_SNPRINTF, [A.heapref(0, 0, 64, gf.GF_REF_READWRITE), A.const(8),
+                                     A.ref(1, 8, mode=gf.GF_REF_READ), A.iteration()]),
+            (gf.GF_CALLEE_SNPRINTF, [A.heapref(0, 1, 64, gf.GF_REF_WRITE), A.const(32),
+                                     A.ref(1, 8, mode=gf.GF_REF_READ), A.const(-5)]),
+            (gf.GF_CALLEE_FWRITE, [A.heapref(0, 0, 64, gf.GF_REF_READ), A.const(1), A.const(3), A.const(out, "p")]),
+            (gf.GF_CALLEE_FWRITE, [A.heapref(0, 1, 64, gf.GF_REF_READ), A.const(1), A.const(4), A.const(out, "p")]),
+            (gf.GF_CALLEE_FPRINTF, [A.const(out, "p"), A.ref(2, 8, mode=gf.GF_REF_READ),
+                                    A.heapref(0, 2, 64, gf.GF_REF_READ)]),
+            (gf.GF_CALLEE_FPRINTF, [A.const(out, "p"), A.ref(2, 8, mode=gf.GF_REF_READ),
+                                    A.heapref(0, 3, 64, gf.GF_REF_READ)]),
+            (gf.GF_CALLEE_FWRITE, [A.ref(3, 1, mode=gf.GF_REF_READ), A.const(1), A.const(1), A.const(out, "p")]),
+        ]
+        ids = [ctx.register_call(c, args) for c, args in calls]
+        body = [gf.Step.make(gf.GF_S_CALL, fmt_id=i, every=1, flags=gf.GF_STEP_BLOCKING) for i in ids]
+        sc = scalars()
+        ctx.take_output()
+        ctx.run(gf.Program.make([], body, 3), gf.Instance.make({0: ptrs, 1: d1, 2: d2, 3: d3}, sc),
+                mode=_mode(gf, mode))
+        ctx.sync()
+        text = ctx.take_output()
+        line = "{}<-5>%#x|%#x|\n" % (base + 4000, 0x1234)
+        assert text == "".join(line.format(f"<{k}>") for k in range(1, 4))
+        ctx.set_heap(None)

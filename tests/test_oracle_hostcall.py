@@ -116,3 +116,34 @@ def test_references_outside_their_array_are_rejected():
     with pytest.raises(ValueError):
         hc.call("fwrite", [("ref", 0, 0, 4, 5, "r"), ("const", "i", 1), ("const", "i", 1),
                            ("const", "p", hc.STDOUT)], {0: np.zeros(10, dtype=np.uint8)})
+
+
+def test_heap_reference_ships_the_whole_object_found_by_the_allocator():
+    """A pointer into the middle of a heap object: the whole object goes to
+    the host, the callee gets the same offset into the copy, and read-write
+    bytes it does not touch are kept."""
+    from oracle.heap import BalancedHeap
+    model = BalancedHeap(4096, 1, 1, 1)
+    a = model.malloc(0, 0, 40)                     # 48-byte object at offset 16
+    b = model.malloc(0, 0, 20)                     # 32-byte object at offset 80
+    mem = np.full(4096, 0xAA, dtype=np.uint8)
+    addr = 0x7000_0000
+    ptrs = np.array([addr + a + 10, addr + b, addr + 4000, 0x1234], dtype=np.int64)
+    fmt = _cstr(b"<%lld>", 8)
+    heap = (addr, mem, model)
+    ret, _ = hc.call("snprintf", [("heapref", 0, 0, 64, "rw"), ("const", "i", 8), ("ref", 1, 0, 8, 0, "r"),
+                                  ("iter",)], {0: ptrs, 1: fmt}, it=6, heap=heap)
+    assert ret == 3
+    want = np.full(4096, 0xAA, dtype=np.uint8)
+    want[a + 10:a + 14] = np.frombuffer(b"<7>\0", dtype=np.uint8)
+    assert np.array_equal(mem, want)
+    # write-only: the whole 32-byte object comes back, zero-filled past the text
+    hc.call("snprintf", [("heapref", 0, 1, 64, "w"), ("const", "i", 32), ("ref", 1, 0, 8, 0, "r"),
+                         ("const", "i", -5)], {0: ptrs, 1: fmt}, heap=heap)
+    assert bytes(mem[b:b + 32]) == b"<-5>" + bytes(28)
+    # an object larger than the limit, a pointer to no live object and a
+    # pointer outside the heap all travel as plain values
+    for k, limit in ((0, 32), (2, 64), (3, 64)):
+        _, out = hc.call("fprintf", [("const", "p", hc.STDOUT), ("ref", 1, 0, 8, 0, "r"),
+                                     ("heapref", 0, k, limit, "r")], {0: ptrs, 1: _cstr(b"%p", 8)}, heap=heap)
+        assert out == b"%#x" % int(ptrs[k])
