@@ -22,7 +22,8 @@ ARCH = "gfx950"
 
 # The sources the region kernels (persistent and per-region) are compiled
 # from: the device code, its headers and the public header it includes.
-KERNEL_SOURCES = ("csrc/gf_kernels.hip", "csrc/gf_device.h", "csrc/gf_internal.h", "../include/gf.h")
+KERNEL_SOURCES = ("csrc/gf_kernels.hip", "csrc/gf_device.h", "csrc/gf_internal.h", "csrc/gf_heap_dev.h",
+                  "../include/gf.h")
 
 
 def kernel_source_hash() -> str:

@@ -5,12 +5,10 @@
 // object behind a heap pointer passed as a reference argument (Section 3.2).
 //
 // Chunk metadata (the chunk headers and the entry headers inside the heap)
-// is read and written only with agent-scope atomics, which stay coherent
-// across the XCDs without writing back or invalidating whole L2 caches. A
-// chunk's lock is taken with a compare-and-swap. The holder's metadata
-// stores are complete (s_waitcnt) before the lock word is cleared, and the
-// next holder issues its loads only after its own compare-and-swap has
-// returned.
+// is read and written with agent-scope atomics under the chunk's lock. The
+// lock is taken by a compare-and-swap with agent-scope acquire and released
+// by a store with agent-scope release, so each holder sees every earlier
+// holder's metadata updates on any XCD.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -86,27 +84,24 @@ __device__ inline bool with_chunk(const DHeap &h, uint32_t c, F f)
     uint32_t *lock = h.locks + (uint64_t)c * kLockStride;
     const uint64_t t0 = __builtin_amdgcn_s_memrealtime();
     bool done = false, ok = false;
-    uint32_t backoff = 1;
     for (;;) {
         if (!done) {
             // read before trying: a held lock costs the holder nothing
             uint32_t expect = 0;
+            // agent-scope acquire and release: the entry headers share cache
+            // lines with user data, so a line cached by plain accesses is
+            // invalidated before the holder reads headers, and the holder's
+            // updates are written back before the next holder can take the lock
             if (ald(lock) == 0 &&
-                __hip_atomic_compare_exchange_strong(lock, &expect, 1u, __ATOMIC_RELAXED, __ATOMIC_RELAXED,
+                __hip_atomic_compare_exchange_strong(lock, &expect, 1u, __ATOMIC_ACQUIRE, __ATOMIC_RELAXED,
                                                      __HIP_MEMORY_SCOPE_AGENT)) {
-                __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
                 f(ch);
-                // the metadata stores are complete before the lock is released
-                __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
-                ast(lock, 0u);
+                __hip_atomic_store(lock, 0u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
                 done = ok = true;
             } else if ((int64_t)(__builtin_amdgcn_s_memrealtime() - t0) > h.spin_ticks) {
                 done = true;
             } else {
-                // exponential back-off, up to 16 x 8 x 64 clocks
-                for (uint32_t k = 0; k < backoff; ++k)
-                    __builtin_amdgcn_s_sleep(8);
-                backoff = backoff < 16 ? 2 * backoff : 16;
+                __builtin_amdgcn_s_sleep(1);
             }
         }
         if (__builtin_amdgcn_ballot_w64(!done) == 0)

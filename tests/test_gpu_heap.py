@@ -92,16 +92,19 @@ def test_concurrent_blocks_never_overlap(teams, threads, nbytes, N, M):
         assert h.tops() == [0] * (N * M)
 
 
-@pytest.mark.parametrize("teams,threads", [(1, 1), (32, 64), (256, 256), (128, 32)])
-def test_roundtrip_benchmark_shape(teams, threads):
-    """The allocation benchmark's shape: allocate, use, free in one kernel."""
+@pytest.mark.parametrize("teams,threads,N,M", [(1, 1, 32, 16), (32, 64, 32, 16), (256, 256, 32, 16),
+                                               (128, 32, 32, 16), (256, 256, 64, 32), (256, 1, 64, 32)])
+def test_roundtrip_benchmark_shape(teams, threads, N, M):
+    """The allocation benchmark's shape: allocate, use, free in one kernel.
+    After every round each chunk's watermark is back at its start: a free
+    that read a stale in-use mark below the top would leave it raised."""
     import paper_2306_11686_amd as gf
-    print(f"heap roundtrip teams={teams} threads={threads}", flush=True)
-    with gf.Heap(0, 1 << 26, 32, 16, 4) as h:
-        for _ in range(3):
+    print(f"heap roundtrip teams={teams} threads={threads} N={N} M={M}", flush=True)
+    with gf.Heap(0, 1 << 26, N, M, 4) as h:
+        for _ in range(10):
             h.bench(teams, threads, 128, gf.GF_HEAP_BENCH_ROUNDTRIP)
+            assert h.tops() == [0] * (N * M)
         assert h.counts() == {"null": 0, "corrupt": 0, "timeouts": 0, "bad_frees": 0}
-        assert h.tops() == [0] * 512
 
 
 def test_one_chunk_shared_by_every_thread():
