@@ -85,12 +85,13 @@ def time_mode(ctx, gf, torch, prog, inst, mode, launch, steps, warmup):
     return (t1 - t0) * 1e3 / steps, sum(ev_ms) / len(ev_ms), stats
 
 
-def cpu_baseline(u0, n, budget_s=15.0, max_sweeps=200):
+def cpu_baseline(u0, n, budget_s=15.0, max_sweeps=200, omp_budget_s=5.0):
     """The serial oracle on this host's cores (one thread) for a bounded
-    number of sweeps of the same 512^3 workload."""
-    import numpy as np
-
+    number of sweeps of the same 512^3 workload; beside it, for context, the
+    same loop built with OpenMP on all of the host's threads (the CPU build
+    the paper compares each GPU region with)."""
     import oracle
+    from oracle import omp
 
     u = u0.copy()
     w = u0.copy()
@@ -101,9 +102,7 @@ def cpu_baseline(u0, n, budget_s=15.0, max_sweeps=200):
     t0 = time.perf_counter()
     oracle.jacobi3d_inplace(u, w, k)
     dt = time.perf_counter() - t0
-    del u, w
-    _ = np
-    return {
+    cpu = {
         "value": round(k * alg_bytes_per_sweep(n) / dt / 1e9, 3),
         "unit": "GB/s",
         "cores": 1,
@@ -111,6 +110,24 @@ def cpu_baseline(u0, n, budget_s=15.0, max_sweeps=200):
         "sample": f"{k} sweeps of the {n}^3 grid (after 1 timed warm-up sweep), serial C oracle, 1 thread",
         "seconds": round(dt, 3),
     }
+    threads = omp.max_threads()
+    t0 = time.perf_counter()
+    omp.jacobi3d(u, w, 1)
+    t1 = time.perf_counter() - t0
+    k = int(max(1, min(max_sweeps, omp_budget_s / max(t1, 1e-3))))
+    t0 = time.perf_counter()
+    omp.jacobi3d(u, w, k)
+    dt = time.perf_counter() - t0
+    del u, w
+    cpu_omp = {
+        "value": round(k * alg_bytes_per_sweep(n) / dt / 1e9, 3),
+        "unit": "GB/s",
+        "threads": threads,
+        "kind": "legacy loop built with OpenMP",
+        "sample": f"{k} sweeps of the {n}^3 grid (after 1 timed warm-up sweep), {threads} OpenMP threads",
+        "seconds": round(dt, 3),
+    }
+    return cpu, cpu_omp
 
 
 def main():
@@ -202,11 +219,12 @@ def main():
             log(f"[bench] {name} {pms:.2f} ms/run")
         per_region = out
 
-    cpu = None
+    cpu = cpu_omp = None
     if not args.no_cpu_baseline:
-        log("[bench] cpu baseline (serial oracle)")
-        cpu = cpu_baseline(u0, n)
-        log(f"[bench] cpu {cpu['value']} GB/s over {cpu['sample']}")
+        log("[bench] cpu baseline (serial oracle, then the OpenMP build)")
+        cpu, cpu_omp = cpu_baseline(u0, n)
+        log(f"[bench] cpu {cpu['value']} GB/s over {cpu['sample']}; OpenMP {cpu_omp['value']} GB/s")
+        cpu_omp["gpu_speedup"] = round(gbps / cpu_omp["value"], 2)
 
     traffic = load_traffic(workload)
     line = {
@@ -236,6 +254,7 @@ def main():
                      "kernel": "k_persistent (one launch = %d sweeps)" % sweeps,
                      "kernel_ms": round(kern_ms, 3)},
         "cpu_baseline": cpu,
+        "cpu_openmp": cpu_omp,
     }
     ctx.close()
     print(json.dumps(line), flush=True)

@@ -440,3 +440,15 @@ def test_one_phase_adds_the_rotated_array(oracle_lib):
     a, b = oracle_lib.phases(a0, 1, 37)
     assert np.array_equal(a, a0)                      # the source is only read
     assert np.array_equal(b, a0 + np.roll(a0, -37))  # b[i] = a[i] + a[(i + 37) % n]
+
+
+def test_openmp_build_of_the_legacy_loop_matches_the_oracle(oracle_lib):
+    """The CPU OpenMP build (a timing baseline) computes the same grid and
+    residual as the serial oracle, bit for bit, on several threads."""
+    import gf_inputs as gi
+    from oracle import omp
+    u0 = gi.grid3d(37, seed=5)
+    g, r = oracle_lib.jacobi3d(u0, 3)
+    u, w = u0.copy(), u0.copy()
+    m = omp.jacobi3d(u, w, 3, threads=3)
+    assert np.array_equal(w, g) and m == r[-1]
