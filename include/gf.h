@@ -346,8 +346,9 @@ typedef struct {
  * GF_CALL_MAX_REFS references, and that the objects (each rounded up to 16
  * bytes) fit the slot payload. Returns the call-site id >= 0 or a negative
  * gf_status (GF_EINVAL; GF_EUNSUPPORTED for a signature without a landing
- * pad). The caller guarantees that each referenced object lies inside its
- * array, and that host pointer values are valid on the host. */
+ * pad). The caller guarantees that each referenced object, and the pointer
+ * word of each heap reference, lies inside its array, and that host pointer
+ * values are valid on the host. */
 int32_t gf_rpc_register_call(gf_ctx *ctx, int32_t callee, const gf_call_arg *args, int32_t nargs);
 
 /* Average per-call stage times in microseconds of the GF_STEP_TIMED calls at
