@@ -26,15 +26,24 @@ KERNEL_SOURCES = ("csrc/gf_kernels.hip", "csrc/gf_device.h", "csrc/gf_internal.h
                   "../include/gf.h")
 
 
+def _code_only(text: str) -> str:
+    """C/C++ source without comments and with whitespace collapsed, so that
+    edits to comments do not count as changes to the code."""
+    import re
+    text = re.sub(r"/\*.*?\*/", " ", text, flags=re.S)
+    text = re.sub(r"//[^\n]*", " ", text)
+    return " ".join(text.split())
+
+
 def kernel_source_hash() -> str:
-    """Short hash of the sources of the region kernels: measurements tied
-    to those kernels (HBM traffic counters) record it and lapse when it
-    changes."""
+    """Short hash of the code (comments aside) of the region kernels:
+    measurements tied to those kernels (HBM traffic counters) record it and
+    lapse when it changes."""
     import hashlib
     h = hashlib.sha256()
     for rel in KERNEL_SOURCES:
-        with open(os.path.normpath(os.path.join(HERE, rel)), "rb") as f:
-            h.update(f.read())
+        with open(os.path.normpath(os.path.join(HERE, rel)), encoding="utf-8") as f:
+            h.update(_code_only(f.read()).encode())
     return h.hexdigest()[:16]
 
 
