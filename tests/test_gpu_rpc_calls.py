@@ -395,3 +395,41 @@ def test_heap_references_are_found_at_call_time(mode):
         line = "{}<-5>%#x|%#x|\n" % (base + 4000, 0x1234)
         assert text == "".join(line.format(f"<{k}>") for k in range(1, 4))
         ctx.set_heap(None)
+
+
+@pytest.mark.parametrize("mode", MODES)
+def test_call_after_the_last_region_sees_every_workgroups_writes(oracle_lib, mode, tmp_path):
+    """A program whose last region writes an array that a host call then
+    ships: the barrier after that region is kept, so the first workgroup
+    copies what every workgroup wrote (the phase region's result, 64
+    elements per workgroup over 128 workgroups), and fwrite puts exactly
+    those bytes in a file."""
+    import torch
+    import paper_2306_11686_amd as gf
+    import gf_inputs as gi
+    print(f"call after last region mode={mode}", flush=True)
+    n, P, s = 8192, 3, 4097
+    a0 = gi.um11(12, 21, np.arange(n, dtype=np.uint64))
+    a, b = dev(a0), torch.zeros(n, dtype=torch.float64, device="cuda")
+    libc = ctypes.CDLL(None)
+    libc.fopen.restype = ctypes.c_void_p
+    path = tmp_path / "phase_result.bin"
+    f = libc.fopen(str(path).encode(), b"wb")
+    assert f
+    try:
+        with gf.Context(0, rpc_thread=True, rpc_payload=8 * n) as ctx:
+            args = [gf.CallArg.ref(1, 8 * n, mode=gf.GF_REF_READ), gf.CallArg.const(8), gf.CallArg.const(n),
+                    gf.CallArg.const(f, "p")]
+            cid = ctx.register_call(gf.GF_CALLEE_FWRITE, args)
+            pro = [gf.Step.make(gf.GF_R_PHASES, arr=(0, 1, -1), np=0, chunk=P, mask=s),
+                   gf.Step.make(gf.GF_S_CALL, fmt_id=cid, every=1, flags=gf.GF_STEP_BLOCKING, sc=(0,))]
+            sc = scalars()
+            ctx.run(gf.Program.make(pro, [], 0), gf.Instance.make({0: a, 1: b}, sc, ip=(n,)),
+                    mode=_mode(gf, mode), launch=gf.Launch.make(wg_size=64, num_wg=128))
+            ctx.sync()
+    finally:
+        libc.fclose(ctypes.c_void_p(f))
+    _, rb = oracle_lib.phases(a0, P, s)    # three phases: the result is in the second buffer
+    assert np.array_equal(host(b), rb)
+    assert host(sc)[0] == n                 # fwrite's count of items written
+    assert np.array_equal(np.frombuffer(path.read_bytes(), dtype=np.float64), rb)
