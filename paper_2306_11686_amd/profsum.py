@@ -1,12 +1,15 @@
 """Summaries of rocprofv3 output for the committed profiles.
 
     python -m paper_2306_11686_amd.profsum stats KERNEL_STATS_CSV [--top 8]
+    python -m paper_2306_11686_amd.profsum positions KERNEL_TRACE_CSV --kernel NAME --period P --count N \\
+        [--skip S] [--labels a,b,...]
     python -m paper_2306_11686_amd.profsum traffic --fetch COUNTER_CSV --write COUNTER_CSV \\
         --workload jacobi3d_512 --kernel k_persistent --alg-bytes N [--copy-bytes 1073741824] \\
         [--update profiles/traffic.json]
 
 `stats` prints the kernel-trace statistics (``--kernel-trace --stats``) as a
-markdown table. `traffic` turns two counter passes (FETCH_SIZE, WRITE_SIZE,
+markdown table. `positions` tabulates one kernel's dispatch durations by
+their position in a repeating sequence (the regions of a program's loop). `traffic` turns two counter passes (FETCH_SIZE, WRITE_SIZE,
 in KiB per dispatch) into HBM bytes per launch of the named kernel, each
 scaled by what the same counter read for the copy kernel (`gf::k_copy_tiles`,
 copy_bytes read and copy_bytes written per dispatch) in the same run, and
@@ -80,12 +83,45 @@ def traffic(args) -> dict:
     return entry
 
 
+def positions_table(path: str, kernel: str, skip: int, period: int, count: int, labels) -> str:
+    """Durations of the dispatches of one kernel, taken in start order, by
+    their position in a repeating sequence (a program's regions): the
+    first `skip` dispatches are passed over, then `count` dispatches are
+    grouped by index modulo `period`."""
+    rows = sorted((r for r in _rows(path) if kernel in r["Kernel_Name"]), key=lambda r: int(r["Start_Timestamp"]))
+    run = rows[skip:skip + count]
+    if len(run) < count:
+        raise SystemExit(f"only {len(run)} dispatches of {kernel!r} after skipping {skip}")
+    by = [[] for _ in range(period)]
+    for i, r in enumerate(run):
+        by[i % period].append((int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) / 1e3)
+    span = (int(run[-1]["End_Timestamp"]) - int(run[0]["Start_Timestamp"])) / 1e3
+    out = ["| position | region | median (us) | mean (us) | share of kernel time |", "|---|---|---|---|---|"]
+    total = sum(sum(v) for v in by)
+    for k, v in enumerate(by):
+        name = labels[k] if k < len(labels) else ""
+        out.append(f"| {k} | {name} | {statistics.median(v):.1f} | {statistics.mean(v):.1f} | "
+                   f"{100 * sum(v) / total:.1f} % |")
+    reps = count / period
+    out.append("")
+    out.append(f"Kernel time per period: {total / reps:.1f} us; wall span per period (first dispatch start to "
+               f"last dispatch end, divided by {reps:g}): {span / reps:.1f} us.")
+    return "\n".join(out)
+
+
 def main():
     ap = argparse.ArgumentParser()
     sub = ap.add_subparsers(dest="cmd", required=True)
     s = sub.add_parser("stats")
     s.add_argument("csv")
     s.add_argument("--top", type=int, default=8)
+    q = sub.add_parser("positions")
+    q.add_argument("csv")
+    q.add_argument("--kernel", required=True)
+    q.add_argument("--skip", type=int, default=0)
+    q.add_argument("--period", type=int, required=True)
+    q.add_argument("--count", type=int, required=True)
+    q.add_argument("--labels", default="")
     t = sub.add_parser("traffic")
     t.add_argument("--fetch", required=True)
     t.add_argument("--write", required=True)
@@ -97,6 +133,10 @@ def main():
     args = ap.parse_args()
     if args.cmd == "stats":
         print(stats_table(args.csv, args.top))
+        return
+    if args.cmd == "positions":
+        print(positions_table(args.csv, args.kernel, args.skip, args.period, args.count,
+                              [x for x in args.labels.split(",") if x] if args.labels else []))
         return
     e = traffic(args)
     a = args.alg_bytes
