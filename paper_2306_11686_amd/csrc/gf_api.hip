@@ -1345,6 +1345,8 @@ gf_status enqueue_per_region(gf_ctx *ctx, const DProg &p, const gf_instance &in,
                 for (int k = 0; k < c.nargs; ++k)
                     if ((c.a[k].kind == GF_ARG_REF || c.a[k].kind == GF_ARG_HEAPREF))
                         g.obj[c.a[k].ref] = arr[c.a[k].slot];
+                if (c.nrefs > 0)
+                    cur.publish = 1;
             }
         }
     }

@@ -73,11 +73,15 @@ __device__ __forceinline__ double block_reduce_rt(int op, double v, double *lds)
 // Reduce p[0..n) in a fixed order (strided per thread, then the workgroup
 // tree). Every workgroup that calls this on the same data with the same
 // blockDim gets the same bits; the result is valid in thread 0.
+// COHERENT: read each partial with an agent-scope load, for partials that
+// were stored at agent scope and never written back by a release.
+template <bool COHERENT = false>
 __device__ __forceinline__ double reduce_partials(int op, const double *p, int64_t n, double *lds)
 {
     double acc = red_identity(op);
     for (int64_t i = threadIdx.x; i < n; i += blockDim.x)
-        acc = red_apply(op, acc, p[i]);
+        acc = red_apply(op, acc,
+                        COHERENT ? __hip_atomic_load(p + i, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) : p[i]);
     return block_reduce_rt(op, acc, lds);
 }
 
@@ -185,6 +189,16 @@ __device__ __forceinline__ void wg_publish()
     __syncthreads();
     if (threadIdx.x == 0)
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+}
+
+// The cheap half of wg_publish: every wavefront's memory operations have
+// completed (loads returned; stores acknowledged, which for agent-scope
+// stores means they reached memory past the XCD's L2), then the workgroup
+// barrier. No L2 write-back: plain stores stay in this XCD's L2.
+__device__ __forceinline__ void wg_settle()
+{
+    __builtin_amdgcn_s_waitcnt(0x0F70);  // vmcnt(0)
+    __syncthreads();
 }
 
 __device__ __forceinline__ bool tree_barrier(uint32_t *genw, uint32_t *tree, uint32_t member, uint32_t nmembers,

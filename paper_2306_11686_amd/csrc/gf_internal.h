@@ -221,7 +221,7 @@ struct RegionLaunch {
     int32_t n_items;
     int32_t n_glue;
     int32_t inst;          // instance index (finalize counter line)
-    int32_t pad_;
+    int32_t publish;       // 1: the glue reads what the region wrote (a host call with references)
     Glue glue[kMaxGlue];
 };
 
