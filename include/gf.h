@@ -164,6 +164,21 @@ typedef enum {
 
 #define GF_STEP_BLOCKING 1u
 #define GF_STEP_TIMED 2u   /* GF_S_CALL: accumulate per-stage times */
+/* GF_STEP_NOWAIT on a region: OpenMP's nowait clause (Section 3.3: a
+ * region's implicit barrier becomes a barrier across all workgroups in the
+ * persistent modes; nowait removes it). Threads that finish their part go on
+ * to the steps that follow without waiting for the others. The caller
+ * guarantees, as an OpenMP programmer does, that nothing before the next
+ * barrier reads or writes another thread's part of what the region
+ * accessed. As with OpenMP's static schedule, GF_R_DOT and GF_R_AXPBY over
+ * the same size in one launch give element i to the same thread, so an
+ * axpby writing r may skip its barrier before a dot reading r. Rejected
+ * (GF_EINVAL) with a reduction clause (its value needs the barrier), on
+ * GF_R_HIST and GF_R_PHASES, and when a GF_S_CALL follows before the next
+ * region (its copy-in would read data other workgroups may still write).
+ * The per-region and kernel-split modes end every region with its launch
+ * and ignore the flag. */
+#define GF_STEP_NOWAIT 4u
 
 typedef struct {
     int32_t kind;      /* gf_step_kind */
@@ -175,7 +190,7 @@ typedef struct {
     int32_t fmt_id;    /* GF_S_PRINTF format id from gf_rpc_register_format;
                           GF_S_CALL call-site id from gf_rpc_register_call */
     int32_t nargs;     /* GF_S_PRINTF argument count incl. the iteration number */
-    uint32_t flags;    /* GF_STEP_BLOCKING, GF_STEP_TIMED */
+    uint32_t flags;    /* GF_STEP_BLOCKING, GF_STEP_TIMED (serial); GF_STEP_NOWAIT (regions) */
     uint32_t mask;     /* GF_R_HIST bin mask (nbins - 1, nbins a power of two);
                           GF_R_PHASES shift s */
     int64_t chunk;     /* GF_R_OWNER schedule(static, chunk), 0 = schedule(static);

@@ -19,7 +19,7 @@ GF_R_JACOBI2D, GF_R_JACOBI3D, GF_R_SPMV, GF_R_DOT, GF_R_AXPBY, GF_R_HIST, GF_R_O
     1, 2, 3, 4, 5, 6, 7, 8
 GF_S_SET, GF_S_COPY, GF_S_DIV, GF_S_SQRT, GF_S_SWAP, GF_S_RECORD, GF_S_PRINTF, GF_S_CALL = \
     32, 33, 34, 35, 36, 37, 38, 39
-GF_STEP_BLOCKING, GF_STEP_TIMED = 1, 2
+GF_STEP_BLOCKING, GF_STEP_TIMED, GF_STEP_NOWAIT = 1, 2, 4
 
 GF_CALLEE_FPRINTF, GF_CALLEE_SNPRINTF, GF_CALLEE_SSCANF, GF_CALLEE_FWRITE, GF_CALLEE_FREAD = 1, 2, 3, 4, 5
 GF_ARG_CONST, GF_ARG_SCALAR, GF_ARG_ITER, GF_ARG_REF, GF_ARG_HEAPREF = 0, 1, 2, 3, 4

@@ -885,6 +885,12 @@ gf_status check_step(gf_ctx *ctx, const gf_step &s, int idx)
         if (s.kind == GF_R_PHASES && (s.arr[0] == s.arr[1] || s.arr[2] == s.arr[0] || s.arr[2] == s.arr[1]))
             return fail(ctx, GF_EINVAL, "step %d: the two phase buffers and the owner map must be distinct slots",
                         idx);
+        if (s.flags & ~GF_STEP_NOWAIT)
+            return fail(ctx, GF_EINVAL, "step %d: a region takes only the nowait flag", idx);
+        if ((s.flags & GF_STEP_NOWAIT) && s.red_op != GF_OP_NONE)
+            return fail(ctx, GF_EINVAL, "step %d: nowait with a reduction clause (its value needs the barrier)", idx);
+        if ((s.flags & GF_STEP_NOWAIT) && (s.kind == GF_R_HIST || s.kind == GF_R_PHASES))
+            return fail(ctx, GF_EINVAL, "step %d: nowait on a region with barriers inside it", idx);
         return GF_OK;
     }
     if (!is_serial(s.kind))
@@ -1063,6 +1069,24 @@ gf_status build_program(gf_ctx *ctx, const gf_program *prog, DProg *out)
     }
     if (program_mixes_hist(*out))
         return fail(ctx, GF_EUNSUPPORTED, "a histogram region can only share a program with schedule regions");
+    // a host call between a nowait region and the next region would copy
+    // in data that other workgroups may still be writing. Steps are walked
+    // in execution order, the body taken as repeating.
+    auto next_step = [&](int j) -> int {
+        if (j + 1 < out->n_steps)
+            return (j + 1 == out->n_pro && out->iters == 0) ? -1 : j + 1;
+        return (out->n_body > 0 && out->iters > 0) ? out->n_pro : -1;
+    };
+    for (int i = 0; i < out->n_steps; ++i) {
+        if (!is_region(out->steps[i].kind) || !(out->steps[i].flags & GF_STEP_NOWAIT))
+            continue;
+        int j = next_step(i);
+        for (int guard = 0; j >= 0 && guard < out->n_steps && !is_region(out->steps[j].kind);
+             ++guard, j = next_step(j))
+            if (out->steps[j].kind == GF_S_CALL)
+                return fail(ctx, GF_EINVAL, "step %d: a host call (step %d) follows a nowait region before the "
+                            "next region", i, j);
+    }
     // last region in execution order and the number of grid barriers
     out->last_region = -1;
     int64_t bar_pro = 0, bar_body = 0;
@@ -1071,7 +1095,7 @@ gf_status build_program(gf_ctx *ctx, const gf_program *prog, DProg *out)
             continue;
         // a histogram region has one barrier inside it, a phase region one
         // between consecutive phases
-        int64_t b = 1;
+        int64_t b = (out->steps[i].flags & GF_STEP_NOWAIT) ? 0 : 1;
         if (out->steps[i].kind == GF_R_HIST)
             b = 2;
         else if (out->steps[i].kind == GF_R_PHASES)
@@ -1090,10 +1114,11 @@ gf_status build_program(gf_ctx *ctx, const gf_program *prog, DProg *out)
     out->barriers = bar_pro + bar_body * out->iters;
     if (out->last_region >= 0) {
         // the persistent kernel skips the barrier after the last region
-        // when that region has no reduction
+        // when that region has no reduction (a nowait region was not
+        // counted)
         const int64_t lr = out->last_region;
         const int si = lr < out->n_pro ? (int)lr : out->n_pro + (int)((lr - out->n_pro) % out->n_body);
-        if (out->steps[si].red_op == GF_OP_NONE)
+        if (out->steps[si].red_op == GF_OP_NONE && !(out->steps[si].flags & GF_STEP_NOWAIT))
             out->barriers -= 1;
     }
     // host calls: a grid barrier after each call that fires; a call that
@@ -1111,7 +1136,7 @@ gf_status build_program(gf_ctx *ctx, const gf_program *prog, DProg *out)
     if (call_refs && out->last_region >= 0) {
         const int64_t lr = out->last_region;
         const int si = lr < out->n_pro ? (int)lr : out->n_pro + (int)((lr - out->n_pro) % out->n_body);
-        if (out->steps[si].red_op == GF_OP_NONE)
+        if (out->steps[si].red_op == GF_OP_NONE && !(out->steps[si].flags & GF_STEP_NOWAIT))
             out->barriers += 1;
         out->last_region = -1;
     }

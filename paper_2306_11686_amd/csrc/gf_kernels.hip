@@ -1210,8 +1210,9 @@ __global__ void __launch_bounds__(family_max_threads<KMASK>())
             const int64_t n = inst.ip[st.np];
             const bool red = st.red_op != GF_OP_NONE;
             // after the last region, a region without a reduction needs no
-            // barrier: the serial steps that may follow touch no region data
-            const bool need_bar = red || si != last_region;
+            // barrier: the serial steps that may follow touch no region data;
+            // nor does a nowait region (the caller vouches for what follows)
+            const bool need_bar = red || (si != last_region && !(st.flags & GF_STEP_NOWAIT));
             double *part = scr.partials + (parity ? scr.partials_cap : 0) + be.part_off;
             void *op[5];
 #pragma unroll

@@ -12,7 +12,7 @@ import math
 
 from .binding import (GF_OP_MAX, GF_OP_NONE, GF_OP_SUM, GF_R_AXPBY, GF_R_DOT, GF_R_HIST, GF_R_JACOBI2D,
                       GF_R_JACOBI3D, GF_R_OWNER, GF_R_PHASES, GF_R_SPMV, GF_S_COPY, GF_S_DIV, GF_S_PRINTF,
-                      GF_S_RECORD, GF_S_SET, GF_S_SQRT, GF_S_SWAP, Program, Step)
+                      GF_S_RECORD, GF_S_SET, GF_S_SQRT, GF_S_SWAP, GF_STEP_NOWAIT, Program, Step)
 
 JACOBI2D_FORMAT = "sweep %d residual %.10e\n"
 
@@ -53,24 +53,30 @@ def jacobi2d(sweeps: int, fmt_id: int = -1, print_every: int = 10, blocking: boo
     return Program.make([], body, sweeps)
 
 
-def cg(iters: int) -> Program:
+def cg(iters: int, nowait: bool = True) -> Program:
     """Conjugate gradients, every loop a separate region. The caller sets
-    x = 0, r = b, p = b. rho_hist[k] = rho after iteration k."""
+    x = 0, r = b, p = b. rho_hist[k] = rho after iteration k.
+
+    With `nowait`, the two axpby loops of the update drop their barriers, as
+    an OpenMP author would mark them: x += alpha p touches nothing the next
+    loop uses, and r -= alpha q shares its static schedule with the dot that
+    reads r (each thread reads back only the elements it wrote)."""
     pro = [
         Step.make(GF_S_SET, sc=(CG_S_RHO,), c=0.0),
         Step.make(GF_R_DOT, arr=(CG_R, CG_R), sc=(CG_S_RHO,), red_op=GF_OP_SUM, np=0),
     ]
-    return Program.make(pro, list(_cg_body()), iters)
+    return Program.make(pro, list(_cg_body(nowait)), iters)
 
 
-def _cg_body():
+def _cg_body(nowait: bool = True):
+    nw = GF_STEP_NOWAIT if nowait else 0
     return [
         Step.make(GF_R_SPMV, arr=(CG_ROWPTR, CG_COL, CG_VAL, CG_P, CG_Q), np=0),
         Step.make(GF_S_SET, sc=(CG_S_PQ,), c=0.0),
         Step.make(GF_R_DOT, arr=(CG_P, CG_Q), sc=(CG_S_PQ,), red_op=GF_OP_SUM, np=0),
         Step.make(GF_S_DIV, sc=(CG_S_ALPHA, CG_S_RHO, CG_S_PQ)),
-        Step.make(GF_R_AXPBY, arr=(CG_X, CG_X, CG_P), sc=(-1, CG_S_ALPHA), c=1.0, np=0),
-        Step.make(GF_R_AXPBY, arr=(CG_R, CG_R, CG_Q), sc=(-1, CG_S_ALPHA), c=-1.0, np=0),
+        Step.make(GF_R_AXPBY, arr=(CG_X, CG_X, CG_P), sc=(-1, CG_S_ALPHA), c=1.0, np=0, flags=nw),
+        Step.make(GF_R_AXPBY, arr=(CG_R, CG_R, CG_Q), sc=(-1, CG_S_ALPHA), c=-1.0, np=0, flags=nw),
         Step.make(GF_S_SET, sc=(CG_S_RHONEW,), c=0.0),
         Step.make(GF_R_DOT, arr=(CG_R, CG_R), sc=(CG_S_RHONEW,), red_op=GF_OP_SUM, np=0),
         Step.make(GF_S_DIV, sc=(CG_S_BETA, CG_S_RHONEW, CG_S_RHO)),
@@ -80,10 +86,10 @@ def _cg_body():
     ]
 
 
-def cg_iterations_only(iters: int) -> Program:
+def cg_iterations_only(iters: int, nowait: bool = True) -> Program:
     """The CG body without its prologue: continues from the state (x, r, p) and
     the scalar rho already held by the instance."""
-    return Program.make([], list(_cg_body()), iters)
+    return Program.make([], list(_cg_body(nowait)), iters)
 
 
 def histogram(nbins: int = 65536) -> Program:

@@ -146,6 +146,69 @@ def test_cg_persistent_equals_per_region_bitwise(gfx):
     assert np.array_equal(outs[0][0], outs[1][0]) and np.array_equal(outs[0][1], outs[1][1])
 
 
+@pytest.mark.parametrize("m,iters", [(9, 25), (64, 12)])
+def test_cg_nowait_equals_every_barrier_bitwise(gfx, m, iters):
+    """The two axpby loops marked nowait drop two of the six barriers per
+    iteration in the persistent kernel. The results are the same bits as
+    with every barrier kept (same schedule, same summation order), and the
+    run reports two fewer barriers per iteration."""
+    import paper_2306_11686_amd as gf
+    from paper_2306_11686_amd import programs
+    print(f"cg nowait m={m} iters={iters}", flush=True)
+    b = gi.cg_rhs(m ** 3, seed=3)
+    outs, bars = [], []
+    for nowait in (False, True):
+        inst, t, sc = _cg_instance(gf, programs, m, b, rho_hist_len=iters)
+        st = gfx.run(programs.cg(iters, nowait=nowait), inst, mode=gf.GF_EXEC_PERSISTENT)
+        gfx.sync()
+        outs.append([host(t[k]) for k in (programs.CG_X, programs.CG_R, programs.CG_P, programs.CG_RHO)])
+        bars.append(st["barriers"])
+    assert bars[0] - bars[1] == 2 * iters
+    for a, c in zip(*outs):
+        assert np.array_equal(a, c)
+
+
+def test_nowait_misuse_is_rejected(gfx):
+    """nowait is refused where the barrier it drops is needed: after a
+    reduction, on regions with barriers inside them, and before a host call
+    that would copy in arrays other workgroups may still write."""
+    import torch
+    import paper_2306_11686_amd as gf
+    from oracle import hostcall as hc
+    S = gf.Step
+    n = 1024
+    a = torch.ones(n, dtype=torch.float64, device="cuda")
+    sc = scalars()
+    inst = gf.Instance.make({0: a, 1: a, 2: a}, sc, ip=(n,))
+    nw = gf.GF_STEP_NOWAIT
+    axpby = S.make(gf.GF_R_AXPBY, arr=(2, 0, 1), sc=(-1, 2), c=1.0, np=0, flags=nw)
+    bad = [
+        [S.make(gf.GF_R_DOT, arr=(0, 1), sc=(1,), red_op=gf.GF_OP_SUM, np=0, flags=nw)],
+        [S.make(gf.GF_R_HIST, arr=(0, 1), np=0, mask=255, flags=nw)],
+        [S.make(gf.GF_R_PHASES, arr=(0, 1, -1), np=0, chunk=2, mask=1, flags=nw)],
+        [S.make(gf.GF_R_AXPBY, arr=(2, 0, 1), sc=(-1, 2), c=1.0, np=0, flags=gf.GF_STEP_BLOCKING)],
+    ]
+    for steps in bad:
+        with pytest.raises(gf.GfError) as ei:
+            gfx.run(gf.Program.make(steps, [], 0), inst)
+        assert ei.value.status == gf.binding.GF_EINVAL
+    cid = gfx.register_call(gf.GF_CALLEE_FWRITE, [gf.CallArg.ref(0, 8, mode=gf.GF_REF_READ), gf.CallArg.const(8),
+                                                  gf.CallArg.const(1), gf.CallArg.const(hc.STDOUT, "p")])
+    call = S.make(gf.GF_S_CALL, fmt_id=cid, every=1)
+    setv = S.make(gf.GF_S_SET, sc=(3,), c=1.0)
+    plain = S.make(gf.GF_R_AXPBY, arr=(2, 0, 1), sc=(-1, 2), c=1.0, np=0)
+    for pro, body, iters in (([axpby, setv, call], [], 0),       # directly after, past a serial step
+                             ([], [call, axpby], 2),              # the body wraps around to the call
+                             ([axpby], [setv, call, plain], 1)):  # the prologue runs into the body
+        with pytest.raises(gf.GfError) as ei:
+            gfx.run(gf.Program.make(pro, body, iters), inst)
+        assert ei.value.status == gf.binding.GF_EINVAL
+    # a region between them restores the barrier, and the last region's
+    # nowait is accepted
+    gfx.run(gf.Program.make([axpby, setv, plain, call, axpby], [], 0), inst)
+    gfx.sync()
+
+
 @pytest.mark.parametrize("k", [1, 10, 100, 499])
 def test_cg_128_lockstep_replay(gfx, oracle_lib, k):
     """128^3 (2,097,152 rows, 55,742,968 nonzeros), the benchmark size: run k

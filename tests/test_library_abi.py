@@ -65,7 +65,7 @@ def test_binding_constants_match_header():
     names = ["GF_S_CALL", "GF_STEP_TIMED", "GF_CALLEE_FPRINTF", "GF_CALLEE_SNPRINTF", "GF_CALLEE_SSCANF",
              "GF_CALLEE_FWRITE", "GF_CALLEE_FREAD", "GF_ARG_CONST", "GF_ARG_SCALAR", "GF_ARG_ITER", "GF_ARG_REF", "GF_ARG_HEAPREF",
              "GF_REF_READ", "GF_REF_WRITE", "GF_REF_READWRITE", "GF_CALL_MAX_ARGS", "GF_CALL_MAX_REFS",
-             "GF_CALL_MAX_SITES", "GF_S_PRINTF", "GF_STEP_BLOCKING", "GF_R_OWNER", "GF_R_PHASES",
+             "GF_CALL_MAX_SITES", "GF_S_PRINTF", "GF_STEP_BLOCKING", "GF_STEP_NOWAIT", "GF_R_OWNER", "GF_R_PHASES",
              "GF_HEAP_OP_MALLOC", "GF_HEAP_OP_FREE", "GF_HEAP_OP_FIND", "GF_HEAP_BENCH_ROUNDTRIP",
              "GF_HEAP_BENCH_HOLD", "GF_HEAP_BENCH_RELEASE"]
     with tempfile.TemporaryDirectory() as d:
