@@ -90,3 +90,34 @@ def test_copy_kernel(gfx):
     gfx.copy(b, a, a.numel() * 8)
     torch.cuda.synchronize()
     assert torch.equal(a, b)
+
+
+@pytest.mark.parametrize("num_wg", [4096, 1021])
+def test_per_region_reduction_sees_every_workgroup(gfx, oracle_lib, num_wg):
+    """One launch per region over thousands of workgroups on all XCDs: the
+    workgroup that finishes last reads every other one's partial, which was
+    stored at agent scope without an L2 write-back. Ten launches over fresh
+    data, each checked against the oracle."""
+    import torch
+    import paper_2306_11686_amd as gf
+    from tests.gpu_helpers import scalars
+    print(f"per-region dot num_wg={num_wg}", flush=True)
+    n = (1 << 22) + 5
+    idx = np.arange(n, dtype=np.uint64)
+    ta = torch.empty(n, dtype=torch.float64, device="cuda")
+    tb = torch.empty(n, dtype=torch.float64, device="cuda")
+    sc = scalars()
+    prog = gf.Program.make([gf.Step.make(gf.GF_R_DOT, arr=(0, 1), sc=(1,), red_op=gf.GF_OP_SUM, np=0)], [], 0)
+    inst = gf.Instance.make({0: ta, 1: tb}, sc, ip=(n,))
+    for rep in range(10):
+        a = gi.um11(40 + rep, 11, idx)
+        b = gi.um11(80 + rep, 11, idx)
+        ta.copy_(torch.from_numpy(a))
+        tb.copy_(torch.from_numpy(b))
+        sc.zero_()
+        st = gfx.run(prog, inst, mode=gf.GF_EXEC_PER_REGION, launch=gf.Launch.make(items=1, num_wg=num_wg))
+        gfx.sync()
+        assert st["num_wg"] == num_wg
+        d, s = oracle_lib.dot_compensated(a, b)
+        got = host(sc)[1]
+        assert abs(got - d) <= 1e-12 * s, (rep, got, d)
