@@ -272,10 +272,10 @@ __device__ __forceinline__ bool flat_barrier(uint32_t *line, uint32_t nmembers, 
 // fences of the tree barrier do per workgroup (write the XCD's L2 back,
 // invalidate it) needs doing once per XCD: a workgroup's stores are in its
 // XCD's L2 once acknowledged, so after the XCD's last arrival has counted
-// every member it writes that L2 back for all of them; after the global
-// generation moves it invalidates that L2 and releases the XCD's members,
-// which acquire in turn. The write-backs (one per XCD instead of one per
-// workgroup) are what the tree barrier pays most for.
+// every member it writes that L2 back for all of them. Every workgroup then
+// waits for the global generation to move and acquires (invalidates) for
+// itself. The write-backs (one per XCD instead of one per workgroup) are
+// what the tree barrier pays most for.
 // Membership is counted once per launch: each workgroup reads its XCD id
 // from the hardware register and adds itself to that XCD's registration word
 // (tagged with the launch's epoch so stale counts from earlier launches are
@@ -361,7 +361,6 @@ __device__ __forceinline__ bool xcd_barrier(uint32_t *lines, const XcdState &xs,
     if (threadIdx.x == 0) {
         uint32_t *genw = lines + 1;
         uint32_t *xcnt = lines + (kXcdCntLine0 + xs.x) * kLineWords;
-        uint32_t *xgen = lines + (kXcdGenLine0 + xs.x) * kLineWords;
         uint32_t *top = lines + kXcdTopLine * kLineWords;
         const uint32_t g = bs->gen;
         int32_t ok = 1;
@@ -379,13 +378,13 @@ __device__ __forceinline__ bool xcd_barrier(uint32_t *lines, const XcdState &xs,
                 ok = wait_equal(genw, g + 1u, err, timeout_ticks) ? 1 : 0;
             }
             __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");  // invalidate this XCD's L2 (and our L1)
-            __builtin_amdgcn_s_waitcnt(0x0F70);
-            __hip_atomic_store(xgen, g + 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         } else {
-            ok = wait_equal(xgen, g + 1u, err, timeout_ticks) ? 1 : 0;
-            // A member still invalidates at agent scope: measured, an L1-only
+            // Members wait for the global generation themselves rather than
+            // for a flag their leader sets after seeing it (one hop less),
+            // and each invalidates at agent scope: measured, an L1-only
             // invalidate after the leader's L2 invalidate let stale lines
             // through.
+            ok = wait_equal(genw, g + 1u, err, timeout_ticks) ? 1 : 0;
             __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
         }
         bs->gen = g + 1u;

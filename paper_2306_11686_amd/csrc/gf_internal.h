@@ -179,22 +179,24 @@ constexpr int kLineWords = 32;  // uint32 words per 128-byte line
 // line 0: generation word of the grid barrier; lines kTreeLine0..: the
 // arrival counters of the barrier's fan-in tree; lines kGroupLine0 + i:
 // per-instance group barriers {count, gen}; lines kFinalizeLine0 + i:
-// per-region last-workgroup counters. Words 4-5 of a group line carry the
-// return value of a GF_S_CALL from the group's first workgroup to the others.
+// per-region last-workgroup counters, fed by the kNumXcd arrival counters
+// at lines kFinalizeSubLine0 + i * kNumXcd + g. Words 4-5 of a group line
+// carry the return value of a GF_S_CALL from the group's first workgroup to
+// the others.
 constexpr int kTreeFanIn = 16;
 constexpr int kTreeLine0 = 1;
 constexpr int kTreeLines = 512;  // >= 4096/16 + 4096/256 + 1
 constexpr int kGroupLine0 = kTreeLine0 + kTreeLines;
 constexpr int kFinalizeLine0 = kGroupLine0 + GF_MAX_INSTANCES;
 // XCD barrier: per-XCD registration words (epoch << 32 | members), per-XCD
-// arrival counters and release generations, the count of XCD leaders, and
+// arrival counters, the count of XCD leaders, and
 // the count of workgroups that reported an unexpected XCD id.
 constexpr int kXcdRegLine0 = kFinalizeLine0 + GF_MAX_INSTANCES;
 constexpr int kXcdCntLine0 = kXcdRegLine0 + kNumXcd;
-constexpr int kXcdGenLine0 = kXcdCntLine0 + kNumXcd;
-constexpr int kXcdTopLine = kXcdGenLine0 + kNumXcd;
+constexpr int kXcdTopLine = kXcdCntLine0 + kNumXcd;
 constexpr int kXcdBadLine = kXcdTopLine + 1;
-constexpr int kNumLines = kXcdBadLine + 1;
+constexpr int kFinalizeSubLine0 = kXcdBadLine + 1;
+constexpr int kNumLines = kFinalizeSubLine0 + GF_MAX_INSTANCES * kNumXcd;
 
 // A serial step attached to a per-region launch, with its array operand
 // resolved on the host (SWAPs are applied by the host while it walks the

@@ -1380,14 +1380,28 @@ __global__ void __launch_bounds__(family_max_threads<KMASK>()) k_region(RegionLa
     // before it counts itself done. The per-workgroup L2 write-back is most
     // of the finalize's cost (a 16 MiB axpby takes 10 us alone, 34 us with
     // it).
+    // Counting is two-level: workgroup b arrives on sub-counter b mod 8 (its
+    // own 128-byte line), and the last arrival of each sub-counter on the
+    // top counter. One word taking every workgroup's atomic serialised them
+    // (about 10 us for 1,024 workgroups).
     uint32_t *cnt = scr.lines + (int64_t)(kFinalizeLine0 + rl.inst) * kLineWords;
     if (rl.publish)
         wg_publish();
     else
         wg_settle();
     if (threadIdx.x == 0) {
-        const uint32_t a = __hip_atomic_fetch_add(cnt, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        s_last = (a == (uint32_t)G - 1);
+        const uint32_t ug = (uint32_t)G, g = blockIdx.x % kNumXcd;
+        const uint32_t nsub = ug < (uint32_t)kNumXcd ? ug : (uint32_t)kNumXcd;
+        const uint32_t members = ug / kNumXcd + (g < ug % kNumXcd ? 1u : 0u);
+        uint32_t *sub = scr.lines + ((int64_t)kFinalizeSubLine0 + (int64_t)rl.inst * kNumXcd + g) * kLineWords;
+        int last = 0;
+        if (__hip_atomic_fetch_add(sub, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == members - 1) {
+            // every member of this sub-counter has arrived: reset it for the
+            // next launch (the launch boundary orders the two)
+            __hip_atomic_store(sub, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            last = __hip_atomic_fetch_add(cnt, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == nsub - 1;
+        }
+        s_last = last;
     }
     __syncthreads();
     if (!s_last)
