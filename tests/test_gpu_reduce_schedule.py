@@ -121,3 +121,36 @@ def test_per_region_reduction_sees_every_workgroup(gfx, oracle_lib, num_wg):
         d, s = oracle_lib.dot_compensated(a, b)
         got = host(sc)[1]
         assert abs(got - d) <= 1e-12 * s, (rep, got, d)
+
+
+@pytest.mark.parametrize("num_wg", [1, 2, 3, 7, 8, 9, 17, 1000])
+def test_per_region_finalize_counts_every_grid_size(gfx, oracle_lib, num_wg):
+    """The finishing workgroup is found through eight sub-counters (workgroup
+    b on counter b mod 8) and a top counter; grids smaller than eight or not
+    a multiple of it leave sub-counters short or empty. Three launches in a
+    row (the counters must be back at zero after each) of a dot whose glue
+    divides two scalars: the glue runs exactly once per launch."""
+    import torch
+    import paper_2306_11686_amd as gf
+    from tests.gpu_helpers import scalars
+    print(f"per-region finalize num_wg={num_wg}", flush=True)
+    n = 300007
+    idx = np.arange(n, dtype=np.uint64)
+    a = gi.um11(5, 11, idx)
+    b = gi.um11(6, 11, idx)
+    ta, tb = dev(a), dev(b)
+    prog = gf.Program.make([
+        gf.Step.make(gf.GF_R_DOT, arr=(0, 1), sc=(1,), red_op=gf.GF_OP_SUM, np=0),
+        gf.Step.make(gf.GF_S_DIV, sc=(2, 3, 1)),
+        gf.Step.make(gf.GF_S_SET, sc=(4,), c=7.0),
+    ], [], 0)
+    d, s = oracle_lib.dot_compensated(a, b)
+    for rep in range(3):
+        sc = scalars({3: 2.0 + rep})
+        inst = gf.Instance.make({0: ta, 1: tb}, sc, ip=(n,))
+        st = gfx.run(prog, inst, mode=gf.GF_EXEC_PER_REGION, launch=gf.Launch.make(items=1, num_wg=num_wg))
+        gfx.sync()
+        assert st["launches"] == 1 and st["num_wg"] == num_wg
+        h = host(sc)
+        assert abs(h[1] - d) <= 1e-12 * s
+        assert h[2] == (2.0 + rep) / h[1] and h[4] == 7.0
