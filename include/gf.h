@@ -174,8 +174,9 @@ typedef enum {
  * the same size in one launch give element i to the same thread, so an
  * axpby writing r may skip its barrier before a dot reading r. Rejected
  * (GF_EINVAL) with a reduction clause (its value needs the barrier), on
- * GF_R_HIST and GF_R_PHASES, and when a GF_S_CALL follows before the next
- * region (its copy-in would read data other workgroups may still write).
+ * GF_R_HIST and GF_R_PHASES, and when a GF_S_CALL with reference arguments
+ * follows before the next region (its copy-in would read data other
+ * workgroups may still write).
  * The per-region and kernel-split modes end every region with its launch
  * and ignore the flag. */
 #define GF_STEP_NOWAIT 4u

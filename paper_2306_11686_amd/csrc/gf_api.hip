@@ -1069,9 +1069,9 @@ gf_status build_program(gf_ctx *ctx, const gf_program *prog, DProg *out)
     }
     if (program_mixes_hist(*out))
         return fail(ctx, GF_EUNSUPPORTED, "a histogram region can only share a program with schedule regions");
-    // a host call between a nowait region and the next region would copy
-    // in data that other workgroups may still be writing. Steps are walked
-    // in execution order, the body taken as repeating.
+    // a host call with references between a nowait region and the next
+    // region would copy in data that other workgroups may still be writing.
+    // Steps are walked in execution order, the body taken as repeating.
     auto next_step = [&](int j) -> int {
         if (j + 1 < out->n_steps)
             return (j + 1 == out->n_pro && out->iters == 0) ? -1 : j + 1;
@@ -1083,9 +1083,12 @@ gf_status build_program(gf_ctx *ctx, const gf_program *prog, DProg *out)
         int j = next_step(i);
         for (int guard = 0; j >= 0 && guard < out->n_steps && !is_region(out->steps[j].kind);
              ++guard, j = next_step(j))
-            if (out->steps[j].kind == GF_S_CALL)
-                return fail(ctx, GF_EINVAL, "step %d: a host call (step %d) follows a nowait region before the "
-                            "next region", i, j);
+            if (out->steps[j].kind == GF_S_CALL) {
+                std::lock_guard<std::mutex> g(ctx->rpc_mu);
+                if (ctx->calls[out->steps[j].fmt_id].dev.nrefs > 0)
+                    return fail(ctx, GF_EINVAL, "step %d: a host call with references (step %d) follows a nowait "
+                                "region before the next region", i, j);
+            }
     }
     // last region in execution order and the number of grid barriers
     out->last_region = -1;
