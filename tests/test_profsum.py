@@ -1,6 +1,7 @@
 """The rocprofv3 summaries behind the committed profiles (CPU only): per-kernel
-statistics, dispatch durations by position in a repeating sequence, and HBM
-traffic scaled by the copy kernel's counter readings."""
+statistics, dispatch durations by position in a repeating sequence, HBM
+traffic scaled by the copy kernel's counter readings, and the source hash
+that ties a traffic measurement to the code it was taken on."""
 import argparse
 import csv
 import json
@@ -85,3 +86,26 @@ def test_traffic_scales_each_counter_by_the_copy_kernel(tmp_path):
     assert e["write_bytes_per_launch"] == 400 * 1024            # mean over the kernel's dispatches
     assert e["dispatches"] == [1, 2]
     assert json.loads(db.read_text())["w"]["bytes_per_launch"] == e["bytes_per_launch"]
+
+
+def test_source_hash_ignores_comments_but_not_code():
+    from paper_2306_11686_amd.build import _code_only
+    a = "int f(int x) {\n    return x + 1;  // one more\n}\n/* note */\n"
+    b = "int f(int x)\n{ /* changed\n comment */ return x + 1; }\n"
+    c = "int f(int x) { return x + 2; }"
+    assert _code_only(a) == _code_only(b) != _code_only(c)
+
+
+def test_bench_reports_traffic_only_for_the_measured_code(tmp_path, monkeypatch):
+    """bench.py's roofline.traffic comes from profiles/traffic.json only when
+    the entry's source hash is that of the kernels as they are now."""
+    import bench
+    (tmp_path / "profiles").mkdir()
+    (tmp_path / "profiles" / "traffic.json").write_text(json.dumps(
+        {"w": {"source_hash": "abc", "bytes_per_launch": 42}}))
+    monkeypatch.setattr(bench, "ROOT", str(tmp_path))
+    monkeypatch.setattr(bench, "kernel_source_hash", lambda: "abc")
+    assert bench.load_traffic("w") == 42
+    assert bench.load_traffic("other") is None
+    monkeypatch.setattr(bench, "kernel_source_hash", lambda: "def")
+    assert bench.load_traffic("w") is None
