@@ -168,6 +168,29 @@ def test_cg_nowait_equals_every_barrier_bitwise(gfx, m, iters):
         assert np.array_equal(a, c)
 
 
+def test_cg_nowait_in_a_batched_launch(gfx):
+    """Three CG instances of different sizes in one persistent launch (group
+    barriers per instance): with the nowait axpbys the results are the same
+    bits as with every barrier kept, and as each instance run alone."""
+    import paper_2306_11686_amd as gf
+    from paper_2306_11686_amd import programs
+    sides, iters = (5, 9, 13), 15
+    print(f"cg batched nowait sides={sides}", flush=True)
+    runs = []
+    for nowait in (False, True):
+        made = [_cg_instance(gf, programs, m, gi.cg_rhs(m ** 3, seed=10 + m), rho_hist_len=iters) for m in sides]
+        gfx.run(programs.cg(iters, nowait=nowait), [i for i, _, _ in made], mode=gf.GF_EXEC_PERSISTENT)
+        gfx.sync()
+        runs.append([[host(t[k]) for k in (programs.CG_X, programs.CG_RHO)] for _, t, _ in made])
+    for m, a, b in zip(sides, *runs):
+        inst, t, _ = _cg_instance(gf, programs, m, gi.cg_rhs(m ** 3, seed=10 + m), rho_hist_len=iters)
+        gfx.run(programs.cg(iters), inst, mode=gf.GF_EXEC_PERSISTENT)
+        gfx.sync()
+        alone = [host(t[k]) for k in (programs.CG_X, programs.CG_RHO)]
+        for u, v, w in zip(a, b, alone):
+            assert np.array_equal(u, v) and np.array_equal(v, w), m
+
+
 def test_nowait_misuse_is_rejected(gfx):
     """nowait is refused where the barrier it drops is needed: after a
     reduction, on regions with barriers inside them, and before a host call
