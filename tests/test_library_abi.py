@@ -83,6 +83,11 @@ def test_programs_are_well_formed():
     from paper_2306_11686_amd import programs
     p = programs.cg(500)
     assert p.n_prologue == 2 and p.n_body == 12 and p.iters == 500
+    # the two update axpbys (x += alpha p, r -= alpha q) are nowait; no other step is
+    flags = [p.body[i].flags for i in range(p.n_body)]
+    assert [p.body[i].kind for i in (4, 5)] == [5, 5] and flags[4] == flags[5] == 4
+    assert all(f == 0 for i, f in enumerate(flags) if i not in (4, 5))
+    assert all(programs.cg(3, nowait=False).body[i].flags == 0 for i in range(12))
     p3 = programs.jacobi3d(200)
     kinds = [p3.body[i].kind for i in range(p3.n_body)]
     assert kinds == [32, 2, 37, 36]
