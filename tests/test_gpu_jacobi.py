@@ -33,16 +33,17 @@ def test_jacobi3d_small_odd_shapes(gfx, oracle_lib, mode, n, sweeps):
     assert np.array_equal(r, r_ref)
 
 
-@pytest.mark.parametrize("ty,tz,wg,remap", [(1, 1, 64, 0), (2, 7, 128, 1), (4, 16, 192, 0), (8, 64, 256, 1),
-                                            (16, 5, 256, 1), (8, 300, 64, 1)])
+_TILINGS = [(1, 1, 64, 0), (2, 7, 128, 1), (4, 16, 192, 0), (8, 64, 256, 1), (16, 5, 256, 1), (8, 300, 64, 1)]
+
+
+@pytest.mark.parametrize("n,ty,tz,wg,remap", [(n,) + t for n in (41, 64) for t in _TILINGS]
+                         + [(300, 8, 300, 64, 1)])
 @pytest.mark.parametrize("mode", ["persistent", "per_region"])
-@pytest.mark.parametrize("n", [41, 64, 300])
-def test_jacobi3d_tilings(gfx, oracle_lib, ty, tz, wg, remap, mode, n):
+def test_jacobi3d_tilings(gfx, oracle_lib, n, ty, tz, wg, remap, mode):
     """Odd n runs the one-value-per-thread tile, even n the x-pair tile with
-    lane shifts (n = 300 spans several row chunks for small workgroups)."""
+    lane shifts; n = 300 with 64-thread workgroups spans several row chunks
+    per tile row."""
     import paper_2306_11686_amd as gf
-    if n == 300 and wg != 64:
-        pytest.skip("one configuration per large grid keeps the suite short")
     print(f"jacobi3d tiling n={n} ty={ty} tz={tz} wg={wg} remap={remap} mode={mode}", flush=True)
     u0 = gi.grid3d(n, seed=2)
     g_ref, r_ref = oracle_lib.jacobi3d(u0, 3)

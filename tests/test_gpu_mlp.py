@@ -77,10 +77,19 @@ def test_forward_and_backward_match_fp64_oracle(gfx, batch):
     assert abs(float(loss.cpu()[0]) - oracle.mlp_loss(y_ref, tgt, mask)) <= 1e-5 * oracle.mlp_loss(y_ref, tgt, mask)
 
 
+def _plain_draw(batch, seed):
+    """float32 parameters and features with no filter: determinism does not
+    depend on the ReLU masks agreeing with a float64 evaluation."""
+    rng = np.random.default_rng(seed)
+    flat = (rng.standard_normal(NP) * 0.2).astype(np.float32)
+    f = rng.standard_normal((batch, IN)).astype(np.float32)
+    return flat, f
+
+
 def test_backward_is_deterministic(gfx):
     import torch
     batch = 300
-    flat, f, P = _fixture(batch, seed=3)
+    flat, f = _plain_draw(batch, seed=3)
     tgt = np.random.default_rng(5).standard_normal((batch, K)).astype(np.float32)
     mask = np.ones((batch, K), np.float32)
     dp, df = torch.from_numpy(flat).cuda(), torch.from_numpy(f).cuda()

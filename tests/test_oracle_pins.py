@@ -406,6 +406,42 @@ def test_adam_first_step_closed_form(oracle_lib):
     assert np.allclose(p1, p - 0.01 * g / (np.abs(g) + 1e-8), rtol=1e-12, atol=0)
 
 
+def test_adam_constant_gradient_moves_the_same_every_step(oracle_lib):
+    # With g fixed, m_t = (1 - beta1^t) g and v_t = (1 - beta2^t) g^2, so the
+    # bias-corrected moments are g and g^2 at every t and each step moves the
+    # parameter by exactly -lr * g / (|g| + eps). Dropping the decayed previous
+    # moment (beta1 * m or beta2 * v) or taking the correction at the wrong t
+    # changes the step from t = 2 on.
+    g = np.array([0.75, -3.0, 2e-4, 5.0])
+    p = np.array([0.3, -1.0, 2.0, 0.0])
+    m = np.zeros(4); v = np.zeros(4)
+    step = 0.02 * g / (np.abs(g) + 1e-8)
+    for t in range(1, 41):
+        q, m, v = oracle_lib.adam_step(p, g, m, v, t, lr=0.02)
+        assert np.allclose(p - q, step, rtol=1e-9, atol=0), t
+        assert np.allclose(m, (1.0 - 0.9 ** t) * g, rtol=1e-12, atol=0)
+        assert np.allclose(v, (1.0 - 0.999 ** t) * g * g, rtol=1e-12, atol=0)
+        p = q
+
+
+def test_adam_two_steps_worked_by_hand(oracle_lib):
+    # Hand-worked, beta1 = 0.9, beta2 = 0.999, lr = 0.1, p0 = 0, g1 = 2, g2 = 1:
+    #   t=1: m1 = 0.2, v1 = 0.004, mhat = 2, vhat = 4, p1 = -0.1 * 2 / (2 + eps)
+    #   t=2: m2 = 0.9*0.2 + 0.1*1 = 0.28, v2 = 0.999*0.004 + 0.001*1 = 0.004996,
+    #        mhat = 0.28 / 0.19 = 28/19, vhat = 0.004996 / 0.001999 = 4996/1999,
+    #        p2 = p1 - 0.1 * (28/19) / (sqrt(4996/1999) + eps)
+    #           = -0.0999999995 - 0.0932180... = -0.1932180...
+    # The second coordinate takes the negated gradients and must mirror the first.
+    eps = 1e-8
+    p1, m1, v1 = oracle_lib.adam_step(np.zeros(2), np.array([2.0, -2.0]), np.zeros(2), np.zeros(2), 1, lr=0.1)
+    assert abs(m1[0] - 0.2) < 1e-15 and abs(v1[0] - 0.004) < 1e-17
+    p2, m2, v2 = oracle_lib.adam_step(p1, np.array([1.0, -1.0]), m1, v1, 2, lr=0.1)
+    assert abs(m2[0] - 0.28) < 1e-15 and abs(v2[0] - 0.004996) < 1e-17
+    want = -0.1 * 2.0 / (2.0 + eps) - 0.1 * (28.0 / 19.0) / (np.sqrt(4996.0 / 1999.0) + eps)
+    assert abs(p2[0] - want) < 1e-14 and p2[1] == -p2[0] and m2[1] == -m2[0] and v2[1] == v2[0]
+    assert abs(p2[0] - (-0.1932180)) < 1e-7
+
+
 # ---------------------------------------------------------------------------
 # Producer/consumer phases (manual worksharing with barriers, Section 3.3)
 # ---------------------------------------------------------------------------
