@@ -85,6 +85,18 @@ def time_mode(ctx, gf, torch, prog, inst, mode, launch, steps, warmup):
     return (t1 - t0) * 1e3 / steps, sum(ev_ms) / len(ev_ms), stats
 
 
+def cpu_model() -> str:
+    """The host CPU's model name (what lscpu prints), from /proc/cpuinfo."""
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
 def cpu_baseline(u0, n, budget_s=15.0, max_sweeps=200, omp_budget_s=5.0):
     """The serial oracle on this host's cores (one thread) for a bounded
     number of sweeps of the same 512^3 workload; beside it, for context, the
@@ -95,20 +107,32 @@ def cpu_baseline(u0, n, budget_s=15.0, max_sweeps=200, omp_budget_s=5.0):
 
     u = u0.copy()
     w = u0.copy()
-    t0 = time.perf_counter()
-    oracle.jacobi3d_inplace(u, w, 1)
-    t1 = time.perf_counter() - t0
-    k = int(max(1, min(max_sweeps, budget_s / max(t1, 1e-3))))
-    t0 = time.perf_counter()
-    oracle.jacobi3d_inplace(u, w, k)
-    dt = time.perf_counter() - t0
+    # the serial oracle runs on one core: pin this thread to the first core it
+    # may use, and restore the mask for the OpenMP leg afterwards
+    mask = os.sched_getaffinity(0)
+    core = min(mask)
+    os.sched_setaffinity(0, {core})
+    try:
+        t0 = time.perf_counter()
+        oracle.jacobi3d_inplace(u, w, 1)
+        t1 = time.perf_counter() - t0
+        k = int(max(1, min(max_sweeps, budget_s / max(t1, 1e-3))))
+        t0 = time.perf_counter()
+        oracle.jacobi3d_inplace(u, w, k)
+        dt = time.perf_counter() - t0
+    finally:
+        os.sched_setaffinity(0, mask)
     cpu = {
         "value": round(k * alg_bytes_per_sweep(n) / dt / 1e9, 3),
         "unit": "GB/s",
         "cores": 1,
         "kind": "oracle",
-        "sample": f"{k} sweeps of the {n}^3 grid (after 1 timed warm-up sweep), serial C oracle, 1 thread",
+        "sample": f"{k} sweeps of the {n}^3 grid (after 1 timed warm-up sweep), serial C oracle, 1 thread "
+                  f"pinned to core {core}",
         "seconds": round(dt, 3),
+        "pinned_core": core,
+        "nproc": len(mask),
+        "cpu_model": cpu_model(),
     }
     threads = omp.max_threads()
     t0 = time.perf_counter()

@@ -41,6 +41,15 @@
  *  - gf_last_error(ctx) returns a message for the last failure on that ctx.
  *  - No C++ exception crosses the ABI. A ctx is not thread-safe, except that
  *    gf_rpc_poll may run concurrently on one server thread.
+ *  - Work enqueued through one ctx shares its device scratch (reduction
+ *    partials, counter lines, the batched-launch table, training buffers),
+ *    so a ctx orders its own enqueues across streams: a gf_region_run,
+ *    gf_reduce, gf_mlp_backward, gf_mlp_loss or gf_train_predictor call on a
+ *    stream other than the previous such call's first makes that stream
+ *    wait for the previous call's work. Work enqueued while the caller
+ *    captures the stream into a graph is not tracked; two captured graphs of
+ *    one ctx must not be replayed concurrently. Use one ctx per stream for
+ *    concurrent execution.
  */
 #ifndef GF_H
 #define GF_H

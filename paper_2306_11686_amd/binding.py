@@ -1,8 +1,11 @@
 """ctypes marshalling for libgf.so; names and layouts mirror include/gf.h."""
 from __future__ import annotations
 
+import atexit
 import ctypes
 import os
+import sys
+import weakref
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 _LIB_PATH = os.path.join(HERE, "libgf.so")
@@ -295,6 +298,21 @@ def exported_symbols():
     return sorted(_SIGS)
 
 
+# Contexts and heaps still open when the interpreter exits are closed by an
+# exit hook, before module teardown; a finalizer that runs later (during
+# interpreter finalization) makes no HIP call and leaks the handle instead.
+_LIVE = weakref.WeakSet()
+
+
+@atexit.register
+def _close_live_handles():
+    for obj in list(_LIVE):
+        try:
+            obj.close()
+        except Exception:
+            pass
+
+
 def tune_pick(ms) -> int:
     """Host-only argmin over finite timings (the library's gf_tune_pick)."""
     lib = load_library()
@@ -325,13 +343,18 @@ class Context:
             raise GfError(st, "gf_ctx_create failed")
         self.h = h
         self.device = device
+        _LIVE.add(self)
 
     def close(self):
-        if getattr(self, "h", None):
-            self.lib.gf_ctx_destroy(self.h)
-            self.h = None
+        """Destroy the context (waits for the device, joins the server
+        thread). Idempotent."""
+        h, self.h = getattr(self, "h", None), None
+        if h:
+            self.lib.gf_ctx_destroy(h)
 
     def __del__(self):
+        if sys.is_finalizing():
+            return
         try:
             self.close()
         except Exception:
@@ -494,13 +517,17 @@ class Heap:
         if st != GF_OK:
             raise GfError(st, "gf_heap_create failed")
         self.h = h
+        _LIVE.add(self)
 
     def close(self):
-        if getattr(self, "h", None):
-            self.lib.gf_heap_destroy(self.h)
-            self.h = None
+        """Destroy the heap. Idempotent."""
+        h, self.h = getattr(self, "h", None), None
+        if h:
+            self.lib.gf_heap_destroy(h)
 
     def __del__(self):
+        if sys.is_finalizing():
+            return
         try:
             self.close()
         except Exception:

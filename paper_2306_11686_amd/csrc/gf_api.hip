@@ -286,6 +286,12 @@ struct gf_ctx {
     hipEvent_t batch_copied = nullptr;
     bool batch_pending = false;
 
+    // Every enqueue shares the scratch above: work enqueued on a stream other
+    // than the previous call's waits for the previous call's work first
+    hipEvent_t last_done = nullptr;
+    hipStream_t last_stream = nullptr;
+    bool have_last = false;
+
     // predictor: device scratch for training, host copy for inference
     float *d_mlp = nullptr;       // gradient partials | grads | z1 | z2 | y | loss partials
     size_t d_mlp_floats = 0;
@@ -327,6 +333,37 @@ RpcRing ring_of(const gf_ctx *ctx)
     r.call_stats = ctx->d_call_stats;
     r.heap = ctx->heap;
     return r;
+}
+
+// Enqueues of one context are ordered even across streams, because they
+// share the context's scratch (reduction partials, counter lines, the
+// batched table, MLP buffers): before enqueueing on stream s, wait for the
+// work the previous call enqueued if that was on another stream; afterwards
+// mark the end of this call's work. Work enqueued while s is being captured
+// into a graph by the caller is not tracked (an event recorded inside a
+// capture cannot be waited on from outside it).
+bool capturing(hipStream_t s)
+{
+    hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+    return hipStreamIsCapturing(s, &cs) == hipSuccess && cs != hipStreamCaptureStatusNone;
+}
+
+gf_status order_before(gf_ctx *ctx, hipStream_t s)
+{
+    if (!ctx->have_last || s == ctx->last_stream || !ctx->last_done || capturing(s))
+        return GF_OK;
+    hipError_t e = hipStreamWaitEvent(s, ctx->last_done, 0);
+    return e == hipSuccess ? GF_OK : hipfail(ctx, e, "stream wait on the previous call");
+}
+
+void mark_after(gf_ctx *ctx, hipStream_t s)
+{
+    if (!ctx->last_done || capturing(s))
+        return;
+    if (hipEventRecord(ctx->last_done, s) == hipSuccess) {
+        ctx->last_stream = s;
+        ctx->have_last = true;
+    }
 }
 
 int64_t now_us()
@@ -435,6 +472,40 @@ int32_t poll_locked(gf_ctx *ctx, int32_t max_requests, int32_t timeout_us)
         break;
     }
     return done;
+}
+
+// After a device error, with no kernel of the device running: bring the
+// ring back to a state the next run can use. A client takes its ticket
+// before it waits for the slot to be freed; if that wait (or the wait for
+// the reply) gave up, the ticket was never published, or its caller never
+// freed the slot after copying back. Every request published in ticket order
+// is serviced as usual; a ticket that was taken but never published is
+// skipped (completed with return value -1, nothing run); finally each slot
+// is marked free for the last ticket that used it, so that clients of later
+// tickets do not wait for a caller that has gone.
+void recover_ring(gf_ctx *ctx)
+{
+    uint64_t taken = 0;
+    if (hipMemcpy(&taken, ctx->d_ticket, sizeof taken, hipMemcpyDeviceToHost) != hipSuccess)
+        return;
+    std::lock_guard<std::mutex> g(ctx->rpc_mu);
+    while (ctx->next_ticket < taken) {
+        if (poll_locked(ctx, 1 << 20, 0) > 0)
+            continue;
+        if (ctx->next_ticket >= taken)
+            break;
+        RpcSlot *slot = &ctx->h_slots[ctx->next_ticket & (ctx->nslots - 1)];
+        slot->ret = -1;
+        __atomic_store_n(&slot->freed, ctx->next_ticket + 1, __ATOMIC_RELAXED);
+        __atomic_store_n(&slot->done, ctx->next_ticket + 1, __ATOMIC_RELEASE);
+        ++ctx->next_ticket;
+    }
+    const uint64_t ns = ctx->nslots;
+    for (uint64_t t = taken > ns ? taken - ns : 0; t < taken; ++t) {
+        RpcSlot *slot = &ctx->h_slots[t & (ns - 1)];
+        if (__atomic_load_n(&slot->freed, __ATOMIC_RELAXED) < t + 1)
+            __atomic_store_n(&slot->freed, t + 1, __ATOMIC_RELEASE);
+    }
 }
 
 }  // namespace
@@ -547,7 +618,8 @@ gf_status gf_ctx_create(int32_t hip_device, const gf_ctx_opts *opts, gf_ctx **ou
         ctx->split_stream = nullptr;
     if (hipMalloc(&ctx->d_batch, kBatchBytes) != hipSuccess ||
         hipHostMalloc(&ctx->h_batch, kBatchBytes, hipHostMallocDefault) != hipSuccess ||
-        hipEventCreateWithFlags(&ctx->batch_copied, hipEventDisableTiming) != hipSuccess) {
+        hipEventCreateWithFlags(&ctx->batch_copied, hipEventDisableTiming) != hipSuccess ||
+        hipEventCreateWithFlags(&ctx->last_done, hipEventDisableTiming) != hipSuccess) {
         gf_ctx_destroy(ctx);
         return GF_ENOMEM;
     }
@@ -600,6 +672,8 @@ gf_status gf_ctx_destroy(gf_ctx *ctx)
         hipStreamDestroy(ctx->split_stream);
     if (ctx->batch_copied)
         hipEventDestroy(ctx->batch_copied);
+    if (ctx->last_done)
+        hipEventDestroy(ctx->last_done);
     if (ctx->h_batch)
         hipHostFree(ctx->h_batch);
     if (ctx->d_batch)
@@ -1621,11 +1695,28 @@ int32_t gf_persistent_capacity(gf_ctx *ctx, const gf_program *prog, int32_t wg_s
     return persistent_capacity(p, t, ctx->num_cu);
 }
 
+static gf_status region_run(gf_ctx *ctx, const gf_program *prog, const gf_instance *inst, int32_t n_inst,
+                            int32_t mode, const gf_launch *launch, gf_run_stats *stats, void *hip_stream);
+
 gf_status gf_region_run(gf_ctx *ctx, const gf_program *prog, const gf_instance *inst, int32_t n_inst, int32_t mode,
                         const gf_launch *launch, gf_run_stats *stats, void *hip_stream)
 {
     if (!ctx)
         return GF_EINVAL;
+    hipSetDevice(ctx->device);
+    hipStream_t s = (hipStream_t)hip_stream;
+    gf_status st = order_before(ctx, s);
+    if (st != GF_OK)
+        return st;
+    st = region_run(ctx, prog, inst, n_inst, mode, launch, stats, hip_stream);
+    if (st == GF_OK)
+        mark_after(ctx, s);
+    return st;
+}
+
+static gf_status region_run(gf_ctx *ctx, const gf_program *prog, const gf_instance *inst, int32_t n_inst,
+                            int32_t mode, const gf_launch *launch, gf_run_stats *stats, void *hip_stream)
+{
     if (!inst || n_inst < 1 || n_inst > GF_MAX_INSTANCES)
         return fail(ctx, GF_EINVAL, "need 1..%d instances", GF_MAX_INSTANCES);
     if (mode != GF_EXEC_PER_REGION && mode != GF_EXEC_PERSISTENT && mode != GF_EXEC_PER_REGION_GRAPH &&
@@ -1779,9 +1870,14 @@ gf_status gf_reduce(gf_ctx *ctx, int32_t op, int32_t dt, const void *d_in, int64
     if (n < 0 || (n > 0 && !d_in) || !d_out)
         return fail(ctx, GF_EINVAL, "bad reduction arguments");
     hipSetDevice(ctx->device);
-    hipError_t e = launch_reduce(op, dt, d_in, n, d_out, ctx->scr, ctx->num_cu, (hipStream_t)hip_stream);
+    hipStream_t s = (hipStream_t)hip_stream;
+    gf_status st = order_before(ctx, s);
+    if (st != GF_OK)
+        return st;
+    hipError_t e = launch_reduce(op, dt, d_in, n, d_out, ctx->scr, ctx->num_cu, s);
     if (e != hipSuccess)
         return hipfail(ctx, e, "reduce launch");
+    mark_after(ctx, s);
     return GF_OK;
 }
 
@@ -1818,7 +1914,11 @@ gf_status gf_sync(gf_ctx *ctx, void *hip_stream, gf_run_stats *stats)
         return hipfail(ctx, e, "error word read");
     if (code != kErrNone) {
         // a kernel that stopped on the error may have left barrier counters
-        // mid-count: clear every counter line with the error word
+        // mid-count: clear every counter line with the error word; a caller
+        // that gave up on an RPC slot may have left the ring mid-ticket:
+        // re-synchronise it (both once no kernel of the device still runs)
+        hipDeviceSynchronize();
+        recover_ring(ctx);
         const int32_t zero = 0;
         hipMemset(ctx->scr.lines, 0, (size_t)kNumLines * kLineWords * sizeof(uint32_t));
         hipMemcpy(ctx->scr.error, &zero, sizeof zero, hipMemcpyHostToDevice);
@@ -2164,12 +2264,17 @@ gf_status gf_mlp_backward(gf_ctx *ctx, const float *d_params, const float *d_fea
         batch > kMaxMlpBatch)
         return fail(ctx, GF_EINVAL, "bad MLP backward arguments");
     hipSetDevice(ctx->device);
-    gf_status st = mlp_scratch(ctx, mlp_part_floats(batch));
+    gf_status st = order_before(ctx, (hipStream_t)hip_stream);
+    if (st == GF_OK)
+        st = mlp_scratch(ctx, mlp_part_floats(batch));
     if (st != GF_OK)
         return st;
     hipError_t e = launch_mlp_backward(d_params, d_feats, d_z1, d_z2, d_y, d_target, d_mask, batch, inv_norm,
                                        ctx->d_mlp, d_grads, (hipStream_t)hip_stream);
-    return e == hipSuccess ? GF_OK : hipfail(ctx, e, "MLP backward");
+    if (e != hipSuccess)
+        return hipfail(ctx, e, "MLP backward");
+    mark_after(ctx, (hipStream_t)hip_stream);
+    return GF_OK;
 }
 
 gf_status gf_mlp_loss(gf_ctx *ctx, const float *d_y, const float *d_target, const float *d_mask, int64_t count,
@@ -2180,12 +2285,17 @@ gf_status gf_mlp_loss(gf_ctx *ctx, const float *d_y, const float *d_target, cons
     if (!d_y || !d_target || !d_mask || !d_loss || count < 0)
         return fail(ctx, GF_EINVAL, "bad MLP loss arguments");
     hipSetDevice(ctx->device);
-    gf_status st = mlp_scratch(ctx, 64);
+    gf_status st = order_before(ctx, (hipStream_t)hip_stream);
+    if (st == GF_OK)
+        st = mlp_scratch(ctx, 64);
     if (st != GF_OK)
         return st;
     hipError_t e = launch_mlp_loss(d_y, d_target, d_mask, count, inv_norm, ctx->d_mlp, d_loss,
                                    (hipStream_t)hip_stream);
-    return e == hipSuccess ? GF_OK : hipfail(ctx, e, "MLP loss");
+    if (e != hipSuccess)
+        return hipfail(ctx, e, "MLP loss");
+    mark_after(ctx, (hipStream_t)hip_stream);
+    return GF_OK;
 }
 
 gf_status gf_adam_step(gf_ctx *ctx, float *d_params, const float *d_grads, float *d_m, float *d_v, int32_t n,
@@ -2213,7 +2323,9 @@ gf_status gf_train_predictor(gf_ctx *ctx, float *d_params, float *d_m, float *d_
     // scratch: gradient partials | grads | z1 | z2 | y | loss partials
     const size_t part = mlp_part_floats(batch);
     const size_t zsz = (size_t)batch * GF_MLP_HIDDEN, ysz = (size_t)batch * GF_MLP_OUT;
-    gf_status st = mlp_scratch(ctx, part + GF_MLP_NPARAMS + 2 * zsz + ysz + 64);
+    gf_status st = order_before(ctx, (hipStream_t)hip_stream);
+    if (st == GF_OK)
+        st = mlp_scratch(ctx, part + GF_MLP_NPARAMS + 2 * zsz + ysz + 64);
     if (st != GF_OK)
         return st;
     float *dpart = ctx->d_mlp, *dg = dpart + part, *z1 = dg + GF_MLP_NPARAMS, *z2 = z1 + zsz, *y = z2 + zsz,
@@ -2230,6 +2342,7 @@ gf_status gf_train_predictor(gf_ctx *ctx, float *d_params, float *d_m, float *d_
         if (r != hipSuccess)
             return hipfail(ctx, r, "training step");
     }
+    mark_after(ctx, s);
     return GF_OK;
 }
 

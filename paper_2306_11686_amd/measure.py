@@ -73,7 +73,8 @@ def measure_cg(ctx, gf, programs, tuner, torch, reps):
     N = m ** 3
     nnz = (3 * m - 2) ** 3
     spmv_b = 12 * nnz + 4 * (N + 1) + 8 * N + 8 * N
-    it_b = spmv_b + 2 * 16 * N + 3 * 24 * N
+    # dot(p, q) reads two vectors, dot(r, r) one; each axpby reads two and writes one
+    it_b = spmv_b + 16 * N + 8 * N + 3 * 24 * N
     out = {"config": f"cg_27pt_{m}^3_f64_{iters}iters", "rows": N, "nnz": nnz, "alg_bytes_per_iteration": it_b}
     launch = _launch(tuner, "cg_128")
     for name, mode in MODES:
