@@ -247,8 +247,15 @@ typedef struct {
     int32_t wg_size;
     int32_t rpc_posted;    /* filled by gf_sync: RPC requests serviced so far */
     int32_t candidate;     /* gf_region_run with launch NULL: the launch shape the
-                              installed predictor chose (0..31), -1 if none */
+                              installed predictor or its autotuner fallback chose
+                              (0..31), -1 if none */
+    int32_t launch_source; /* where the launch shape came from: GF_LAUNCH_* */
 } gf_run_stats;
+
+#define GF_LAUNCH_GIVEN 0        /* the caller's launch, or the defaults */
+#define GF_LAUNCH_PREDICTED 1    /* the installed predictor's choice */
+#define GF_LAUNCH_TUNED 2        /* the autotuner, timed during this call (predictor deferred) */
+#define GF_LAUNCH_TUNED_CACHED 3 /* the autotuner's earlier choice for this program, sizes and mode */
 
 typedef struct {
     int32_t rpc_slots;        /* ring slots (power of two, 8..4096); 0 = 256 */
@@ -261,6 +268,10 @@ typedef struct {
     int64_t rpc_payload;      /* payload bytes per ring slot for the objects of
                                  GF_S_CALL references (multiple of 16, 16..65536);
                                  0 = 1024 */
+    int32_t tune_fallback;    /* gf_region_run with launch NULL when the installed
+                                 predictor defers: 0 = run the autotuner (on copies of
+                                 the instances' data) and cache its choice; -1 = use
+                                 the default launch */
 } gf_ctx_opts;
 
 /* Create a context on HIP device `hip_device`: allocates the pinned RPC ring
@@ -277,9 +288,15 @@ const char *gf_last_error(const gf_ctx *ctx);
  * hip_stream in execution mode `mode`. With n_inst > 1 the instances run
  * concurrently in one persistent launch, each on its own group of
  * workgroups with group barriers (GF_EXEC_PERSISTENT), or as per-instance
- * launches (per-region modes). launch may be NULL: with one instance and an
- * installed predictor the predicted launch shape is used (gf_predict_launch;
- * for SpMV programs that call waits for hip_stream), otherwise the defaults.
+ * launches (per-region modes). launch may be NULL: with an installed
+ * predictor the predicted launch shape is used (gf_predict_launch; for SpMV
+ * programs that call waits for hip_stream); when the predictor defers (the
+ * program lies outside its training distribution, e.g. several instances)
+ * the autotuner decides: every candidate shape is timed on copies of the
+ * instances' arrays and scalars (allocated for the call and freed; the
+ * program's printf and host-call steps left out), the fastest is used and
+ * cached in the ctx for this program, sizes and mode (opts.tune_fallback).
+ * Without a predictor, or with the fallback off, the defaults are used.
  * stats (nullable) receives counts. Asynchronous: results are valid after
  * the stream completes; call gf_sync to surface device errors. */
 gf_status gf_region_run(gf_ctx *ctx, const gf_program *prog, const gf_instance *inst,
@@ -288,8 +305,8 @@ gf_status gf_region_run(gf_ctx *ctx, const gf_program *prog, const gf_instance *
 
 /* A single reduction region over a device array: d_out[0] = op over
  * d_in[0..n) (SUM: + ; MAX: max, F64 max starts from -infinity, unsigned
- * from 0, I64 from INT64_MIN). U32 sums are widened: d_out is u64 for
- * GF_U32/SUM and of type dt otherwise. F64 sums use a fixed two-pass tree
+ * from 0, I64 from INT64_MIN). U32 inputs are widened: d_out is a u64 for
+ * GF_U32 (sum and max) and of type dt otherwise. F64 sums use a fixed two-pass tree
  * (deterministic for a given n). n may be 0 (identity). */
 gf_status gf_reduce(gf_ctx *ctx, int32_t op, int32_t dt, const void *d_in, int64_t n,
                     void *d_out, void *hip_stream);

@@ -13,7 +13,8 @@ from .binding import (  # noqa: F401
     GF_OP_SUM, GF_OP_MAX, GF_OP_NONE, GF_F64, GF_U32, GF_U64, GF_I64,
     GF_R_JACOBI2D, GF_R_JACOBI3D, GF_R_SPMV, GF_R_DOT, GF_R_AXPBY, GF_R_HIST, GF_R_OWNER, GF_R_PHASES,
     GF_S_SET, GF_S_COPY, GF_S_DIV, GF_S_SQRT, GF_S_SWAP, GF_S_RECORD, GF_S_PRINTF, GF_S_CALL,
-    GF_STEP_BLOCKING, GF_STEP_TIMED, GF_STEP_NOWAIT, GF_NUM_CANDIDATES, GF_MLP_IN, GF_MLP_HIDDEN, GF_MLP_OUT, GF_MLP_NPARAMS,
+    GF_STEP_BLOCKING, GF_STEP_TIMED, GF_STEP_NOWAIT, GF_LAUNCH_GIVEN, GF_LAUNCH_PREDICTED, GF_LAUNCH_TUNED,
+    GF_LAUNCH_TUNED_CACHED, GF_NUM_CANDIDATES, GF_MLP_IN, GF_MLP_HIDDEN, GF_MLP_OUT, GF_MLP_NPARAMS,
     GF_CALLEE_FPRINTF, GF_CALLEE_SNPRINTF, GF_CALLEE_SSCANF, GF_CALLEE_FWRITE, GF_CALLEE_FREAD,
     GF_ARG_CONST, GF_ARG_SCALAR, GF_ARG_ITER, GF_ARG_REF, GF_ARG_HEAPREF, GF_REF_READ, GF_REF_WRITE, GF_REF_READWRITE,
     GF_CALL_MAX_ARGS, GF_CALL_MAX_REFS, GF_CALL_MAX_SITES,

@@ -23,6 +23,7 @@ GF_R_JACOBI2D, GF_R_JACOBI3D, GF_R_SPMV, GF_R_DOT, GF_R_AXPBY, GF_R_HIST, GF_R_O
 GF_S_SET, GF_S_COPY, GF_S_DIV, GF_S_SQRT, GF_S_SWAP, GF_S_RECORD, GF_S_PRINTF, GF_S_CALL = \
     32, 33, 34, 35, 36, 37, 38, 39
 GF_STEP_BLOCKING, GF_STEP_TIMED, GF_STEP_NOWAIT = 1, 2, 4
+GF_LAUNCH_GIVEN, GF_LAUNCH_PREDICTED, GF_LAUNCH_TUNED, GF_LAUNCH_TUNED_CACHED = 0, 1, 2, 3
 
 GF_CALLEE_FPRINTF, GF_CALLEE_SNPRINTF, GF_CALLEE_SSCANF, GF_CALLEE_FWRITE, GF_CALLEE_FREAD = 1, 2, 3, 4, 5
 GF_ARG_CONST, GF_ARG_SCALAR, GF_ARG_ITER, GF_ARG_REF, GF_ARG_HEAPREF = 0, 1, 2, 3, 4
@@ -106,7 +107,7 @@ class Launch(ctypes.Structure):
 class RunStats(ctypes.Structure):
     _fields_ = [("regions", ctypes.c_int32), ("launches", ctypes.c_int32), ("barriers", ctypes.c_int32),
                 ("num_wg", ctypes.c_int32), ("wg_size", ctypes.c_int32), ("rpc_posted", ctypes.c_int32),
-                ("candidate", ctypes.c_int32)]
+                ("candidate", ctypes.c_int32), ("launch_source", ctypes.c_int32)]
 
     def as_dict(self):
         return {f: getattr(self, f) for f, _ in self._fields_}
@@ -115,7 +116,7 @@ class RunStats(ctypes.Structure):
 class CtxOpts(ctypes.Structure):
     _fields_ = [("rpc_slots", ctypes.c_int32), ("rpc_capture", ctypes.c_int32), ("rpc_thread", ctypes.c_int32),
                 ("rpc_timeout_us", ctypes.c_int64), ("barrier_timeout_us", ctypes.c_int64),
-                ("rpc_payload", ctypes.c_int64)]
+                ("rpc_payload", ctypes.c_int64), ("tune_fallback", ctypes.c_int32)]
 
 
 class CallArg(ctypes.Structure):
@@ -333,10 +334,11 @@ class Context:
     """One libgf context on a HIP device."""
 
     def __init__(self, device: int = 0, rpc_slots: int = 0, rpc_capture: bool = False, rpc_thread: bool = False,
-                 rpc_timeout_us: int = 0, barrier_timeout_us: int = 0, rpc_payload: int = 0):
+                 rpc_timeout_us: int = 0, barrier_timeout_us: int = 0, rpc_payload: int = 0,
+                 tune_fallback: bool = True):
         self.lib = load_library()
         opts = CtxOpts(rpc_slots, 1 if rpc_capture else 0, 1 if rpc_thread else 0, rpc_timeout_us,
-                       barrier_timeout_us, rpc_payload)
+                       barrier_timeout_us, rpc_payload, 0 if tune_fallback else -1)
         h = ctypes.c_void_p()
         st = self.lib.gf_ctx_create(device, ctypes.byref(opts), ctypes.byref(h))
         if st != GF_OK:

@@ -292,6 +292,15 @@ struct gf_ctx {
     hipStream_t last_stream = nullptr;
     bool have_last = false;
 
+    // launches the autotuner chose when the predictor deferred, by program,
+    // sizes, instance count and mode
+    bool tune_fallback = true;
+    struct Tuned {
+        gf_launch launch;
+        int32_t cand;
+    };
+    std::unordered_map<std::string, Tuned> tuned;
+
     // predictor: device scratch for training, host copy for inference
     float *d_mlp = nullptr;       // gradient partials | grads | z1 | z2 | y | loss partials
     size_t d_mlp_floats = 0;
@@ -611,6 +620,7 @@ gf_status gf_ctx_create(int32_t hip_device, const gf_ctx_opts *opts, gf_ctx **ou
         return GF_EHIP;
     }
     ctx->rpc_timeout_us = o.rpc_timeout_us > 0 ? o.rpc_timeout_us : 2 * 1000 * 1000;
+    ctx->tune_fallback = o.tune_fallback >= 0;
     ctx->capture = o.rpc_capture != 0;
     if (hipStreamCreateWithFlags(&ctx->capture_stream, hipStreamNonBlocking) != hipSuccess)
         ctx->capture_stream = nullptr;
@@ -1600,12 +1610,18 @@ int32_t predict_launch(gf_ctx *ctx, const DProg &p, const gf_instance *inst, int
 struct CandidateNote {
     gf_run_stats *stats;
     int32_t cand;
+    int32_t source = GF_LAUNCH_GIVEN;
     ~CandidateNote()
     {
-        if (stats)
+        if (stats) {
             stats->candidate = cand;
+            stats->launch_source = source;
+        }
     }
 };
+
+int32_t tune_fallback(gf_ctx *ctx, const gf_program *prog, const DProg &p, const gf_instance *inst, int n_inst,
+                      int mode, hipStream_t s, gf_launch *out, bool *cached);
 }  // namespace
 
 // Kernel split: the main kernel (one thread) runs on `stream`; its region
@@ -1730,13 +1746,26 @@ static gf_status region_run(gf_ctx *ctx, const gf_program *prog, const gf_instan
     hipStream_t stream = (hipStream_t)hip_stream;
     gf_launch predicted;
     CandidateNote note{stats, -1};
-    if (!launch && n_inst == 1 && !ctx->pred_params.empty()) {
-        const int32_t k = predict_launch(ctx, p, inst, n_inst, mode, stream, &predicted);
+    if (!launch && !ctx->pred_params.empty()) {
+        int32_t k = predict_launch(ctx, p, inst, n_inst, mode, stream, &predicted);
         if (k < -1)
             return (gf_status)k;
         if (k >= 0) {
             note.cand = k;
+            note.source = GF_LAUNCH_PREDICTED;
             launch = &predicted;
+        } else if (ctx->tune_fallback && mode != GF_EXEC_KERNEL_SPLIT) {
+            // the predictor defers (outside its training distribution, or
+            // no runnable shape it knows): the autotuner decides
+            bool cached = false;
+            k = tune_fallback(ctx, prog, p, inst, n_inst, mode, stream, &predicted, &cached);
+            if (k < -1)
+                return (gf_status)k;
+            if (k >= 0) {
+                note.cand = k;
+                note.source = cached ? GF_LAUNCH_TUNED_CACHED : GF_LAUNCH_TUNED;
+                launch = &predicted;
+            }
         }
     }
     Tiling t = choose_tiling(p, launch);
@@ -2093,6 +2122,169 @@ int32_t predict_launch(gf_ctx *ctx, const DProg &p, const gf_instance *inst, int
     if (k >= 0)
         *out = cand[k];
     return k;
+}
+
+// Bytes of each array slot that the program's regions and records touch in
+// instance `in` (0: unused). SpMV's column and value arrays take their
+// length from the row pointer's last entry, read from the device on s.
+gf_status slot_bytes(gf_ctx *ctx, const DProg &p, const gf_instance &in, hipStream_t s, int64_t *bytes)
+{
+    for (int k = 0; k < GF_MAX_ARRAYS; ++k)
+        bytes[k] = 0;
+    auto need = [&](int slot, int64_t b) {
+        if (slot >= 0 && slot < GF_MAX_ARRAYS)
+            bytes[slot] = std::max(bytes[slot], b);
+    };
+    for (int i = 0; i < p.n_steps; ++i) {
+        const DStep &st = p.steps[i];
+        const int64_t n = is_region(st.kind) ? in.ip[st.np] : 0;
+        switch (st.kind) {
+        case GF_R_JACOBI2D:
+            need(st.arr[0], 8 * n * n), need(st.arr[1], 8 * n * n);
+            break;
+        case GF_R_JACOBI3D:
+            need(st.arr[0], 8 * n * n * n), need(st.arr[1], 8 * n * n * n);
+            break;
+        case GF_R_SPMV: {
+            int32_t nnz = 0;
+            if (n > 0) {
+                hipError_t e = hipMemcpyAsync(&nnz, (const int32_t *)in.arr[st.arr[0]] + n, sizeof nnz,
+                                              hipMemcpyDeviceToHost, s);
+                if (e == hipSuccess)
+                    e = hipStreamSynchronize(s);
+                if (e != hipSuccess)
+                    return hipfail(ctx, e, "reading the row pointer");
+            }
+            need(st.arr[0], 4 * (n + 1)), need(st.arr[1], 4 * (int64_t)nnz), need(st.arr[2], 8 * (int64_t)nnz);
+            need(st.arr[3], 8 * n), need(st.arr[4], 8 * n);
+            break;
+        }
+        case GF_R_DOT:
+            need(st.arr[0], 8 * n), need(st.arr[1], 8 * n);
+            break;
+        case GF_R_AXPBY:
+            need(st.arr[0], 8 * n), need(st.arr[1], 8 * n), need(st.arr[2], 8 * n);
+            break;
+        case GF_R_HIST:
+            need(st.arr[0], (4 * n + 15) / 16 * 16), need(st.arr[1], 4 * ((int64_t)st.mask + 1));
+            break;
+        case GF_R_OWNER:
+            need(st.arr[0], 4 * n);
+            break;
+        case GF_R_PHASES:
+            need(st.arr[0], 8 * n), need(st.arr[1], 8 * n), need(st.arr[2], 4 * n);
+            break;
+        case GF_S_RECORD:
+            need(st.arr[0], 8 * std::max<int64_t>(1, p.iters));
+            break;
+        default:
+            break;
+        }
+    }
+    // swapped slots hold buffers of the same size
+    for (int round = 0; round < 2; ++round)
+        for (int i = 0; i < p.n_steps; ++i)
+            if (p.steps[i].kind == GF_S_SWAP) {
+                const int a = p.steps[i].arr[0], b = p.steps[i].arr[1];
+                need(a, bytes[b]), need(b, bytes[a]);
+            }
+    return GF_OK;
+}
+
+std::string fallback_key(const DProg &p, const gf_instance *inst, int n_inst, int mode)
+{
+    std::string k;
+    k.append((const char *)p.steps, sizeof(DStep) * (size_t)p.n_steps);
+    k.append((const char *)&p.n_pro, sizeof p.n_pro);
+    k.append((const char *)&p.iters, sizeof p.iters);
+    k.append((const char *)&mode, sizeof mode);
+    for (int i = 0; i < n_inst; ++i)
+        k.append((const char *)inst[i].ip, sizeof inst[i].ip);
+    return k;
+}
+
+// The autotuner as the predictor's fallback: time every candidate shape on
+// copies of the instances' arrays and scalars (the caller's data is only
+// read), with the program's host calls and printfs left out (they do not
+// depend on the launch shape and must not run more than once), pick the
+// fastest and remember it for this program, sizes and mode. Per-region
+// graph runs are tuned as per-region launches. Returns the candidate index,
+// -1 if none could run, or a negative gf_status below -1 on failure.
+int32_t tune_fallback(gf_ctx *ctx, const gf_program *prog, const DProg &p, const gf_instance *inst, int n_inst,
+                      int mode, hipStream_t s, gf_launch *out, bool *cached)
+{
+    const std::string key = fallback_key(p, inst, n_inst, mode);
+    auto hit = ctx->tuned.find(key);
+    if (hit != ctx->tuned.end()) {
+        *out = hit->second.launch;
+        *cached = true;
+        return hit->second.cand;
+    }
+    std::vector<gf_step> pro, body;
+    for (int32_t i = 0; i < prog->n_prologue; ++i)
+        if (prog->prologue[i].kind != GF_S_PRINTF && prog->prologue[i].kind != GF_S_CALL)
+            pro.push_back(prog->prologue[i]);
+    for (int32_t i = 0; i < prog->n_body; ++i)
+        if (prog->body[i].kind != GF_S_PRINTF && prog->body[i].kind != GF_S_CALL)
+            body.push_back(prog->body[i]);
+    gf_program tp{(int32_t)pro.size(), pro.data(), (int32_t)body.size(), body.data(), prog->iters};
+    // one device block per instance: its arrays (256-byte aligned) and scalars
+    std::vector<gf_instance> tinst(inst, inst + n_inst);
+    std::vector<void *> blocks(n_inst, nullptr);
+    gf_status st = GF_OK;
+    for (int i = 0; i < n_inst && st == GF_OK; ++i) {
+        int64_t b[GF_MAX_ARRAYS];
+        if ((st = slot_bytes(ctx, p, inst[i], s, b)) != GF_OK)
+            break;
+        int64_t total = 256 * (int64_t)(GF_MAX_SCALARS * sizeof(double) / 256 + 1);
+        for (int k = 0; k < GF_MAX_ARRAYS; ++k)
+            total += (b[k] + 255) / 256 * 256;
+        if (hipMalloc(&blocks[i], (size_t)total) != hipSuccess) {
+            st = fail(ctx, GF_ENOMEM, "autotuner fallback: copies of instance %d (%lld bytes)", i, (long long)total);
+            break;
+        }
+        char *q = (char *)blocks[i];
+        hipError_t e = hipMemcpyAsync(q, inst[i].scal, GF_MAX_SCALARS * sizeof(double), hipMemcpyDeviceToDevice, s);
+        tinst[i].scal = (double *)q;
+        q += 256 * (int64_t)(GF_MAX_SCALARS * sizeof(double) / 256 + 1);
+        for (int k = 0; k < GF_MAX_ARRAYS && e == hipSuccess; ++k) {
+            if (b[k] == 0 || !inst[i].arr[k]) {
+                tinst[i].arr[k] = b[k] == 0 ? inst[i].arr[k] : nullptr;
+                continue;
+            }
+            e = hipMemcpyAsync(q, inst[i].arr[k], (size_t)b[k], hipMemcpyDeviceToDevice, s);
+            tinst[i].arr[k] = q;
+            q += (b[k] + 255) / 256 * 256;
+        }
+        if (e != hipSuccess)
+            st = hipfail(ctx, e, "autotuner fallback: copying the instance");
+    }
+    int32_t best = -1;
+    if (st == GF_OK) {
+        gf_launch cand[GF_NUM_CANDIDATES];
+        float ms[GF_NUM_CANDIDATES];
+        const int32_t nc = gf_tune_candidates(ctx, &tp, tinst.data(), cand);
+        const int tmode = mode == GF_EXEC_PER_REGION_GRAPH ? GF_EXEC_PER_REGION : mode;
+        if (nc < 0) {
+            st = (gf_status)nc;
+        } else {
+            const int32_t ran = gf_tune(ctx, &tp, tinst.data(), n_inst, tmode, cand, nc, 3, ms, &best, s);
+            if (ran < 0)
+                st = (gf_status)ran;
+            else if (best >= 0) {
+                *out = cand[best];
+                ctx->tuned[key] = {cand[best], best};
+            }
+        }
+    }
+    hipStreamSynchronize(s);
+    for (void *b : blocks)
+        if (b)
+            hipFree(b);
+    if (st != GF_OK)
+        return st < -1 ? st : GF_EHIP;
+    *cached = false;
+    return best;
 }
 
 }  // namespace

@@ -31,6 +31,21 @@ struct RedOp<GF_OP_MAX> {
 };
 
 __device__ __forceinline__ double red_identity(int op) { return op == GF_OP_MAX ? -INFINITY : 0.0; }
+
+// Order-preserving map of doubles to unsigned 64-bit keys (negative values
+// have every bit flipped, non-negative ones the sign bit set), so an
+// unsigned atomic max over keys is the max over the doubles: exact, and the
+// same bits in any order of arrival (NaN-free inputs; -0 sorts below +0).
+__device__ __forceinline__ uint64_t max_key(double d)
+{
+    const uint64_t b = (uint64_t)__double_as_longlong(d);
+    return (b >> 63) ? ~b : (b | 0x8000000000000000ull);
+}
+__device__ __forceinline__ double max_unkey(uint64_t k)
+{
+    return __longlong_as_double((long long)((k >> 63) ? (k & 0x7FFFFFFFFFFFFFFFull) : ~k));
+}
+constexpr uint64_t kMaxKeyIdentity = 0x000FFFFFFFFFFFFFull;  // max_key(-infinity)
 __device__ __forceinline__ double red_apply(int op, double a, double b)
 {
     return op == GF_OP_MAX ? (a > b ? a : b) : a + b;
@@ -353,8 +368,11 @@ __device__ __forceinline__ bool wait_equal(uint32_t *w, uint32_t want, int32_t *
     return true;
 }
 
+// reset (nullable): a 64-bit word the last arrival sets to kMaxKeyIdentity
+// before it releases the others -- every workgroup has then arrived, so none
+// still reads it, and none writes it again before the release.
 __device__ __forceinline__ bool xcd_barrier(uint32_t *lines, const XcdState &xs, BarrierState *bs, int32_t *err,
-                                            int64_t timeout_ticks)
+                                            int64_t timeout_ticks, uint64_t *reset = nullptr)
 {
     __builtin_amdgcn_s_waitcnt(0x0F70);  // vmcnt(0): this wavefront's stores are in the XCD's L2
     __syncthreads();
@@ -372,6 +390,8 @@ __device__ __forceinline__ bool xcd_barrier(uint32_t *lines, const XcdState &xs,
             const uint32_t b = __hip_atomic_fetch_add(top, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
             if (b == xs.nx - 1) {
                 __hip_atomic_store(top, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                if (reset)
+                    __hip_atomic_store(reset, kMaxKeyIdentity, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
                 __builtin_amdgcn_s_waitcnt(0x0F70);
                 __hip_atomic_store(genw, g + 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
             } else {

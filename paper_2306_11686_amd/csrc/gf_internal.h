@@ -196,7 +196,11 @@ constexpr int kXcdCntLine0 = kXcdRegLine0 + kNumXcd;
 constexpr int kXcdTopLine = kXcdCntLine0 + kNumXcd;
 constexpr int kXcdBadLine = kXcdTopLine + 1;
 constexpr int kFinalizeSubLine0 = kXcdBadLine + 1;
-constexpr int kNumLines = kFinalizeSubLine0 + GF_MAX_INSTANCES * kNumXcd;
+// Two 64-bit slots (one line each) into which the persistent kernel's
+// workgroups fold a MAX reduction with one atomic each; regions alternate
+// between them.
+constexpr int kMaxSlotLine0 = kFinalizeSubLine0 + GF_MAX_INSTANCES * kNumXcd;
+constexpr int kNumLines = kMaxSlotLine0 + 2;
 
 // A serial step attached to a per-region launch, with its array operand
 // resolved on the host (SWAPs are applied by the host while it walks the
@@ -251,6 +255,10 @@ hipError_t launch_region(const RegionLaunch &rl, const Tiling &t, int num_wg, co
                          const RpcRing &rpc, hipStream_t s);
 hipError_t launch_reduce(int op, int dt, const void *in, int64_t n, void *out, const Scratch &scr,
                          int num_cu, hipStream_t s);
+int64_t reduce_grid(int64_t n, int num_cu, int64_t max_wg);
+hipError_t launch_reduce_into(int op, int dt, const void *in, int64_t n, void *out, void *part, uint32_t *cnt,
+                              int64_t g, hipStream_t s);
+hipError_t launch_clear_u32(uint32_t *p, int32_t n, hipStream_t s);
 hipError_t launch_copy(void *dst, const void *src, int64_t nbytes, int num_wg, hipStream_t s);
 
 // Number of work items (tiles / chunks) a region splits into under tiling t.

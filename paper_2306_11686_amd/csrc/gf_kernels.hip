@@ -1154,7 +1154,11 @@ __global__ void __launch_bounds__(family_max_threads<KMASK>())
     uint32_t *genw = batched ? gline + 1 : scr.lines + 1;  // generation word
     uint32_t *tree = scr.lines + kTreeLine0 * kLineWords;
     const bool xmode = !batched && scr.barrier_kind == kBarrierXcd && G >= kXcdBarrierMinWg;
-    auto barrier = [&]() -> bool {
+    // MAX reductions under the XCD barrier fold into two 64-bit slots (one
+    // atomic max per workgroup instead of a partial per work item that every
+    // workgroup reads back after the barrier)
+    uint64_t *max_slot = (uint64_t *)(scr.lines + (int64_t)kMaxSlotLine0 * kLineWords);
+    auto barrier = [&](uint64_t *reset = nullptr) -> bool {
         if (G == 1) {
             // a group of one workgroup: a workgroup-scope barrier suffices
             __builtin_amdgcn_s_waitcnt(0x0F70);
@@ -1164,7 +1168,7 @@ __global__ void __launch_bounds__(family_max_threads<KMASK>())
         if (batched)
             return flat_barrier(gline, (uint32_t)G, &s_bar, scr.error, scr.barrier_timeout_ticks);
         if (xmode && s_xcd.use)
-            return xcd_barrier(scr.lines, s_xcd, &s_bar, scr.error, scr.barrier_timeout_ticks);
+            return xcd_barrier(scr.lines, s_xcd, &s_bar, scr.error, scr.barrier_timeout_ticks, reset);
         return tree_barrier(genw, tree, (uint32_t)member, (uint32_t)G, &s_bar, scr.error, scr.barrier_timeout_ticks);
     };
     if (threadIdx.x < GF_MAX_SCALARS)
@@ -1182,6 +1186,11 @@ __global__ void __launch_bounds__(family_max_threads<KMASK>())
     }
     __syncthreads();
     if (xmode) {
+        if (member == 0 && threadIdx.x == 0) {
+            __hip_atomic_store(max_slot, kMaxKeyIdentity, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            __hip_atomic_store(max_slot + kLineWords / 2, kMaxKeyIdentity, __ATOMIC_RELAXED,
+                               __HIP_MEMORY_SCOPE_AGENT);
+        }
         if (!tree_barrier(genw, tree, (uint32_t)member, (uint32_t)G, &s_bar, scr.error, scr.barrier_timeout_ticks))
             return;
         if (threadIdx.x == 0)
@@ -1189,7 +1198,8 @@ __global__ void __launch_bounds__(family_max_threads<KMASK>())
         __syncthreads();
     }
 
-    int parity = 0;
+    int parity = 0;   // partials half of the next reduction
+    int mparity = 0;  // max slot of the next folded MAX reduction
     const int64_t total = (int64_t)n_pro + (int64_t)prog.iters * prog.n_body;
     // (sidx, iter): the step and the body iteration of flattened step si,
     // advanced incrementally
@@ -1238,20 +1248,38 @@ __global__ void __launch_bounds__(family_max_threads<KMASK>())
                 }
             } else {
                 const int64_t nitems = region_items_dev(st, n, t);
+                // fold: this workgroup's max over its items, then one atomic
+                const bool fold = red && st.red_op == GF_OP_MAX && xmode && s_xcd.use;
+                uint64_t *slot = max_slot + (mparity ? kLineWords / 2 : 0);
+                double wmax = -INFINITY;
                 for (int64_t it = worker; it < nitems; it += G) {
                     double v = region_item<KMASK, TY, PF>(st, op, coef, n, it, t);
                     if (red) {
                         v = block_reduce_rt(st.red_op, v, s_red);
-                        if (threadIdx.x == 0)
+                        if (fold)
+                            wmax = v > wmax ? v : wmax;
+                        else if (threadIdx.x == 0)
                             part[it] = v;
                     }
                 }
-                if (need_bar && !barrier())
+                if (fold && threadIdx.x == 0 && worker < nitems)
+                    __hip_atomic_fetch_max(slot, max_key(wmax), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                // the last arrival resets the other slot, which the previous
+                // folded region used and every workgroup has read by now
+                if (need_bar && !barrier(fold ? max_slot + (mparity ? 0 : kLineWords / 2) : nullptr))
                     return;
                 if (red) {
-                    const double v = reduce_partials(st.red_op, part, nitems, s_red);
-                    if (threadIdx.x == 0)
-                        s_scal[st.sc[0]] = red_apply(st.red_op, s_scal[st.sc[0]], v);
+                    if (fold) {
+                        if (threadIdx.x == 0)
+                            s_scal[st.sc[0]] = red_apply(
+                                st.red_op, s_scal[st.sc[0]],
+                                max_unkey(__hip_atomic_load(slot, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)));
+                        mparity ^= 1;
+                    } else {
+                        const double v = reduce_partials(st.red_op, part, nitems, s_red);
+                        if (threadIdx.x == 0)
+                            s_scal[st.sc[0]] = red_apply(st.red_op, s_scal[st.sc[0]], v);
+                    }
                     parity ^= 1;
                 }
                 __syncthreads();
@@ -1878,18 +1906,45 @@ __global__ void __launch_bounds__(kMaxWg) k_reduce(const TI *__restrict__ in, in
     }
 }
 
-hipError_t launch_reduce(int op, int dt, const void *in, int64_t n, void *out, const Scratch &scr, int num_cu,
-                         hipStream_t s)
+int64_t reduce_grid(int64_t n, int num_cu, int64_t max_wg)
 {
     // Enough workgroups to stream at full bandwidth, each with >= 4K elements.
     int64_t g = cdiv(n, 4096);
-    const int64_t gmax = (int64_t)num_cu * 4;
+    int64_t gmax = (int64_t)num_cu * 4;
+    if (gmax > max_wg)
+        gmax = max_wg;
     if (g > gmax)
         g = gmax;
     if (g < 1)
         g = 1;
+    return g;
+}
+
+hipError_t launch_reduce(int op, int dt, const void *in, int64_t n, void *out, const Scratch &scr, int num_cu,
+                         hipStream_t s)
+{
     uint32_t *cnt = scr.lines + (int64_t)(kFinalizeLine0 + GF_MAX_INSTANCES - 1) * kLineWords;
-    void *part = scr.partials;
+    return launch_reduce_into(op, dt, in, n, out, scr.partials, cnt, reduce_grid(n, num_cu, INT32_MAX), s);
+}
+
+__global__ void __launch_bounds__(kWave) k_clear_u32(uint32_t *p, int32_t n)
+{
+    for (int32_t i = threadIdx.x; i < n; i += blockDim.x)
+        p[i] = 0u;
+}
+
+hipError_t launch_clear_u32(uint32_t *p, int32_t n, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_clear_u32, dim3(1), dim3(kWave), 0, s, p, n);
+    return hipGetLastError();
+}
+
+// The reduction kernels on caller-given scratch: `part` holds g partials of
+// the accumulation type (8 bytes each), `cnt` one counter word that is zero
+// on entry and is left zero.
+hipError_t launch_reduce_into(int op, int dt, const void *in, int64_t n, void *out, void *part, uint32_t *cnt,
+                              int64_t g, hipStream_t s)
+{
     const dim3 grid((unsigned)g), blk(kMaxWg);
 #define GF_RED(TI, T, OP) \
     hipLaunchKernelGGL((k_reduce<TI, T, OP>), grid, blk, 0, s, (const TI *)in, n, (T *)out, (T *)part, cnt)
