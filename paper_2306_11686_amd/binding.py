@@ -84,13 +84,17 @@ class Instance(ctypes.Structure):
 
     @classmethod
     def make(cls, arrays: dict, scal_ptr: int, ip=()):
-        """arrays: {slot: device pointer (int) or a tensor}; scal_ptr: device pointer of 16 doubles."""
+        """arrays: {slot: device pointer (int) or a tensor}; scal_ptr: device pointer of 16 doubles.
+        Tensors passed here are referenced by the instance, so that a
+        temporary one is not freed (and its memory handed to another tensor)
+        while the instance is still in use."""
         inst = cls()
         for k, v in arrays.items():
             inst.arr[k] = _ptr(v)
         inst.scal = _ptr(scal_ptr)
         for i, v in enumerate(ip):
             inst.ip[i] = int(v)
+        inst._keep = [v for v in list(arrays.values()) + [scal_ptr] if not isinstance(v, int)]
         return inst
 
 

@@ -276,6 +276,7 @@ struct gf_ctx {
         gf_launch l;
         bool has_l = false;
         int regions = 0, launches = 0, max_grid = 0;
+        int64_t j3runs = 0;
     } split;
     std::unordered_map<std::string, GraphEntry> graphs;
 
@@ -1088,6 +1089,12 @@ Tiling choose_tiling(const DProg &p, const gf_launch *l)
     if (!program_is_hist_family(p))
         t.items = 4;
     t.xcd_remap = 1;
+    // GF_ZALT=1: successive 3D stencil sweeps alternate their z direction
+    static const int zalt = [] {
+        const char *e = std::getenv("GF_ZALT");
+        return e ? std::atoi(e) : 0;
+    }();
+    t.zalt = zalt;
     if (l) {
         if (l->wg_size)
             t.wg_size = l->wg_size;
@@ -1368,6 +1375,11 @@ int64_t split_region(gf_ctx *ctx, int sidx, uint64_t perm)
     cur.n = sp.in.ip[s.np];
     cur.n_items = (int32_t)region_items(s, cur.n, sp.t);
     cur.inst = 0;
+    if (s.kind == GF_R_JACOBI3D) {
+        if (sp.t.zalt && (sp.j3runs & 1))
+            cur.step.flags |= kStepZRev;
+        ++sp.j3runs;
+    }
     if (launch_one(ctx, cur, sp.t, sp.has_l ? &sp.l : nullptr, ctx->split_stream, &sp.launches, &sp.max_grid) !=
         GF_OK)
         return -1;
@@ -1385,6 +1397,7 @@ gf_status enqueue_per_region(gf_ctx *ctx, const DProg &p, const gf_instance &in,
     RegionLaunch cur;
     bool pending = false;
     int launches = 0, regions = 0, max_grid = 0;
+    int64_t j3runs = 0;  // 3D stencil executions so far (z direction alternates with t.zalt)
 
     auto flush = [&]() -> gf_status {
         if (!pending)
@@ -1428,6 +1441,11 @@ gf_status enqueue_per_region(gf_ctx *ctx, const DProg &p, const gf_instance &in,
             cur.n = in.ip[s.np];
             cur.n_items = (int32_t)region_items(s, cur.n, t);
             cur.inst = inst_idx;
+            if (s.kind == GF_R_JACOBI3D) {
+                if (t.zalt && (j3runs & 1))
+                    cur.step.flags |= kStepZRev;
+                ++j3runs;
+            }
             pending = true;
             ++regions;
         } else if (s.kind == GF_S_SWAP) {
@@ -1649,6 +1667,7 @@ gf_status run_kernel_split(gf_ctx *ctx, const DProg &p, const gf_instance &in, i
         if (launch)
             sp.l = *launch;
         sp.regions = sp.launches = sp.max_grid = 0;
+        sp.j3runs = 0;
     }
     DInst di;
     std::memcpy(di.arr, in.arr, sizeof di.arr);

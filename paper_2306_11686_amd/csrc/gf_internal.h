@@ -74,7 +74,12 @@ struct Tiling {
     int32_t items;
     int32_t xcd_remap;
     int32_t prefetch;  // 3D stencil: planes requested ahead of the one computed (1 or 2)
+    int32_t zalt;      // 3D stencil (even n): successive executions alternate the z direction
 };
+
+// Step flag set by the per-region launchers on a 3D stencil execution that
+// marches its z segments downwards (Tiling::zalt, odd-numbered executions).
+constexpr uint32_t kStepZRev = 1u << 30;
 
 // One RPC request slot in pinned, coherent host memory (cf. the paper's
 // RPCInfo / RPCArgInfo records, Section 3.2): the device fills the body,

@@ -245,15 +245,18 @@ __device__ __forceinline__ gf_d2 ld_row(GF_GLOBAL const double *p, int r)
     return *(GF_GLOBAL const gf_d2 *)p;
 }
 
-// One tile of planes [z0, z1). PF (1 or 2) planes ahead of the computed
-// plane z are in flight: registers hold planes z-1 (own rows), z, z+1 and,
-// for PF = 2, z+2, while the next plane is requested at the top of the step.
-// The two depths are written out separately: folding them into one ring
-// array cost a fifth of the bandwidth at depth 1 (measured).
+// One tile of planes [z0, z1), marched upwards (dir = +1) or downwards
+// (dir = -1). PF (1 or 2) planes ahead of the computed plane z are in
+// flight: registers hold the plane behind z (own rows), z, the plane ahead
+// and, for PF = 2, the one after it, while the next plane is requested at
+// the top of the step. The two z-neighbours enter one addition, so marching
+// downwards gives the same bits (the sum of two doubles does not depend on
+// their order). The two depths are written out separately: folding them
+// into one ring array cost a fifth of the bandwidth at depth 1 (measured).
 template <int TY, int PF, bool FULL>
 __device__ __forceinline__ double j3v2_tile(GF_GLOBAL const double *__restrict__ u, GF_GLOBAL double *__restrict__ w,
                                             int64_t n, int64_t x, int64_t y0, int ny, int64_t z0, int64_t z1,
-                                            bool want_red)
+                                            int dir, bool want_red)
 {
     static_assert(PF == 1 || PF == 2, "prefetch depth 1 or 2");
     __shared__ double s_edge[2][kMaxWg / kWave][TY][2];
@@ -267,37 +270,42 @@ __device__ __forceinline__ double j3v2_tile(GF_GLOBAL const double *__restrict__
     const bool gather_l = wv == 0 && lane == 0 && xs >= 1;
     const bool gather_r = wv == nw - 1 && lane == kWave - 1 && xs + 2 <= n - 1;
     const int64_t SY = n, SZ = n * n;
+    const int64_t DZ = dir * SZ;                   // one plane in the marching direction
+    const int64_t cnt = z1 - z0;                   // planes computed
+    const int64_t zb = dir > 0 ? z0 : z1 - 1;      // first plane computed
     const double c6 = 1.0 / 6.0;
     double mx = -INFINITY;
-    // pm: plane z-1 (own rows); pc: plane z; pn: plane z+1; pa: z+2 (PF = 2);
-    // pf: the plane being requested (z+1+PF)
+    // pm: the plane behind z (own rows); pc: plane z; pn: the plane ahead;
+    // pa: the one after it (PF = 2); pf: the plane being requested
     gf_d2 pm[TY], pc[TY + 2], pn[TY + 2], pa[PF == 2 ? TY + 2 : 1], pf[TY + 2];
     const gf_d2 zero2 = {0.0, 0.0};
-    GF_GLOBAL const double *col = u + (y0 - 1) * SY + xs;  // row y0-1 of plane 0
+    GF_GLOBAL const double *col = u + (y0 - 1) * SY + xs + zb * SZ;  // row y0-1 of plane zb
 #pragma unroll
     for (int r = 0; r < TY; ++r)
-        pm[r] = (FULL || r < ny) ? ld_row<TY>(col + (z0 - 1) * SZ + (r + 1) * SY, r + 1) : zero2;
-    // planes z0 and z0+1 exist (z0+1 <= z1 <= n-1); z0+2 may be past the grid
+        pm[r] = (FULL || r < ny) ? ld_row<TY>(col - DZ + (r + 1) * SY, r + 1) : zero2;
+    // the first plane and the one ahead exist (both within [z0-1, z1]); the
+    // plane after may be past the segment
 #pragma unroll
     for (int r = 0; r < TY + 2; ++r) {
-        pc[r] = (FULL || r < ny + 2) ? ld_row<TY>(col + z0 * SZ + r * SY, r) : zero2;
-        pn[r] = (FULL || r < ny + 2) ? ld_row<TY>(col + (z0 + 1) * SZ + r * SY, r) : zero2;
+        pc[r] = (FULL || r < ny + 2) ? ld_row<TY>(col + r * SY, r) : zero2;
+        pn[r] = (FULL || r < ny + 2) ? ld_row<TY>(col + DZ + r * SY, r) : zero2;
         pf[r] = zero2;
     }
     if constexpr (PF == 2) {
-        const bool have = z0 + 2 <= z1;
+        const bool have = cnt >= 2;
 #pragma unroll
         for (int r = 0; r < TY + 2; ++r)
-            pa[r] = (have && (FULL || r < ny + 2)) ? ld_row<TY>(col + (z0 + 2) * SZ + r * SY, r) : zero2;
+            pa[r] = (have && (FULL || r < ny + 2)) ? ld_row<TY>(col + 2 * DZ + r * SY, r) : zero2;
     }
-    for (int64_t z = z0; z < z1; ++z) {
-        if (z + 1 + PF <= z1) {
+    for (int64_t k = 0; k < cnt; ++k) {
+        const int64_t z = zb + k * dir;
+        if (k + 1 + PF <= cnt) {
 #pragma unroll
             for (int r = 0; r < TY + 2; ++r)
                 if (FULL || r < ny + 2)
-                    pf[r] = ld_row<TY>(col + (z + 1 + PF) * SZ + r * SY, r);
+                    pf[r] = ld_row<TY>(col + (k + 1 + PF) * DZ + r * SY, r);
         }
-        const int par = (int)(z & 1);
+        const int par = (int)(k & 1);
         if (lane == 0) {
 #pragma unroll
             for (int r = 0; r < TY; ++r)
@@ -371,9 +379,12 @@ __device__ __forceinline__ double j3v2_tile(GF_GLOBAL const double *__restrict__
     return mx;
 }
 
+// zrev: march the segment downwards (successive sweeps alternate, so each
+// starts on the planes the previous one wrote last, which the memory-side
+// cache may still hold).
 template <int TY, int PF>
 __device__ __forceinline__ double j3v2_item(const double *u_, double *w_, int64_t n, int64_t item, const Tiling &t,
-                                            bool want_red)
+                                            bool zrev, bool want_red)
 {
     const StencilGeom g = j3v2_geom(n, t);
     const int64_t xc = item % g.nxc;
@@ -385,9 +396,10 @@ __device__ __forceinline__ double j3v2_item(const double *u_, double *w_, int64_
     const int ny = (int)(n - 1 - y0 < TY ? n - 1 - y0 : TY);
     const int64_t z0 = 1 + zs * t.tile_z;
     const int64_t z1 = (z0 + t.tile_z < n - 1) ? z0 + t.tile_z : n - 1;
+    const int dir = zrev ? -1 : 1;
     if (ny == TY)
-        return j3v2_tile<TY, PF, true>(gptr(u_), gptr(w_), n, x, y0, ny, z0, z1, want_red);
-    return j3v2_tile<TY, PF, false>(gptr(u_), gptr(w_), n, x, y0, ny, z0, z1, want_red);
+        return j3v2_tile<TY, PF, true>(gptr(u_), gptr(w_), n, x, y0, ny, z0, z1, dir, want_red);
+    return j3v2_tile<TY, PF, false>(gptr(u_), gptr(w_), n, x, y0, ny, z0, z1, dir, want_red);
 }
 
 // 2D 5-point Jacobi: the workgroup owns (row chunk) x (TY rows); each thread
@@ -860,14 +872,14 @@ __device__ bool phases_region(GF_GLOBAL double *a, GF_GLOBAL double *b, GF_GLOBA
 // caller); s is the AXPBY coefficient scal[st.sc[1]] * st.c.
 template <unsigned KMASK, int TY, int PF>
 __device__ __forceinline__ double region_item(const DStep &st, void *const *op, double s, int64_t n, int64_t item,
-                                              const Tiling &t)
+                                              const Tiling &t, bool zrev)
 {
     const bool red = st.red_op != GF_OP_NONE;
     switch (st.kind) {
     case GF_R_JACOBI3D:
         if constexpr ((KMASK >> GF_R_JACOBI3D) & 1u) {
             if ((n & 1) == 0)
-                return j3v2_item<TY, PF>((const double *)op[0], (double *)op[1], n, item, t, red);
+                return j3v2_item<TY, PF>((const double *)op[0], (double *)op[1], n, item, t, zrev, red);
             return j3_item<TY>((const double *)op[0], (double *)op[1], n, item, t, red);
         }
         break;
@@ -1123,8 +1135,19 @@ constexpr int family_max_threads()
     return KMASK == kFamHist ? kMaxWgHist : kMaxWg;
 }
 
+// Waves per SIMD the persistent kernel is compiled to fit: three 256-thread
+// workgroups per CU for the 3D stencil with tiles of one or two rows and one
+// plane in flight (its register need sits just above the 168 VGPRs that
+// allows; the compiler fits it without spilling).
+template <unsigned KMASK, int TY, int PF>
+constexpr int persistent_min_waves()
+{
+    return (KMASK == ((1u << GF_R_JACOBI3D) | (1u << GF_R_OWNER)) && TY <= 2 && PF == 1) ? 3 : 1;
+}
+
 template <unsigned KMASK, int TY, int PF>
 __global__ void __launch_bounds__(family_max_threads<KMASK>())
+    __attribute__((amdgpu_waves_per_eu(persistent_min_waves<KMASK, TY, PF>())))
     k_persistent(DProg prog, DInst inst_arg, Tiling t, Scratch scr, RpcRing rpc, BatchTable batch)
 {
     __shared__ double s_scal[GF_MAX_SCALARS];
@@ -1200,6 +1223,7 @@ __global__ void __launch_bounds__(family_max_threads<KMASK>())
 
     int parity = 0;   // partials half of the next reduction
     int mparity = 0;  // max slot of the next folded MAX reduction
+    int64_t j3runs = 0;  // 3D stencil executions so far (their z direction alternates with t.zalt)
     const int64_t total = (int64_t)n_pro + (int64_t)prog.iters * prog.n_body;
     // (sidx, iter): the step and the body iteration of flattened step si,
     // advanced incrementally
@@ -1248,12 +1272,14 @@ __global__ void __launch_bounds__(family_max_threads<KMASK>())
                 }
             } else {
                 const int64_t nitems = region_items_dev(st, n, t);
+                const bool zrev = st.kind == GF_R_JACOBI3D && t.zalt && (j3runs & 1);
+                j3runs += st.kind == GF_R_JACOBI3D ? 1 : 0;
                 // fold: this workgroup's max over its items, then one atomic
                 const bool fold = red && st.red_op == GF_OP_MAX && xmode && s_xcd.use;
                 uint64_t *slot = max_slot + (mparity ? kLineWords / 2 : 0);
                 double wmax = -INFINITY;
                 for (int64_t it = worker; it < nitems; it += G) {
-                    double v = region_item<KMASK, TY, PF>(st, op, coef, n, it, t);
+                    double v = region_item<KMASK, TY, PF>(st, op, coef, n, it, t, zrev);
                     if (red) {
                         v = block_reduce_rt(st.red_op, v, s_red);
                         if (fold)
@@ -1389,7 +1415,7 @@ __global__ void __launch_bounds__(family_max_threads<KMASK>()) k_region(RegionLa
         const double coef = (st.kind == GF_R_AXPBY) ? rl.scal[st.sc[1]] * st.c : 0.0;
         const int64_t worker = worker_id(blockIdx.x, G, t.xcd_remap);
         for (int64_t it = worker; it < rl.n_items; it += G) {
-            double v = region_item<KMASK, TY, PF>(st, rl.arr, coef, rl.n, it, t);
+            double v = region_item<KMASK, TY, PF>(st, rl.arr, coef, rl.n, it, t, (st.flags & kStepZRev) != 0);
             if (red) {
                 v = block_reduce_rt(st.red_op, v, s_red);
                 if (threadIdx.x == 0)
@@ -1629,6 +1655,7 @@ int phases_capacity(int wg_size, int num_cu)
 // ---------------------------------------------------------------------------
 
 constexpr unsigned kFamJ3 = (1u << GF_R_JACOBI3D) | (1u << GF_R_OWNER);
+static_assert(persistent_min_waves<kFamJ3, 2, 1>() == 3, "3D stencil family mask");
 constexpr unsigned kFamJ2 = (1u << GF_R_JACOBI2D) | (1u << GF_R_OWNER);
 constexpr unsigned kFamVec =
     (1u << GF_R_SPMV) | (1u << GF_R_DOT) | (1u << GF_R_AXPBY) | (1u << GF_R_OWNER) | (1u << GF_R_PHASES);
