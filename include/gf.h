@@ -311,6 +311,23 @@ gf_status gf_region_run(gf_ctx *ctx, const gf_program *prog, const gf_instance *
 gf_status gf_reduce(gf_ctx *ctx, int32_t op, int32_t dt, const void *d_in, int64_t n,
                     void *d_out, void *hip_stream);
 
+/* gf_reduce without any allocation, for callers that cannot allocate
+ * device memory at call time: code under HIP graph capture, tight serving
+ * loops, harnesses that forbid hipMalloc. Same arguments, semantics and
+ * result bits as gf_reduce (same grid and summation order). Its scratch is
+ * a static device array of 8,448 bytes per GPU (one counter line and 1,024
+ * per-workgroup partials), held until the process ends; gf_ctx_create
+ * resolves that GPU's copy once, and this call allocates nothing and calls
+ * no allocating routine. The grid never exceeds the 1,024 partials the
+ * array holds, so any n >= 0 fits; a grid that would not fit is rejected
+ * with GF_EINVAL. The counter word is cleared by a small kernel at the start
+ * of every call (no memset). All calls on one GPU share its array: calls
+ * that overlap on one GPU (several streams or host threads, in any
+ * context) race and give wrong results; the caller serialises them. Not
+ * ordered against the context's other work on other streams. */
+gf_status gf_reduce_noalloc(gf_ctx *ctx, int32_t op, int32_t dt, const void *d_in, int64_t n,
+                            void *d_out, void *hip_stream);
+
 /* Service pending RPC requests in ticket (FIFO) order (Section 2.3: the
  * host is the server of a synchronous client-server protocol): runs the
  * landing pad of each request, writes its return value and marks it done.

@@ -220,6 +220,8 @@ _SIGS = {
                                      ctypes.POINTER(RunStats), ctypes.c_void_p]),
     "gf_reduce": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_int32, ctypes.c_void_p, ctypes.c_int64,
                                  ctypes.c_void_p, ctypes.c_void_p]),
+    "gf_reduce_noalloc": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_int32, ctypes.c_void_p,
+                                         ctypes.c_int64, ctypes.c_void_p, ctypes.c_void_p]),
     "gf_rpc_poll": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_int32]),
     "gf_rpc_register_format": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_char_p, ctypes.c_char_p]),
     "gf_rpc_take_output": (ctypes.c_int64, [ctypes.c_void_p, ctypes.c_char_p, ctypes.c_int64]),
@@ -394,6 +396,10 @@ class Context:
 
     def reduce(self, op: int, dtype: int, d_in, n: int, d_out, stream=None):
         self._check(self.lib.gf_reduce(self.h, op, dtype, _ptr(d_in), n, _ptr(d_out), _stream_handle(stream)))
+
+    def reduce_noalloc(self, op: int, dtype: int, d_in, n: int, d_out, stream=None):
+        self._check(self.lib.gf_reduce_noalloc(self.h, op, dtype, _ptr(d_in), n, _ptr(d_out),
+                                               _stream_handle(stream)))
 
     def rpc_poll(self, max_requests: int = 1 << 20, timeout_us: int = 0) -> int:
         return self._check(self.lib.gf_rpc_poll(self.h, max_requests, timeout_us))

@@ -15,7 +15,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
-SOURCES = ["gf_api.hip", "gf_kernels.hip", "gf_mlp.hip", "gf_heap.hip"]
+SOURCES = ["gf_api.hip", "gf_kernels.hip", "gf_mlp.hip", "gf_heap.hip", "gf_noalloc.hip"]
 LIB = os.path.join(HERE, "libgf.so")
 ARCH = "gfx950"
 

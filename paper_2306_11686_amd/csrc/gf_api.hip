@@ -302,6 +302,9 @@ struct gf_ctx {
     };
     std::unordered_map<std::string, Tuned> tuned;
 
+    // set-up of gf_reduce_noalloc's static array on this device
+    hipError_t noalloc_status = hipErrorNotInitialized;
+
     // predictor: device scratch for training, host copy for inference
     float *d_mlp = nullptr;       // gradient partials | grads | z1 | z2 | y | loss partials
     size_t d_mlp_floats = 0;
@@ -545,6 +548,9 @@ gf_status gf_ctx_create(int32_t hip_device, const gf_ctx_opts *opts, gf_ctx **ou
         return GF_EHIP;
     }
     ctx->num_cu = prop.multiProcessorCount;
+    // gf_reduce_noalloc's static array on this device: resolved once per
+    // device here, so that the entry point itself allocates nothing
+    ctx->noalloc_status = noalloc_setup(hip_device);
 
     // device scratch: partials (two halves), counter lines, error word
     const int64_t cap = 1 << 20;
@@ -1926,6 +1932,30 @@ gf_status gf_reduce(gf_ctx *ctx, int32_t op, int32_t dt, const void *d_in, int64
     if (e != hipSuccess)
         return hipfail(ctx, e, "reduce launch");
     mark_after(ctx, s);
+    return GF_OK;
+}
+
+gf_status gf_reduce_noalloc(gf_ctx *ctx, int32_t op, int32_t dt, const void *d_in, int64_t n, void *d_out,
+                            void *hip_stream)
+{
+    if (!ctx)
+        return GF_EINVAL;
+    if (op != GF_OP_SUM && op != GF_OP_MAX)
+        return fail(ctx, GF_EINVAL, "unknown reduction op %d", op);
+    if (dt < GF_F64 || dt > GF_I64)
+        return fail(ctx, GF_EINVAL, "unknown dtype %d", dt);
+    if (n < 0 || (n > 0 && !d_in) || !d_out)
+        return fail(ctx, GF_EINVAL, "bad reduction arguments");
+    if (ctx->noalloc_status != hipSuccess)
+        return hipfail(ctx, ctx->noalloc_status, "gf_reduce_noalloc: static scratch not set up on this device");
+    hipError_t e = hipSetDevice(ctx->device);
+    if (e == hipSuccess)
+        e = noalloc_reduce(ctx->device, ctx->num_cu, op, dt, d_in, n, d_out, (hipStream_t)hip_stream, nullptr);
+    if (e == hipErrorInvalidValue)
+        return fail(ctx, GF_EINVAL, "gf_reduce_noalloc: the grid for n = %lld needs more partials than the static "
+                    "array holds (%zu bytes)", (long long)n, noalloc_scratch_bytes());
+    if (e != hipSuccess)
+        return hipfail(ctx, e, "gf_reduce_noalloc launch");
     return GF_OK;
 }
 

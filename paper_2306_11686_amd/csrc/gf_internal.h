@@ -264,6 +264,13 @@ int64_t reduce_grid(int64_t n, int num_cu, int64_t max_wg);
 hipError_t launch_reduce_into(int op, int dt, const void *in, int64_t n, void *out, void *part, uint32_t *cnt,
                               int64_t g, hipStream_t s);
 hipError_t launch_clear_u32(uint32_t *p, int32_t n, hipStream_t s);
+// gf_reduce_noalloc's static scratch (gf_noalloc.hip): set-up per device
+// (device current), its address, and the reduction on it
+hipError_t noalloc_setup(int device);
+void *noalloc_ptr(int device);
+size_t noalloc_scratch_bytes();
+hipError_t noalloc_reduce(int device, int num_cu, int op, int dt, const void *in, int64_t n, void *out,
+                          hipStream_t s, int64_t *grid_out);
 hipError_t launch_copy(void *dst, const void *src, int64_t nbytes, int num_wg, hipStream_t s);
 
 // Number of work items (tiles / chunks) a region splits into under tiling t.
