@@ -230,7 +230,8 @@ typedef struct {
 typedef struct {
     int32_t wg_size;     /* threads per workgroup (multiple of 64, <= 1024) */
     int32_t num_wg;      /* workgroups (persistent: <= co-resident capacity) */
-    int32_t tile_y;      /* stencil rows per tile (1..16) */
+    int32_t tile_y;      /* 3D stencil: rows per tile (1, 2, 4, 8 or 16); 2D stencil:
+                          * rows per segment a workgroup marches through (>= 1) */
     int32_t tile_z;      /* 3D stencil z-segment length */
     int32_t items;       /* elements per thread for streaming regions (histogram:
                           * groups of four keys per thread per chunk, 1, 2, 4 or 8) */
@@ -457,8 +458,8 @@ gf_status gf_copy(gf_ctx *ctx, void *d_dst, const void *d_src, int64_t nbytes, i
  * a = c & 3, b = (c >> 2) & 3, h = c >> 4:
  *   3D stencil : tile_y = {1,2,4,8}[a], tile_z = ceil((n-2)/{2,3,4,6}[b]),
  *                num_wg = h ? 3 * CUs : default
- *   2D stencil : tile_y = {1,2,4,8}[a], wg_size = {64,128,192,256}[b],
- *                xcd_remap = 1 - h
+ *   2D stencil : tile_y = {2,8,32,128}[a] rows per segment,
+ *                wg_size = {64,128,192,256}[b], xcd_remap = 1 - h
  *   streaming (SpMV, dot, axpby): wg_size = {64,128,192,256}[a],
  *                items = {1,2,4,8}[b], num_wg = h ? 4 * CUs : default
  *   histogram  : wg_size = {256,512,768,1024}[a], items = {1,2,4,8}[b],
@@ -485,6 +486,51 @@ int32_t gf_tune(gf_ctx *ctx, const gf_program *prog, const gf_instance *inst, in
 /* Index of the smallest finite ms[i] (ties: lowest index), or -1 if none is
  * finite. Pure host function. */
 int32_t gf_tune_pick(const float *ms, int32_t n);
+
+/* ---- batched runs with a launch shape per instance -----------------------
+ * Many uneven instances of one program (not in the paper): instance i runs
+ * with launches[i].tile_y rows per tile (0: the default; a 3D stencil's rows
+ * must be the same for all, being compiled into the kernel) and a share of
+ * the persistent grid proportional to launches[i].num_wg (a relative weight;
+ * 0: its number of work items). wg_size, items, xcd_remap and prefetch are
+ * taken from launches[0]; the grid is the co-resident capacity. In the
+ * persistent mode the instances are packed onto the eight XCDs and each
+ * instance's workgroups stay on one XCD (see DESIGN of the batched launch);
+ * the per-region modes launch each instance with its own rows per tile.
+ * Same conventions as gf_region_run otherwise. */
+gf_status gf_region_run_batched(gf_ctx *ctx, const gf_program *prog, const gf_instance *inst,
+                                int32_t n_inst, int32_t mode, const gf_launch *launches,
+                                gf_run_stats *stats, void *hip_stream);
+
+/* The plan of a batched persistent launch (pure host function, used by
+ * gf_region_run_batched): instance i has items[i] >= 1 work items per region
+ * and weight weights[i] (its total cost; NULL or <= 0: items[i]). With align,
+ * instances are packed onto the 8 XCDs (xcd[i]; heaviest first onto the least
+ * loaded XCD with room) and each XCD's budget / 8 workgroups are shared among
+ * its instances; else xcd[i] = -1 and the whole budget is shared. A group of
+ * g workgroups takes ceil(items / g) items each per region; group[i]
+ * receives the sizes that minimise the slowest group's time (greedy: the
+ * slowest group gets just enough workgroups to take one item less each,
+ * while the budget lasts). Returns the grid (8 x the largest XCD's
+ * workgroups when aligned, else the sum of the groups), or GF_EINVAL. */
+int32_t gf_batch_plan(int32_t n_inst, const int64_t *items, const double *weights, int32_t budget,
+                      int32_t align, int32_t *group, int32_t *xcd);
+
+/* Autotuner for batched persistent runs: instances are grouped into size
+ * classes (floor(log2 n) of the program's first stencil size); for each
+ * common workgroup size in {64, 128, 256} every class is run alone with each
+ * rows-per-segment candidate in {8, 16, 32, 64, 128} and keeps its fastest;
+ * the class's cost per work item (median ms x workgroups / items) then
+ * weights its instances' shares of the grid. The whole batch is timed with
+ * those weights and with plain item-count weights; the fastest of all
+ * becomes out[0..n_inst) (for gf_region_run_batched), and *best_ms its
+ * median (nullable). Programs without a 2D stencil get one common shape from
+ * gf_tune's candidates, weighted by items. Every timed run changes the
+ * instances' data like a real run (reps + 1 runs per configuration). Blocks
+ * until done. Returns the number of configurations timed, or a negative
+ * gf_status. */
+int32_t gf_tune_batched(gf_ctx *ctx, const gf_program *prog, const gf_instance *inst, int32_t n_inst,
+                        int32_t reps, gf_launch *out, float *best_ms, void *hip_stream);
 
 /* ---- learned launch-config predictor --------------------------------------
  * Not in the paper (its team counts are chosen by hand): a small FP32 MLP

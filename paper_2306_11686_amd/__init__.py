@@ -21,6 +21,6 @@ from .binding import (  # noqa: F401
     GF_HEAP_OP_MALLOC, GF_HEAP_OP_FREE, GF_HEAP_OP_FIND, GF_HEAP_BENCH_ROUNDTRIP, GF_HEAP_BENCH_HOLD,
     GF_HEAP_BENCH_RELEASE, Heap,
     GfError, Context, Step, Launch, Program, Instance, CallArg, CallStats, host_stream, lib_path, load_library,
-    exported_symbols, tune_pick,
+    exported_symbols, tune_pick, batch_plan,
 )
 from . import programs  # noqa: F401

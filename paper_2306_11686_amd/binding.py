@@ -250,6 +250,15 @@ _SIGS = {
                                  ctypes.c_int32, ctypes.POINTER(Launch), ctypes.c_int32, ctypes.c_int32,
                                  ctypes.POINTER(ctypes.c_float), ctypes.POINTER(ctypes.c_int32), ctypes.c_void_p]),
     "gf_tune_pick": (ctypes.c_int32, [ctypes.POINTER(ctypes.c_float), ctypes.c_int32]),
+    "gf_region_run_batched": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(Program), ctypes.POINTER(Instance),
+                                             ctypes.c_int32, ctypes.c_int32, ctypes.POINTER(Launch),
+                                             ctypes.POINTER(RunStats), ctypes.c_void_p]),
+    "gf_batch_plan": (ctypes.c_int32, [ctypes.c_int32, ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_double),
+                                       ctypes.c_int32, ctypes.c_int32, ctypes.POINTER(ctypes.c_int32),
+                                       ctypes.POINTER(ctypes.c_int32)]),
+    "gf_tune_batched": (ctypes.c_int32, [ctypes.c_void_p, ctypes.POINTER(Program), ctypes.POINTER(Instance),
+                                         ctypes.c_int32, ctypes.c_int32, ctypes.POINTER(Launch),
+                                         ctypes.POINTER(ctypes.c_float), ctypes.c_void_p]),
     "gf_mlp_forward": (ctypes.c_int, [ctypes.c_void_p] + [ctypes.c_void_p] * 2 + [ctypes.c_int32] +
                        [ctypes.c_void_p] * 4),
     "gf_mlp_backward": (ctypes.c_int, [ctypes.c_void_p] + [ctypes.c_void_p] * 7 + [ctypes.c_int32, ctypes.c_float,
@@ -327,6 +336,21 @@ def tune_pick(ms) -> int:
     return lib.gf_tune_pick(arr, len(ms))
 
 
+def batch_plan(items, weights=None, budget: int = 4096, align: bool = True):
+    """Host-only plan of a batched persistent launch (the library's
+    gf_batch_plan): (grid, group sizes, XCD per instance or -1)."""
+    lib = load_library()
+    n = len(items)
+    it = (ctypes.c_int64 * n)(*[int(v) for v in items])
+    w = (ctypes.c_double * n)(*[float(v) for v in weights]) if weights is not None else None
+    g = (ctypes.c_int32 * n)()
+    x = (ctypes.c_int32 * n)()
+    grid = lib.gf_batch_plan(n, it, w, budget, 1 if align else 0, g, x)
+    if grid < 0:
+        raise GfError(grid, "gf_batch_plan: invalid arguments")
+    return grid, list(g), list(x)
+
+
 def _stream_handle(stream):
     if stream is None:
         import torch
@@ -393,6 +417,28 @@ class Context:
                                     _stream_handle(stream))
         self._check(st)
         return stats.as_dict()
+
+    def run_batched(self, program: Program, instances, launches, mode: int = GF_EXEC_PERSISTENT,
+                    stream=None) -> dict:
+        """One run of many instances with a launch shape per instance
+        (rows per tile, relative share of the grid)."""
+        if len(launches) != len(instances):
+            raise ValueError("one launch per instance")
+        arr = (Instance * len(instances))(*instances)
+        ls = (Launch * len(launches))(*launches)
+        stats = RunStats()
+        self._check(self.lib.gf_region_run_batched(self.h, ctypes.byref(program), arr, len(instances), mode, ls,
+                                                   ctypes.byref(stats), _stream_handle(stream)))
+        return stats.as_dict()
+
+    def tune_batched(self, program: Program, instances, reps: int = 3, stream=None):
+        """The batched autotuner: returns (launches, one per instance; median ms of the best run)."""
+        arr = (Instance * len(instances))(*instances)
+        out = (Launch * len(instances))()
+        ms = ctypes.c_float(0.0)
+        self._check(self.lib.gf_tune_batched(self.h, ctypes.byref(program), arr, len(instances), reps, out,
+                                             ctypes.byref(ms), _stream_handle(stream)))
+        return [out[i] for i in range(len(instances))], float(ms.value)
 
     def reduce(self, op: int, dtype: int, d_in, n: int, d_out, stream=None):
         self._check(self.lib.gf_reduce(self.h, op, dtype, _ptr(d_in), n, _ptr(d_out), _stream_handle(stream)))

@@ -276,7 +276,6 @@ struct gf_ctx {
         gf_launch l;
         bool has_l = false;
         int regions = 0, launches = 0, max_grid = 0;
-        int64_t j3runs = 0;
     } split;
     std::unordered_map<std::string, GraphEntry> graphs;
 
@@ -284,6 +283,7 @@ struct gf_ctx {
     // event that marks when the staging buffer may be rewritten
     void *d_batch = nullptr;
     void *h_batch = nullptr;
+    bool batch_align = true;  // keep each batched group on one XCD (GF_BATCH_ALIGN=0: lay groups out in order)
     hipEvent_t batch_copied = nullptr;
     bool batch_pending = false;
 
@@ -299,6 +299,7 @@ struct gf_ctx {
     struct Tuned {
         gf_launch launch;
         int32_t cand;
+        std::vector<gf_launch> per;  // batched persistent runs: a shape per instance
     };
     std::unordered_map<std::string, Tuned> tuned;
 
@@ -582,6 +583,8 @@ gf_status gf_ctx_create(int32_t hip_device, const gf_ctx_opts *opts, gf_ctx **ou
     ctx->scr.barrier_kind = kBarrierXcd;
     if (const char *bk = std::getenv("GF_BARRIER"))
         ctx->scr.barrier_kind = std::strcmp(bk, "tree") == 0 ? kBarrierTree : kBarrierXcd;
+    if (const char *ba = std::getenv("GF_BATCH_ALIGN"))
+        ctx->batch_align = std::strcmp(ba, "0") != 0;
 
     // RPC ring
     uint32_t ns = o.rpc_slots > 0 ? (uint32_t)o.rpc_slots : 256u;
@@ -1089,18 +1092,12 @@ Tiling choose_tiling(const DProg &p, const gf_launch *l)
     t.wg_size = program_is_hist_family(p) ? 1024 : 256;
     if (program_is_hist_family(p))
         t.items = 8;
-    t.tile_y = (m & (1u << GF_R_JACOBI3D)) ? 8 : ((m & (1u << GF_R_JACOBI2D)) ? 1 : 1);
+    t.tile_y = (m & (1u << GF_R_JACOBI3D)) ? 8 : ((m & (1u << GF_R_JACOBI2D)) ? 16 : 1);
     t.tile_z = 64;
     t.prefetch = 1;
     if (!program_is_hist_family(p))
         t.items = 4;
     t.xcd_remap = 1;
-    // GF_ZALT=1: successive 3D stencil sweeps alternate their z direction
-    static const int zalt = [] {
-        const char *e = std::getenv("GF_ZALT");
-        return e ? std::atoi(e) : 0;
-    }();
-    t.zalt = zalt;
     if (l) {
         if (l->wg_size)
             t.wg_size = l->wg_size;
@@ -1122,8 +1119,13 @@ gf_status check_tiling(gf_ctx *ctx, const DProg &p, const Tiling &t)
     const int maxwg = program_is_hist_family(p) ? 1024 : 256;
     if (t.wg_size < 64 || t.wg_size > maxwg || (t.wg_size % 64))
         return fail(ctx, GF_EINVAL, "wg_size must be a multiple of 64 in [64, %d]", maxwg);
-    if (!(t.tile_y == 1 || t.tile_y == 2 || t.tile_y == 4 || t.tile_y == 8 || t.tile_y == 16))
+    // the 3D stencil keeps tile_y rows per thread in registers (compiled for
+    // five heights); the 2D stencil marches segments of any length
+    if ((program_region_mask(p) & (1u << GF_R_JACOBI3D)) &&
+        !(t.tile_y == 1 || t.tile_y == 2 || t.tile_y == 4 || t.tile_y == 8 || t.tile_y == 16))
         return fail(ctx, GF_EINVAL, "tile_y must be 1, 2, 4, 8 or 16");
+    if (t.tile_y < 1 || t.tile_y > 1 << 20)
+        return fail(ctx, GF_EINVAL, "tile_y out of range");
     if (t.tile_z < 1 || t.tile_z > 1 << 20)
         return fail(ctx, GF_EINVAL, "tile_z out of range");
     if (t.items < 1 || t.items > 64)
@@ -1381,11 +1383,7 @@ int64_t split_region(gf_ctx *ctx, int sidx, uint64_t perm)
     cur.n = sp.in.ip[s.np];
     cur.n_items = (int32_t)region_items(s, cur.n, sp.t);
     cur.inst = 0;
-    if (s.kind == GF_R_JACOBI3D) {
-        if (sp.t.zalt && (sp.j3runs & 1))
-            cur.step.flags |= kStepZRev;
-        ++sp.j3runs;
-    }
+
     if (launch_one(ctx, cur, sp.t, sp.has_l ? &sp.l : nullptr, ctx->split_stream, &sp.launches, &sp.max_grid) !=
         GF_OK)
         return -1;
@@ -1403,7 +1401,6 @@ gf_status enqueue_per_region(gf_ctx *ctx, const DProg &p, const gf_instance &in,
     RegionLaunch cur;
     bool pending = false;
     int launches = 0, regions = 0, max_grid = 0;
-    int64_t j3runs = 0;  // 3D stencil executions so far (z direction alternates with t.zalt)
 
     auto flush = [&]() -> gf_status {
         if (!pending)
@@ -1447,11 +1444,6 @@ gf_status enqueue_per_region(gf_ctx *ctx, const DProg &p, const gf_instance &in,
             cur.n = in.ip[s.np];
             cur.n_items = (int32_t)region_items(s, cur.n, t);
             cur.inst = inst_idx;
-            if (s.kind == GF_R_JACOBI3D) {
-                if (t.zalt && (j3runs & 1))
-                    cur.step.flags |= kStepZRev;
-                ++j3runs;
-            }
             pending = true;
             ++regions;
         } else if (s.kind == GF_S_SWAP) {
@@ -1513,14 +1505,131 @@ std::string graph_key(const DProg &p, const gf_instance *inst, int n_inst, const
 
 }  // namespace
 
+// Per-instance shape of a batched run: rows per tile (0: the launch's) and
+// the relative weight of its share of workgroups (<= 0: its work items).
+struct InstShape {
+    int32_t tile_y;
+    double weight;
+};
+
+// Workgroups for the instances `ids` out of `budget` (each >= 1 and at most
+// its item count). A group of g_i workgroups deals its items_i tiles
+// round-robin, so its time per region is ceil(items_i / g_i) tiles at a cost
+// of w_i / items_i each; the launch lasts as long as its slowest group.
+// Greedy: every instance starts with one workgroup, and while the budget
+// allows, the slowest group gets just enough workgroups to take one tile
+// less each. Workgroups that would not shorten the slowest group stay
+// unused.
+void share_groups(const std::vector<int> &ids, int budget, const std::vector<double> &w,
+                  const std::vector<int64_t> &items, std::vector<int> &g)
+{
+    auto cost = [&](int i) { return w[i] / (double)items[i]; };
+    auto per_wg = [&](int i) { return (items[i] + g[i] - 1) / g[i]; };
+    std::vector<std::pair<double, int>> heap;
+    int used = 0;
+    for (int i : ids) {
+        g[i] = 1;
+        ++used;
+        heap.emplace_back((double)items[i] * cost(i), i);
+    }
+    std::make_heap(heap.begin(), heap.end());
+    while (!heap.empty()) {
+        std::pop_heap(heap.begin(), heap.end());
+        const int i = heap.back().second;
+        heap.pop_back();
+        const int64_t k = per_wg(i);
+        if (k <= 1)
+            break;  // the slowest group takes one tile per workgroup already
+        const int64_t want = (items[i] + (k - 1) - 1) / (k - 1);
+        const int need = (int)(want - g[i]);
+        if (used + need > budget)
+            break;  // the slowest group cannot be shortened
+        g[i] += need;
+        used += need;
+        heap.emplace_back((double)per_wg(i) * cost(i), i);
+        std::push_heap(heap.begin(), heap.end());
+    }
+}
+
+// The plan of a batched persistent launch: with `align`, instance i goes to
+// XCD xcd[i] (heaviest first onto the least loaded XCD with a free slot)
+// and each XCD's budget / 8 workgroups are shared among its instances;
+// otherwise (or when an XCD would need more than its share of instances)
+// xcd[] stays -1 and the whole budget is shared. g[i] receives the group
+// sizes. Returns the grid: 8 times the largest XCD's workgroups when
+// aligned, else the sum of the groups.
+int plan_batch(int n, const std::vector<int64_t> &items, const std::vector<double> &w, int budget, bool align,
+               std::vector<int> &g, std::vector<int> &xcd)
+{
+    const int per = budget / kNumXcd;
+    bool aligned = per >= 1 && align;
+    std::fill(xcd.begin(), xcd.end(), -1);
+    if (aligned) {
+        std::vector<int> order(n);
+        for (int i = 0; i < n; ++i)
+            order[i] = i;
+        std::sort(order.begin(), order.end(), [&](int a, int b) { return w[a] > w[b] || (w[a] == w[b] && a < b); });
+        double load[kNumXcd] = {0};
+        int cnt[kNumXcd] = {0};
+        for (int i : order) {
+            int best = -1;
+            for (int x = 0; x < kNumXcd; ++x)
+                if (cnt[x] < per && (best < 0 || load[x] < load[best]))
+                    best = x;
+            if (best < 0) {
+                aligned = false;
+                break;
+            }
+            xcd[i] = best;
+            load[best] += w[i];
+            ++cnt[best];
+        }
+        if (!aligned)
+            std::fill(xcd.begin(), xcd.end(), -1);
+    }
+    if (aligned) {
+        int longest = 0;
+        for (int x = 0; x < kNumXcd; ++x) {
+            std::vector<int> ids;
+            for (int i = 0; i < n; ++i)
+                if (xcd[i] == x)
+                    ids.push_back(i);
+            share_groups(ids, per, w, items, g);
+            int used = 0;
+            for (int i : ids)
+                used += g[i];
+            longest = std::max(longest, used);
+        }
+        return longest * kNumXcd;
+    }
+    std::vector<int> all(n);
+    for (int i = 0; i < n; ++i)
+        all[i] = i;
+    share_groups(all, budget, w, items, g);
+    int sum = 0;
+    for (int i = 0; i < n; ++i)
+        sum += g[i];
+    return sum;
+}
+
 // Batched persistent launch (many uneven instances of one program in one
-// cooperative launch): instance i gets a group of g_i >= 1 workgroups with
-// g_i proportional to its work items (largest remainders, capped at its
-// item count), its own flat group barrier and its own slice of the
-// reduction partials. The device table is staged through pinned memory; the
-// staging buffer is rewritten only after the previous copy has executed.
+// cooperative launch). Instance i gets a group of g_i >= 1 workgroups, its
+// own group barrier and its own slice of the reduction partials. The groups
+// are kept on single XCDs: the instances are packed onto the eight XCDs
+// (heaviest first onto the least loaded XCD; weight = work items unless the
+// shape gives one), each XCD's share of the grid is divided among its
+// instances, and workgroup b takes an entry of XCD b mod 8
+// (the hardware's round-robin dispatch; the kernel checks it and falls back
+// to the cross-XCD group barrier otherwise). A group on one XCD shares one
+// L2, so its barrier needs no L2 write-back and its tiles share halo rows.
+// Within an XCD the group sizes minimise the slowest group's time per region
+// (share_groups). Without room for that packing the groups are laid out in
+// order. The
+// device table is staged through pinned memory; the staging buffer is
+// rewritten only after the previous copy has executed.
 gf_status run_batched(gf_ctx *ctx, const DProg &p, const gf_instance *inst, int n_inst, const Tiling &t,
-                      const gf_launch *launch, int cap, gf_run_stats *stats, hipStream_t stream)
+                      const gf_launch *launch, int cap, gf_run_stats *stats, hipStream_t stream,
+                      const InstShape *shape)
 {
     if (program_is_hist_family(p))
         return fail(ctx, GF_EUNSUPPORTED, "batched persistent runs of histogram programs are not supported");
@@ -1532,39 +1641,28 @@ gf_status run_batched(gf_ctx *ctx, const DProg &p, const gf_instance *inst, int 
         return fail(ctx, GF_EINVAL, "%d instances need at least %d co-resident workgroups, capacity %d", n_inst,
                     n_inst, budget);
     std::vector<int64_t> items(n_inst), red(n_inst);
-    int64_t total = 0;
+    std::vector<double> w(n_inst);
+    std::vector<int32_t> ty(n_inst, 0);
     for (int i = 0; i < n_inst; ++i) {
-        items[i] = std::max<int64_t>(1, max_items(p, inst[i], t));
+        Tiling ti = t;
+        if (shape && shape[i].tile_y > 0)
+            ti.tile_y = ty[i] = shape[i].tile_y;
+        items[i] = std::max<int64_t>(1, max_items(p, inst[i], ti));
         int64_t r = 0;
         for (int k = 0; k < p.n_steps; ++k)
             if (is_region(p.steps[k].kind) && p.steps[k].red_op != GF_OP_NONE)
-                r = std::max<int64_t>(r, region_items(p.steps[k], inst[i].ip[p.steps[k].np], t));
+                r = std::max<int64_t>(r, region_items(p.steps[k], inst[i].ip[p.steps[k].np], ti));
         red[i] = r;
-        total += items[i];
+        w[i] = (shape && shape[i].weight > 0.0) ? shape[i].weight : (double)items[i];
     }
-    // proportional allocation with a floor of one workgroup each
-    std::vector<int> g(n_inst, 1);
-    int used = n_inst;
-    std::vector<std::pair<double, int>> rem;
-    const int spare = budget - n_inst;
-    for (int i = 0; i < n_inst; ++i) {
-        const double share = (double)spare * (double)items[i] / (double)total;
-        int extra = (int)std::floor(share);
-        extra = (int)std::min<int64_t>(extra, items[i] - 1);
-        g[i] += extra;
-        used += extra;
-        rem.emplace_back(share - std::floor(share), i);
-    }
-    std::sort(rem.begin(), rem.end(), [](const std::pair<double, int> &a, const std::pair<double, int> &b) {
-        return a.first > b.first || (a.first == b.first && a.second < b.second);
-    });
-    for (size_t k = 0; k < rem.size() && used < budget; ++k) {
-        const int i = rem[k].second;
-        if (g[i] < items[i]) {
-            ++g[i];
-            ++used;
-        }
-    }
+    // pack onto XCDs and size the groups
+    std::vector<int> g(n_inst, 1), xcd_of(n_inst, -1);
+    const int grid = plan_batch(n_inst, items, w, budget, ctx->batch_align, g, xcd_of);
+    const bool aligned = xcd_of[0] >= 0;
+    std::vector<std::vector<int>> on(kNumXcd);
+    if (aligned)
+        for (int i = 0; i < n_inst; ++i)
+            on[xcd_of[i]].push_back(i);
     // partial slices
     std::vector<int64_t> off(n_inst);
     int64_t acc = 0;
@@ -1584,15 +1682,41 @@ gf_status run_batched(gf_ctx *ctx, const DProg &p, const gf_instance *inst, int 
     }
     BatchEntry *hb = (BatchEntry *)ctx->h_batch;
     DInst *hi = (DInst *)((char *)ctx->h_batch + (size_t)4096 * sizeof(BatchEntry));
+    auto entry = [&](int i, int m) {
+        BatchEntry e;
+        e.inst = i;
+        e.member = m;
+        e.gsize = g[i];
+        e.tile_y = ty[i];
+        e.part_off = off[i];
+        return e;
+    };
     int wg = 0;
-    for (int i = 0; i < n_inst; ++i) {
-        for (int m = 0; m < g[i]; ++m, ++wg) {
-            hb[wg].inst = i;
-            hb[wg].member = m;
-            hb[wg].gsize = g[i];
-            hb[wg].pad_ = 0;
-            hb[wg].part_off = off[i];
+    if (aligned) {
+        std::vector<std::vector<BatchEntry>> lists(kNumXcd);
+        size_t longest = 0;
+        for (int x = 0; x < kNumXcd; ++x) {
+            for (int i : on[x])
+                for (int m = 0; m < g[i]; ++m)
+                    lists[x].push_back(entry(i, m));
+            longest = std::max(longest, lists[x].size());
         }
+        wg = (int)(longest * kNumXcd);
+        (void)grid;
+        BatchEntry idle;
+        std::memset(&idle, 0, sizeof idle);
+        idle.inst = -1;
+        for (int b = 0; b < wg; ++b) {
+            const auto &l = lists[b % kNumXcd];
+            const size_t r = (size_t)(b / kNumXcd);
+            hb[b] = r < l.size() ? l[r] : idle;
+        }
+    } else {
+        for (int i = 0; i < n_inst; ++i)
+            for (int m = 0; m < g[i]; ++m)
+                hb[wg++] = entry(i, m);
+    }
+    for (int i = 0; i < n_inst; ++i) {
         std::memcpy(hi[i].arr, inst[i].arr, sizeof hi[i].arr);
         hi[i].scal = inst[i].scal;
         std::memcpy(hi[i].ip, inst[i].ip, sizeof hi[i].ip);
@@ -1607,9 +1731,10 @@ gf_status run_batched(gf_ctx *ctx, const DProg &p, const gf_instance *inst, int 
     if (e != hipSuccess)
         return hipfail(ctx, e, "batch table copy");
     ctx->batch_pending = true;
-    BatchTable bt{db, di};
+    BatchTable bt{db, di, aligned ? 1 : 0};
     DInst dummy;
     std::memset(&dummy, 0, sizeof dummy);
+    ctx->scr.epoch += 1;
     e = launch_persistent(p, dummy, t, wg, ctx->scr, ring_of(ctx), stream, &bt);
     if (e != hipSuccess)
         return hipfail(ctx, e, "batched persistent launch");
@@ -1645,7 +1770,7 @@ struct CandidateNote {
 };
 
 int32_t tune_fallback(gf_ctx *ctx, const gf_program *prog, const DProg &p, const gf_instance *inst, int n_inst,
-                      int mode, hipStream_t s, gf_launch *out, bool *cached);
+                      int mode, hipStream_t s, gf_launch *out, bool *cached, std::vector<gf_launch> *per);
 }  // namespace
 
 // Kernel split: the main kernel (one thread) runs on `stream`; its region
@@ -1673,7 +1798,6 @@ gf_status run_kernel_split(gf_ctx *ctx, const DProg &p, const gf_instance &in, i
         if (launch)
             sp.l = *launch;
         sp.regions = sp.launches = sp.max_grid = 0;
-        sp.j3runs = 0;
     }
     DInst di;
     std::memcpy(di.arr, in.arr, sizeof di.arr);
@@ -1737,7 +1861,8 @@ int32_t gf_persistent_capacity(gf_ctx *ctx, const gf_program *prog, int32_t wg_s
 }
 
 static gf_status region_run(gf_ctx *ctx, const gf_program *prog, const gf_instance *inst, int32_t n_inst,
-                            int32_t mode, const gf_launch *launch, gf_run_stats *stats, void *hip_stream);
+                            int32_t mode, const gf_launch *launch, gf_run_stats *stats, void *hip_stream,
+                            const InstShape *shape = nullptr);
 
 gf_status gf_region_run(gf_ctx *ctx, const gf_program *prog, const gf_instance *inst, int32_t n_inst, int32_t mode,
                         const gf_launch *launch, gf_run_stats *stats, void *hip_stream)
@@ -1756,7 +1881,8 @@ gf_status gf_region_run(gf_ctx *ctx, const gf_program *prog, const gf_instance *
 }
 
 static gf_status region_run(gf_ctx *ctx, const gf_program *prog, const gf_instance *inst, int32_t n_inst,
-                            int32_t mode, const gf_launch *launch, gf_run_stats *stats, void *hip_stream)
+                            int32_t mode, const gf_launch *launch, gf_run_stats *stats, void *hip_stream,
+                            const InstShape *shape)
 {
     if (!inst || n_inst < 1 || n_inst > GF_MAX_INSTANCES)
         return fail(ctx, GF_EINVAL, "need 1..%d instances", GF_MAX_INSTANCES);
@@ -1771,7 +1897,7 @@ static gf_status region_run(gf_ctx *ctx, const gf_program *prog, const gf_instan
     hipStream_t stream = (hipStream_t)hip_stream;
     gf_launch predicted;
     CandidateNote note{stats, -1};
-    if (!launch && !ctx->pred_params.empty()) {
+    if (!launch && !shape && !ctx->pred_params.empty()) {
         int32_t k = predict_launch(ctx, p, inst, n_inst, mode, stream, &predicted);
         if (k < -1)
             return (gf_status)k;
@@ -1783,9 +1909,24 @@ static gf_status region_run(gf_ctx *ctx, const gf_program *prog, const gf_instan
             // the predictor defers (outside its training distribution, or
             // no runnable shape it knows): the autotuner decides
             bool cached = false;
-            k = tune_fallback(ctx, prog, p, inst, n_inst, mode, stream, &predicted, &cached);
+            std::vector<gf_launch> per;
+            k = tune_fallback(ctx, prog, p, inst, n_inst, mode, stream, &predicted, &cached, &per);
             if (k < -1)
                 return (gf_status)k;
+            if (!per.empty()) {
+                // a batched persistent run: the autotuner chose a shape per instance
+                std::vector<InstShape> sh(n_inst);
+                for (int i = 0; i < n_inst; ++i) {
+                    sh[i].tile_y = per[i].tile_y;
+                    sh[i].weight = (double)per[i].num_wg;
+                }
+                gf_launch common = per[0];
+                common.num_wg = 0;
+                common.tile_y = 0;
+                note.cand = -1;
+                note.source = cached ? GF_LAUNCH_TUNED_CACHED : GF_LAUNCH_TUNED;
+                return region_run(ctx, prog, inst, n_inst, mode, &common, stats, hip_stream, sh.data());
+            }
             if (k >= 0) {
                 note.cand = k;
                 note.source = cached ? GF_LAUNCH_TUNED_CACHED : GF_LAUNCH_TUNED;
@@ -1796,9 +1937,21 @@ static gf_status region_run(gf_ctx *ctx, const gf_program *prog, const gf_instan
     Tiling t = choose_tiling(p, launch);
     if ((st = check_tiling(ctx, p, t)) != GF_OK)
         return st;
-    for (int i = 0; i < n_inst; ++i)
-        if ((st = check_instance(ctx, p, inst[i], t, i)) != GF_OK)
+    // per instance: its own rows per tile when a shape gives them (the 3D
+    // stencil's rows are compiled into the kernel, so they must agree)
+    std::vector<Tiling> ti(n_inst, t);
+    for (int i = 0; i < n_inst; ++i) {
+        if (shape && shape[i].tile_y > 0) {
+            if ((program_region_mask(p) & (1u << GF_R_JACOBI3D)) && shape[i].tile_y != t.tile_y)
+                return fail(ctx, GF_EINVAL, "instance %d: 3D stencil rows per tile %d differ from the launch's %d", i,
+                            shape[i].tile_y, t.tile_y);
+            ti[i].tile_y = shape[i].tile_y;
+            if ((st = check_tiling(ctx, p, ti[i])) != GF_OK)
+                return st;
+        }
+        if ((st = check_instance(ctx, p, inst[i], ti[i], i)) != GF_OK)
             return st;
+    }
     if (stats)
         std::memset(stats, 0, sizeof *stats);
 
@@ -1808,7 +1961,7 @@ static gf_status region_run(gf_ctx *ctx, const gf_program *prog, const gf_instan
         if (cap <= 0)
             return fail(ctx, GF_EHIP, "occupancy query failed");
         if (n_inst > 1)
-            return run_batched(ctx, p, inst, n_inst, t, launch, cap, stats, stream);
+            return run_batched(ctx, p, inst, n_inst, t, launch, cap, stats, stream, shape);
         for (int i = 0; i < n_inst; ++i) {
             // default grid: at most two workgroups per CU (the grid barrier's
             // cost grows with the number of members), sized so that every
@@ -1867,14 +2020,16 @@ static gf_status region_run(gf_ctx *ctx, const gf_program *prog, const gf_instan
 
     if (mode == GF_EXEC_PER_REGION) {
         for (int i = 0; i < n_inst; ++i)
-            if ((st = enqueue_per_region(ctx, p, inst[i], i, t, launch, stream, stats)) != GF_OK)
+            if ((st = enqueue_per_region(ctx, p, inst[i], i, ti[i], launch, stream, stats)) != GF_OK)
                 return st;
         return GF_OK;
     }
 
     // GF_EXEC_PER_REGION_GRAPH: capture the per-region launch sequence once
-    // per (program, bindings, tiling, stream) and replay it.
-    const std::string key = graph_key(p, inst, n_inst, t, launch, stream);
+    // per (program, bindings, tilings, stream) and replay it.
+    std::string key = graph_key(p, inst, n_inst, t, launch, stream);
+    for (int i = 0; shape && i < n_inst; ++i)
+        key.append((const char *)&ti[i].tile_y, sizeof ti[i].tile_y);
     auto it = ctx->graphs.find(key);
     if (it == ctx->graphs.end()) {
         hipStream_t cs = ctx->capture_stream;
@@ -1885,7 +2040,7 @@ static gf_status region_run(gf_ctx *ctx, const gf_program *prog, const gf_instan
             return hipfail(ctx, e, "begin capture");
         gf_run_stats tmp{};
         for (int i = 0; i < n_inst && st == GF_OK; ++i)
-            st = enqueue_per_region(ctx, p, inst[i], i, t, launch, cs, &tmp);
+            st = enqueue_per_region(ctx, p, inst[i], i, ti[i], launch, cs, &tmp);
         hipGraph_t g = nullptr;
         e = hipStreamEndCapture(cs, &g);
         if (st != GF_OK) {
@@ -2051,7 +2206,8 @@ gf_launch decode_candidate(const DProg &p, const gf_instance &in, int c, int num
         l.xcd_remap = 1;
         l.num_wg = h ? 3 * num_cu : 0;  // three workgroups per CU, or the default grid
     } else if (m & (1u << GF_R_JACOBI2D)) {
-        l.tile_y = ty[a];
+        static const int seg[4] = {2, 8, 32, 128};
+        l.tile_y = seg[a];
         l.wg_size = wg[b];
         l.xcd_remap = 1 - h;
     } else {
@@ -2260,12 +2416,13 @@ std::string fallback_key(const DProg &p, const gf_instance *inst, int n_inst, in
 // graph runs are tuned as per-region launches. Returns the candidate index,
 // -1 if none could run, or a negative gf_status below -1 on failure.
 int32_t tune_fallback(gf_ctx *ctx, const gf_program *prog, const DProg &p, const gf_instance *inst, int n_inst,
-                      int mode, hipStream_t s, gf_launch *out, bool *cached)
+                      int mode, hipStream_t s, gf_launch *out, bool *cached, std::vector<gf_launch> *per)
 {
     const std::string key = fallback_key(p, inst, n_inst, mode);
     auto hit = ctx->tuned.find(key);
     if (hit != ctx->tuned.end()) {
         *out = hit->second.launch;
+        *per = hit->second.per;
         *cached = true;
         return hit->second.cand;
     }
@@ -2309,7 +2466,20 @@ int32_t tune_fallback(gf_ctx *ctx, const gf_program *prog, const DProg &p, const
             st = hipfail(ctx, e, "autotuner fallback: copying the instance");
     }
     int32_t best = -1;
-    if (st == GF_OK) {
+    if (st == GF_OK && n_inst > 1 && mode == GF_EXEC_PERSISTENT) {
+        // batched persistent run: a shape per instance (gf_tune_batched)
+        std::vector<gf_launch> outs(n_inst);
+        float ms = 0.0f;
+        const int32_t ran = gf_tune_batched(ctx, &tp, tinst.data(), n_inst, 3, outs.data(), &ms, s);
+        if (ran < 0) {
+            st = (gf_status)ran;
+        } else {
+            *out = outs[0];
+            *per = outs;
+            best = 0;
+            ctx->tuned[key] = {outs[0], -1, outs};
+        }
+    } else if (st == GF_OK) {
         gf_launch cand[GF_NUM_CANDIDATES];
         float ms[GF_NUM_CANDIDATES];
         const int32_t nc = gf_tune_candidates(ctx, &tp, tinst.data(), cand);
@@ -2322,7 +2492,7 @@ int32_t tune_fallback(gf_ctx *ctx, const gf_program *prog, const DProg &p, const
                 st = (gf_status)ran;
             else if (best >= 0) {
                 *out = cand[best];
-                ctx->tuned[key] = {cand[best], best};
+                ctx->tuned[key] = {cand[best], best, {}};
             }
         }
     }
@@ -2381,6 +2551,57 @@ int32_t gf_tune_pick(const float *ms, int32_t n)
         if (std::isfinite(ms[i]) && (best < 0 || ms[i] < ms[best]))
             best = i;
     return best;
+}
+
+int32_t gf_batch_plan(int32_t n_inst, const int64_t *items, const double *weights, int32_t budget, int32_t align,
+                      int32_t *group, int32_t *xcd)
+{
+    if (n_inst < 1 || n_inst > GF_MAX_INSTANCES || !items || !group || !xcd || budget < n_inst || budget > 4096)
+        return GF_EINVAL;
+    std::vector<int64_t> it(items, items + n_inst);
+    std::vector<double> w(n_inst);
+    for (int i = 0; i < n_inst; ++i) {
+        if (it[i] < 1)
+            return GF_EINVAL;
+        w[i] = (weights && weights[i] > 0.0) ? weights[i] : (double)it[i];
+    }
+    std::vector<int> g(n_inst, 1), x(n_inst, -1);
+    const int grid = plan_batch(n_inst, it, w, budget, align != 0, g, x);
+    for (int i = 0; i < n_inst; ++i) {
+        group[i] = g[i];
+        xcd[i] = x[i];
+    }
+    return grid;
+}
+
+gf_status gf_region_run_batched(gf_ctx *ctx, const gf_program *prog, const gf_instance *inst, int32_t n_inst,
+                                int32_t mode, const gf_launch *launches, gf_run_stats *stats, void *hip_stream)
+{
+    if (!ctx)
+        return GF_EINVAL;
+    if (!launches || !inst || n_inst < 1 || n_inst > GF_MAX_INSTANCES)
+        return fail(ctx, GF_EINVAL, "need 1..%d instances and as many launches", GF_MAX_INSTANCES);
+    if (mode == GF_EXEC_KERNEL_SPLIT)
+        return fail(ctx, GF_EUNSUPPORTED, "the kernel split runs one instance");
+    std::vector<InstShape> sh(n_inst);
+    for (int i = 0; i < n_inst; ++i) {
+        if (launches[i].tile_y < 0 || launches[i].num_wg < 0)
+            return fail(ctx, GF_EINVAL, "instance %d: negative rows per tile or weight", i);
+        sh[i].tile_y = launches[i].tile_y;
+        sh[i].weight = (double)launches[i].num_wg;
+    }
+    gf_launch common = launches[0];
+    common.num_wg = 0;
+    common.tile_y = 0;
+    hipSetDevice(ctx->device);
+    hipStream_t s = (hipStream_t)hip_stream;
+    gf_status st = order_before(ctx, s);
+    if (st != GF_OK)
+        return st;
+    st = region_run(ctx, prog, inst, n_inst, mode, &common, stats, hip_stream, sh.data());
+    if (st == GF_OK)
+        mark_after(ctx, s);
+    return st;
 }
 
 int32_t gf_tune_candidates(gf_ctx *ctx, const gf_program *prog, const gf_instance *inst, gf_launch *out)
@@ -2447,6 +2668,153 @@ int32_t gf_tune(gf_ctx *ctx, const gf_program *prog, const gf_instance *inst, in
         *best_index = gf_tune_pick(ms_out, (int32_t)cands.size());
     ctx->err.clear();
     return ran;
+}
+
+int32_t gf_tune_batched(gf_ctx *ctx, const gf_program *prog, const gf_instance *inst, int32_t n_inst, int32_t reps,
+                        gf_launch *out, float *best_ms, void *hip_stream)
+{
+    if (!ctx || !prog || !inst || !out || n_inst < 1 || n_inst > GF_MAX_INSTANCES || reps < 1)
+        return GF_EINVAL;
+    DProg p;
+    gf_status st = build_program(ctx, prog, &p);
+    if (st != GF_OK)
+        return st;
+    hipSetDevice(ctx->device);
+    hipStream_t s = (hipStream_t)hip_stream;
+    const int mode = GF_EXEC_PERSISTENT;
+    hipEvent_t e0, e1;
+    if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess)
+        return fail(ctx, GF_EHIP, "event create");
+    int32_t timed = 0;
+    // median of reps timed runs after one warm-up; +inf if the run fails
+    auto time_run = [&](const std::vector<gf_instance> &in, const gf_launch &common,
+                        const std::vector<gf_launch> &per, int *grid) -> float {
+        gf_run_stats rs{};
+        if (gf_region_run_batched(ctx, prog, in.data(), (int32_t)in.size(), mode, per.data(), &rs, hip_stream) !=
+            GF_OK)
+            return INFINITY;
+        std::vector<float> t(reps);
+        for (int r = 0; r < reps; ++r) {
+            hipEventRecord(e0, s);
+            if (gf_region_run_batched(ctx, prog, in.data(), (int32_t)in.size(), mode, per.data(), nullptr,
+                                      hip_stream) != GF_OK)
+                return INFINITY;
+            hipEventRecord(e1, s);
+            if (hipEventSynchronize(e1) != hipSuccess)
+                return INFINITY;
+            hipEventElapsedTime(&t[r], e0, e1);
+        }
+        if (gf_sync(ctx, hip_stream, nullptr) != GF_OK)
+            return INFINITY;
+        (void)common;
+        ++timed;
+        if (grid)
+            *grid = rs.num_wg;
+        std::sort(t.begin(), t.end());
+        return t[reps / 2];
+    };
+    std::vector<gf_instance> all(inst, inst + n_inst);
+    std::vector<gf_launch> best(n_inst);
+    float best_t = INFINITY;
+    const bool has2d = (program_region_mask(p) & (1u << GF_R_JACOBI2D)) != 0;
+    if (!has2d) {
+        // one common shape from the single-program candidates, item weights
+        gf_launch cand[GF_NUM_CANDIDATES];
+        if (gf_tune_candidates(ctx, prog, inst, cand) < 0) {
+            hipEventDestroy(e0);
+            hipEventDestroy(e1);
+            return GF_EINVAL;
+        }
+        for (int c = 0; c < GF_NUM_CANDIDATES; ++c) {
+            std::vector<gf_launch> per(n_inst, cand[c]);
+            for (auto &l : per)
+                l.num_wg = 0;
+            const float ms = time_run(all, cand[c], per, nullptr);
+            if (ms < best_t) {
+                best_t = ms;
+                best = per;
+            }
+        }
+    } else {
+        // size classes of the first stencil size
+        std::vector<int> cls(n_inst);
+        std::map<int, std::vector<int>> members;
+        for (int i = 0; i < n_inst; ++i) {
+            const int64_t n = std::max<int64_t>(1, first_stencil_size(p, inst[i]));
+            int c = 0;
+            while ((n >> (c + 1)) > 0)
+                ++c;
+            cls[i] = c;
+            members[c].push_back(i);
+        }
+        static const int kWg[3] = {64, 128, 256};
+        static const int kSeg[5] = {8, 16, 32, 64, 128};
+        for (int wgs : kWg) {
+            gf_launch common;
+            std::memset(&common, 0, sizeof common);
+            common.wg_size = wgs;
+            common.xcd_remap = 1;
+            std::map<int, int> seg_of;
+            std::map<int, double> cost_of;
+            for (auto &kv : members) {
+                std::vector<gf_instance> sub;
+                for (int i : kv.second)
+                    sub.push_back(inst[i]);
+                float bt = INFINITY;
+                int bs = kSeg[2], bgrid = 0;
+                for (int sg : kSeg) {
+                    std::vector<gf_launch> per(sub.size(), common);
+                    for (auto &l : per)
+                        l.tile_y = sg;
+                    int grid = 0;
+                    const float ms = time_run(sub, common, per, &grid);
+                    if (ms < bt) {
+                        bt = ms;
+                        bs = sg;
+                        bgrid = grid;
+                    }
+                }
+                seg_of[kv.first] = bs;
+                // workgroup-milliseconds per work item at the chosen rows
+                double items = 0.0;
+                Tiling tt = choose_tiling(p, &common);
+                tt.tile_y = bs;
+                for (int i : kv.second)
+                    items += (double)std::max<int64_t>(1, max_items(p, inst[i], tt));
+                cost_of[kv.first] = std::isfinite(bt) ? (double)bt * std::max(1, bgrid) / items : 0.0;
+            }
+            for (int variant = 0; variant < 2; ++variant) {
+                std::vector<gf_launch> per(n_inst, common);
+                double wmax = 0.0;
+                std::vector<double> wv(n_inst, 0.0);
+                for (int i = 0; i < n_inst; ++i) {
+                    per[i].tile_y = seg_of[cls[i]];
+                    Tiling tt = choose_tiling(p, &common);
+                    tt.tile_y = per[i].tile_y;
+                    const double items = (double)std::max<int64_t>(1, max_items(p, inst[i], tt));
+                    wv[i] = variant == 0 ? items * cost_of[cls[i]] : items;
+                    wmax = std::max(wmax, wv[i]);
+                }
+                for (int i = 0; i < n_inst; ++i)
+                    per[i].num_wg = wmax > 0.0 ? std::max(1, (int)std::lround(1e6 * wv[i] / wmax)) : 0;
+                const float ms = time_run(all, common, per, nullptr);
+                if (ms < best_t) {
+                    best_t = ms;
+                    best = per;
+                }
+            }
+        }
+    }
+    hipEventDestroy(e0);
+    hipEventDestroy(e1);
+    if (!std::isfinite(best_t))
+        return fail(ctx, GF_EINVAL, "no batched configuration could run");
+    for (int i = 0; i < n_inst; ++i)
+        out[i] = best[i];
+    if (best_ms)
+        *best_ms = best_t;
+    ctx->err.clear();
+    return timed;
 }
 
 }  // extern "C"

@@ -282,6 +282,34 @@ __device__ __forceinline__ bool flat_barrier(uint32_t *line, uint32_t nmembers, 
     return bs->ok != 0;
 }
 
+// Group barrier of a batched group whose members all run on one XCD (checked
+// when the launch starts): the members share that XCD's L2, so a member's
+// stores are visible to the others once acknowledged, and no L2 write-back
+// is needed; waiters invalidate their own caches (agent-scope acquire). The
+// last arrival resets the count before it moves the generation.
+__device__ __forceinline__ bool local_group_barrier(uint32_t *line, uint32_t nmembers, BarrierState *bs, int32_t *err,
+                                                    int64_t timeout_ticks)
+{
+    wg_settle();
+    if (threadIdx.x == 0) {
+        const uint32_t g = bs->gen;
+        int32_t ok = 1;
+        const uint32_t a = __hip_atomic_fetch_add(&line[0], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        if (a == nmembers - 1) {
+            __hip_atomic_store(&line[0], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            __builtin_amdgcn_s_waitcnt(0x0F70);  // the reset has landed before the generation moves
+            __hip_atomic_store(&line[1], g + 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        } else {
+            ok = barrier_wait(&line[1], g, err, timeout_ticks) ? 1 : 0;
+        }
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+        bs->gen = g + 1u;
+        bs->ok = ok;
+    }
+    __syncthreads();
+    return bs->ok != 0;
+}
+
 // ---------------------------------------------------------------------------
 // XCD-aware grid barrier. The L2 is per XCD, so what the release and acquire
 // fences of the tree barrier do per workgroup (write the XCD's L2 back,

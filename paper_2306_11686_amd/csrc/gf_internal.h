@@ -52,18 +52,24 @@ struct DInst {
 // Batched persistent launch: workgroup b of the grid belongs to instance
 // `inst` as member `member` of a group of `gsize` workgroups; the group's
 // barrier lives on line kGroupLine0 + inst; its reduction partials start at
-// `part_off` in each half of the partials buffer.
+// `part_off` in each half of the partials buffer; `tile_y` (> 0) replaces the
+// launch's rows per tile for this instance. inst < 0: an idle workgroup.
 struct BatchEntry {
     int32_t inst;
     int32_t member;
     int32_t gsize;
-    int32_t pad_;
+    int32_t tile_y;
     int64_t part_off;
 };
 
+// aligned = 1: the table places every group on one XCD, assuming workgroup b
+// runs on XCD b mod 8 (the round-robin dispatch); the kernel checks that at
+// start and falls back to the cross-XCD group barrier if any workgroup is
+// elsewhere.
 struct BatchTable {
     const BatchEntry *wg;   // gridDim.x entries
     const DInst *inst;      // per-instance bindings
+    int32_t aligned;
 };
 
 // Tiling chosen on the host; identical in every workgroup of a launch.
@@ -74,12 +80,7 @@ struct Tiling {
     int32_t items;
     int32_t xcd_remap;
     int32_t prefetch;  // 3D stencil: planes requested ahead of the one computed (1 or 2)
-    int32_t zalt;      // 3D stencil (even n): successive executions alternate the z direction
 };
-
-// Step flag set by the per-region launchers on a 3D stencil execution that
-// marches its z segments downwards (Tiling::zalt, odd-numbered executions).
-constexpr uint32_t kStepZRev = 1u << 30;
 
 // One RPC request slot in pinned, coherent host memory (cf. the paper's
 // RPCInfo / RPCArgInfo records, Section 3.2): the device fills the body,
@@ -205,7 +206,10 @@ constexpr int kFinalizeSubLine0 = kXcdBadLine + 1;
 // workgroups fold a MAX reduction with one atomic each; regions alternate
 // between them.
 constexpr int kMaxSlotLine0 = kFinalizeSubLine0 + GF_MAX_INSTANCES * kNumXcd;
-constexpr int kNumLines = kMaxSlotLine0 + 2;
+// Count of the workgroups of a batched launch that found themselves on
+// another XCD than their table entry assumes (epoch << 32 | count).
+constexpr int kBatchPlaceLine = kMaxSlotLine0 + 2;
+constexpr int kNumLines = kBatchPlaceLine + 1;
 
 // A serial step attached to a per-region launch, with its array operand
 // resolved on the host (SWAPs are applied by the host while it walks the

@@ -40,11 +40,13 @@ __host__ __device__ inline StencilGeom j3v2_geom(int64_t n, const Tiling &t)
     return g;
 }
 
+// 2D: a work item is a chunk of columns (two per thread for even n, one for
+// odd n) times a segment of tile_y rows that the workgroup marches through.
 __host__ __device__ inline StencilGeom j2_geom(int64_t n, const Tiling &t)
 {
     StencilGeom g;
     const int64_t interior = n > 2 ? n - 2 : 0;
-    g.nxc = cdiv(n, t.wg_size);
+    g.nxc = cdiv(n, ((n & 1) ? 1 : 2) * (int64_t)t.wg_size);
     g.nyt = cdiv(interior, t.tile_y);
     g.nzs = 1;
     return g;
@@ -245,18 +247,15 @@ __device__ __forceinline__ gf_d2 ld_row(GF_GLOBAL const double *p, int r)
     return *(GF_GLOBAL const gf_d2 *)p;
 }
 
-// One tile of planes [z0, z1), marched upwards (dir = +1) or downwards
-// (dir = -1). PF (1 or 2) planes ahead of the computed plane z are in
-// flight: registers hold the plane behind z (own rows), z, the plane ahead
-// and, for PF = 2, the one after it, while the next plane is requested at
-// the top of the step. The two z-neighbours enter one addition, so marching
-// downwards gives the same bits (the sum of two doubles does not depend on
-// their order). The two depths are written out separately: folding them
-// into one ring array cost a fifth of the bandwidth at depth 1 (measured).
+// One tile of planes [z0, z1). PF (1 or 2) planes ahead of the computed
+// plane z are in flight: registers hold planes z-1 (own rows), z, z+1 and,
+// for PF = 2, z+2, while the next plane is requested at the top of the step.
+// The two depths are written out separately: folding them into one ring
+// array cost a fifth of the bandwidth at depth 1 (measured).
 template <int TY, int PF, bool FULL>
 __device__ __forceinline__ double j3v2_tile(GF_GLOBAL const double *__restrict__ u, GF_GLOBAL double *__restrict__ w,
                                             int64_t n, int64_t x, int64_t y0, int ny, int64_t z0, int64_t z1,
-                                            int dir, bool want_red)
+                                            bool want_red)
 {
     static_assert(PF == 1 || PF == 2, "prefetch depth 1 or 2");
     __shared__ double s_edge[2][kMaxWg / kWave][TY][2];
@@ -270,42 +269,37 @@ __device__ __forceinline__ double j3v2_tile(GF_GLOBAL const double *__restrict__
     const bool gather_l = wv == 0 && lane == 0 && xs >= 1;
     const bool gather_r = wv == nw - 1 && lane == kWave - 1 && xs + 2 <= n - 1;
     const int64_t SY = n, SZ = n * n;
-    const int64_t DZ = dir * SZ;                   // one plane in the marching direction
-    const int64_t cnt = z1 - z0;                   // planes computed
-    const int64_t zb = dir > 0 ? z0 : z1 - 1;      // first plane computed
     const double c6 = 1.0 / 6.0;
     double mx = -INFINITY;
-    // pm: the plane behind z (own rows); pc: plane z; pn: the plane ahead;
-    // pa: the one after it (PF = 2); pf: the plane being requested
+    // pm: plane z-1 (own rows); pc: plane z; pn: plane z+1; pa: z+2 (PF = 2);
+    // pf: the plane being requested (z+1+PF)
     gf_d2 pm[TY], pc[TY + 2], pn[TY + 2], pa[PF == 2 ? TY + 2 : 1], pf[TY + 2];
     const gf_d2 zero2 = {0.0, 0.0};
-    GF_GLOBAL const double *col = u + (y0 - 1) * SY + xs + zb * SZ;  // row y0-1 of plane zb
+    GF_GLOBAL const double *col = u + (y0 - 1) * SY + xs;  // row y0-1 of plane 0
 #pragma unroll
     for (int r = 0; r < TY; ++r)
-        pm[r] = (FULL || r < ny) ? ld_row<TY>(col - DZ + (r + 1) * SY, r + 1) : zero2;
-    // the first plane and the one ahead exist (both within [z0-1, z1]); the
-    // plane after may be past the segment
+        pm[r] = (FULL || r < ny) ? ld_row<TY>(col + (z0 - 1) * SZ + (r + 1) * SY, r + 1) : zero2;
+    // planes z0 and z0+1 exist (z0+1 <= z1 <= n-1); z0+2 may be past the grid
 #pragma unroll
     for (int r = 0; r < TY + 2; ++r) {
-        pc[r] = (FULL || r < ny + 2) ? ld_row<TY>(col + r * SY, r) : zero2;
-        pn[r] = (FULL || r < ny + 2) ? ld_row<TY>(col + DZ + r * SY, r) : zero2;
+        pc[r] = (FULL || r < ny + 2) ? ld_row<TY>(col + z0 * SZ + r * SY, r) : zero2;
+        pn[r] = (FULL || r < ny + 2) ? ld_row<TY>(col + (z0 + 1) * SZ + r * SY, r) : zero2;
         pf[r] = zero2;
     }
     if constexpr (PF == 2) {
-        const bool have = cnt >= 2;
+        const bool have = z0 + 2 <= z1;
 #pragma unroll
         for (int r = 0; r < TY + 2; ++r)
-            pa[r] = (have && (FULL || r < ny + 2)) ? ld_row<TY>(col + 2 * DZ + r * SY, r) : zero2;
+            pa[r] = (have && (FULL || r < ny + 2)) ? ld_row<TY>(col + (z0 + 2) * SZ + r * SY, r) : zero2;
     }
-    for (int64_t k = 0; k < cnt; ++k) {
-        const int64_t z = zb + k * dir;
-        if (k + 1 + PF <= cnt) {
+    for (int64_t z = z0; z < z1; ++z) {
+        if (z + 1 + PF <= z1) {
 #pragma unroll
             for (int r = 0; r < TY + 2; ++r)
                 if (FULL || r < ny + 2)
-                    pf[r] = ld_row<TY>(col + (k + 1 + PF) * DZ + r * SY, r);
+                    pf[r] = ld_row<TY>(col + (z + 1 + PF) * SZ + r * SY, r);
         }
-        const int par = (int)(k & 1);
+        const int par = (int)(z & 1);
         if (lane == 0) {
 #pragma unroll
             for (int r = 0; r < TY; ++r)
@@ -379,12 +373,9 @@ __device__ __forceinline__ double j3v2_tile(GF_GLOBAL const double *__restrict__
     return mx;
 }
 
-// zrev: march the segment downwards (successive sweeps alternate, so each
-// starts on the planes the previous one wrote last, which the memory-side
-// cache may still hold).
 template <int TY, int PF>
 __device__ __forceinline__ double j3v2_item(const double *u_, double *w_, int64_t n, int64_t item, const Tiling &t,
-                                            bool zrev, bool want_red)
+                                            bool want_red)
 {
     const StencilGeom g = j3v2_geom(n, t);
     const int64_t xc = item % g.nxc;
@@ -396,49 +387,153 @@ __device__ __forceinline__ double j3v2_item(const double *u_, double *w_, int64_
     const int ny = (int)(n - 1 - y0 < TY ? n - 1 - y0 : TY);
     const int64_t z0 = 1 + zs * t.tile_z;
     const int64_t z1 = (z0 + t.tile_z < n - 1) ? z0 + t.tile_z : n - 1;
-    const int dir = zrev ? -1 : 1;
     if (ny == TY)
-        return j3v2_tile<TY, PF, true>(gptr(u_), gptr(w_), n, x, y0, ny, z0, z1, dir, want_red);
-    return j3v2_tile<TY, PF, false>(gptr(u_), gptr(w_), n, x, y0, ny, z0, z1, dir, want_red);
+        return j3v2_tile<TY, PF, true>(gptr(u_), gptr(w_), n, x, y0, ny, z0, z1, want_red);
+    return j3v2_tile<TY, PF, false>(gptr(u_), gptr(w_), n, x, y0, ny, z0, z1, want_red);
 }
 
-// 2D 5-point Jacobi: the workgroup owns (row chunk) x (TY rows); each thread
-// holds its column of TY+2 rows in registers.
-template <int TY>
-__device__ __forceinline__ double j2_item(const double *u_, double *w_, int64_t n, int64_t item, const Tiling &t,
-                                          bool want_red)
+// 2D 5-point Jacobi. The workgroup owns a chunk of columns and marches down
+// a segment of rows [y0, y1): each thread owns W adjacent columns (W = 2, one
+// 16-byte access per row, for even n; W = 1 for odd n, whose rows are not
+// 16-byte aligned) and keeps rows y-1, y and y+1 in registers while the next
+// kJ2Ahead rows are in flight, so every value of u is fetched once per
+// segment plus two halo rows. x-neighbours come from the adjacent lanes by
+// DPP shifts; the first and last lane of each wavefront also load their
+// outer neighbour with every row (a cache hit: the adjacent wavefront reads
+// that line), so wavefronts never wait for each other. The ring of rows is
+// indexed with compile-time slots (the step loop is unrolled by the ring
+// size). Lanes past the row end load a clamped in-bounds address and store
+// nothing.
+constexpr int kJ2Ahead = 4;
+constexpr int kJ2Ring = kJ2Ahead + 3;
+
+template <int W>
+struct J2Vec {
+    typedef gf_d2 type;
+};
+template <>
+struct J2Vec<1> {
+    typedef double type;
+};
+
+template <int W>
+__device__ __forceinline__ double j2m_seg(GF_GLOBAL const double *__restrict__ u, GF_GLOBAL double *__restrict__ w,
+                                          int64_t n, int64_t x, int64_t y0, int64_t y1, bool want_red)
 {
-    GF_GLOBAL const double *__restrict__ u = gptr(u_);
-    GF_GLOBAL double *__restrict__ w = gptr(w_);
-    const StencilGeom g = j2_geom(n, t);
-    const int64_t xc = item % g.nxc;
-    const int64_t yt = item / g.nxc;
-    const int64_t x = xc * blockDim.x + threadIdx.x;
-    const int64_t y0 = 1 + yt * TY;
-    const int ny = (int)(n - 1 - y0 < TY ? n - 1 - y0 : TY);
+    typedef typename J2Vec<W>::type V;
+    const int lane = threadIdx.x & (kWave - 1);
+    const bool xload = x < n;
+    const int64_t xs = xload ? x : n - W;  // clamped load column (W = 2: even, in bounds)
+    bool in0, in1;
+    if constexpr (W == 2) {
+        in0 = xload && x >= 1;          // column x is interior (x <= n-2 as x is even)
+        in1 = xload && x + 1 <= n - 2;  // column x+1 is interior
+    } else {
+        in0 = xload && x >= 1 && x <= n - 2;
+        in1 = false;
+    }
+    // the wavefront's edge lanes read the neighbour column beyond the
+    // wavefront: lane 0 the one on its left, the last lane the one on its right
+    const int64_t eoff = lane == 0 ? -1 : W;
+    const bool edge = (lane == 0 && xs >= 1) || (lane == kWave - 1 && xs + W <= n - 1);
+    const int64_t L = y1 - y0;  // rows computed; rows y0-1 .. y1 are read
+    GF_GLOBAL const double *base = u + (y0 - 1) * n + xs;
+    auto ld = [&](int64_t j) -> V { return *(GF_GLOBAL const V *)(base + j * n); };
+    V ring[kJ2Ring];
+    double eg[kJ2Ring];
+#pragma unroll
+    for (int j = 0; j < kJ2Ring; ++j) {
+        if constexpr (W == 2)
+            ring[j] = gf_d2{0.0, 0.0};
+        else
+            ring[j] = 0.0;
+        eg[j] = 0.0;
+    }
+    // rows y0-1 and y0 are only needed as the rows above; the edge value of
+    // a row is needed when that row is computed (rows 1 .. L)
+#pragma unroll
+    for (int j = 0; j < kJ2Ahead + 2; ++j)
+        if (j <= L + 1) {
+            ring[j] = ld(j);
+            if (edge && j >= 1 && j <= L)
+                eg[j] = base[j * n + eoff];
+        }
     double acc = 0.0;
-    if (x >= 1 && x <= n - 2) {
-        double col[TY + 2];
-        GF_GLOBAL const double *b = u + (y0 - 1) * n + x;
+    for (int64_t b0 = 0; b0 < L; b0 += kJ2Ring) {
 #pragma unroll
-        for (int r = 0; r < TY + 2; ++r)
-            col[r] = (r < ny + 2) ? b[r * n] : 0.0;
-        GF_GLOBAL double *out = w + y0 * n + x;
-#pragma unroll
-        for (int r = 0; r < TY; ++r) {
-            if (r < ny) {
-                const double xl = b[(r + 1) * n - 1];
-                const double xr = b[(r + 1) * n + 1];
-                const double v = ((xl + xr) + (col[r] + col[r + 2])) * 0.25;
-                out[r * n] = v;
-                if (want_red) {
-                    const double d = v - col[r + 1];
-                    acc = acc + d * d;
+        for (int k = 0; k < kJ2Ring; ++k) {
+            const int64_t i = b0 + k;  // computing row y0 + i from ring slots k, k+1, k+2
+            if (i < L) {
+                const int64_t jl = i + kJ2Ahead + 2;
+                if (jl <= L + 1) {
+                    ring[(k + kJ2Ahead + 2) % kJ2Ring] = ld(jl);
+                    if (edge && jl <= L)
+                        eg[(k + kJ2Ahead + 2) % kJ2Ring] = base[jl * n + eoff];
+                }
+                const V up = ring[k];
+                const V c = ring[(k + 1) % kJ2Ring];
+                const V dn = ring[(k + 2) % kJ2Ring];
+                const double g = eg[(k + 1) % kJ2Ring];
+                double lo, hi;  // this thread's first and last column of the row
+                if constexpr (W == 2) {
+                    lo = c.x;
+                    hi = c.y;
+                } else {
+                    lo = c;
+                    hi = c;
+                }
+                const double sl = wave_shr1(hi);
+                const double sr = wave_shl1(lo);
+                const double xl = lane == 0 ? g : sl;
+                const double xr = lane == kWave - 1 ? g : sr;
+                GF_GLOBAL double *out = w + (y0 + i) * n + xs;
+                if constexpr (W == 2) {
+                    gf_d2 v;
+                    v.x = ((xl + c.y) + (up.x + dn.x)) * 0.25;
+                    v.y = ((c.x + xr) + (up.y + dn.y)) * 0.25;
+                    if (in0 && in1)
+                        *(GF_GLOBAL gf_d2 *)out = v;
+                    else if (in0)
+                        out[0] = v.x;
+                    else if (in1)
+                        out[1] = v.y;
+                    if (want_red) {
+                        if (in0) {
+                            const double d = v.x - c.x;
+                            acc = acc + d * d;
+                        }
+                        if (in1) {
+                            const double d = v.y - c.y;
+                            acc = acc + d * d;
+                        }
+                    }
+                } else {
+                    const double v = ((xl + xr) + (up + dn)) * 0.25;
+                    if (in0) {
+                        out[0] = v;
+                        if (want_red) {
+                            const double d = v - c;
+                            acc = acc + d * d;
+                        }
+                    }
                 }
             }
         }
     }
     return acc;
+}
+
+__device__ __forceinline__ double j2_item(const double *u_, double *w_, int64_t n, int64_t item, const Tiling &t,
+                                          bool want_red)
+{
+    const StencilGeom g = j2_geom(n, t);
+    const int64_t xc = item % g.nxc;
+    const int64_t ys = item / g.nxc;
+    const int64_t y0 = 1 + ys * t.tile_y;
+    const int64_t y1 = (y0 + t.tile_y < n - 1) ? y0 + t.tile_y : n - 1;
+    if (n & 1)
+        return j2m_seg<1>(gptr(u_), gptr(w_), n, xc * blockDim.x + threadIdx.x, y0, y1, want_red);
+    return j2m_seg<2>(gptr(u_), gptr(w_), n, (xc * blockDim.x + threadIdx.x) * 2, y0, y1, want_red);
 }
 
 // CSR SpMV over a block of wg_size/2 rows (CSR-stream): the block's products
@@ -872,20 +967,20 @@ __device__ bool phases_region(GF_GLOBAL double *a, GF_GLOBAL double *b, GF_GLOBA
 // caller); s is the AXPBY coefficient scal[st.sc[1]] * st.c.
 template <unsigned KMASK, int TY, int PF>
 __device__ __forceinline__ double region_item(const DStep &st, void *const *op, double s, int64_t n, int64_t item,
-                                              const Tiling &t, bool zrev)
+                                              const Tiling &t)
 {
     const bool red = st.red_op != GF_OP_NONE;
     switch (st.kind) {
     case GF_R_JACOBI3D:
         if constexpr ((KMASK >> GF_R_JACOBI3D) & 1u) {
             if ((n & 1) == 0)
-                return j3v2_item<TY, PF>((const double *)op[0], (double *)op[1], n, item, t, zrev, red);
+                return j3v2_item<TY, PF>((const double *)op[0], (double *)op[1], n, item, t, red);
             return j3_item<TY>((const double *)op[0], (double *)op[1], n, item, t, red);
         }
         break;
     case GF_R_JACOBI2D:
         if constexpr ((KMASK >> GF_R_JACOBI2D) & 1u)
-            return j2_item<TY>((const double *)op[0], (double *)op[1], n, item, t, red);
+            return j2_item((const double *)op[0], (double *)op[1], n, item, t, red);
         break;
     case GF_R_SPMV:
         if constexpr ((KMASK >> GF_R_SPMV) & 1u) {
@@ -1148,16 +1243,18 @@ constexpr int persistent_min_waves()
 template <unsigned KMASK, int TY, int PF>
 __global__ void __launch_bounds__(family_max_threads<KMASK>())
     __attribute__((amdgpu_waves_per_eu(persistent_min_waves<KMASK, TY, PF>())))
-    k_persistent(DProg prog, DInst inst_arg, Tiling t, Scratch scr, RpcRing rpc, BatchTable batch)
+    k_persistent(DProg prog, DInst inst_arg, Tiling t_arg, Scratch scr, RpcRing rpc, BatchTable batch)
 {
     __shared__ double s_scal[GF_MAX_SCALARS];
     __shared__ void *s_arr[GF_MAX_ARRAYS];
     __shared__ double s_red[kLdsRed];
     __shared__ BarrierState s_bar;
     __shared__ XcdState s_xcd;
+    __shared__ int32_t s_local;
 
     // Single instance: the whole grid, tree or XCD barrier. Batched: this
-    // workgroup's group of its instance, flat group barrier.
+    // workgroup's group of its instance, flat group barrier (the same-XCD
+    // form when the table keeps every group on one XCD).
     const bool batched = batch.wg != nullptr;
     BatchEntry be;
     if (batched) {
@@ -1166,8 +1263,45 @@ __global__ void __launch_bounds__(family_max_threads<KMASK>())
         be.inst = 0;
         be.member = (int32_t)blockIdx.x;
         be.gsize = (int32_t)gridDim.x;
+        be.tile_y = 0;
         be.part_off = 0;
     }
+    if (batched && batch.aligned) {
+        // every workgroup checks that it runs where the table placed it; a
+        // tree barrier over the whole grid makes the count final
+        __shared__ BarrierState s_gbar;
+        uint64_t *place = (uint64_t *)(scr.lines + (int64_t)kBatchPlaceLine * kLineWords);
+        if (threadIdx.x == 0) {
+            s_gbar.gen = __hip_atomic_load(scr.lines + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            s_gbar.ok = 1;
+            const uint32_t bad = hw_xcc_id() != blockIdx.x % kNumXcd ? 1u : 0u;
+            uint64_t old = __hip_atomic_load(place, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            for (;;) {
+                const uint64_t nw = ((uint32_t)(old >> 32) == scr.epoch) ? old + bad
+                                                                           : (((uint64_t)scr.epoch << 32) | bad);
+                if (__hip_atomic_compare_exchange_strong(place, &old, nw, __ATOMIC_RELAXED, __ATOMIC_RELAXED,
+                                                         __HIP_MEMORY_SCOPE_AGENT))
+                    break;
+            }
+        }
+        __syncthreads();
+        if (!tree_barrier(scr.lines + 1, scr.lines + kTreeLine0 * kLineWords, blockIdx.x, gridDim.x, &s_gbar,
+                          scr.error, scr.barrier_timeout_ticks))
+            return;
+        if (threadIdx.x == 0) {
+            const uint64_t v = __hip_atomic_load(place, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            s_local = ((uint32_t)(v >> 32) == scr.epoch && (uint32_t)v == 0u) ? 1 : 0;
+        }
+        __syncthreads();
+        if (be.inst < 0)
+            return;  // an idle entry of the table
+    } else if (threadIdx.x == 0) {
+        s_local = 0;
+    }
+    // rows per tile: this instance's own when the table gives one
+    Tiling t = t_arg;
+    if (batched && be.tile_y > 0)
+        t.tile_y = be.tile_y;
     const DInst &inst = batched ? batch.inst[be.inst] : inst_arg;
     // workgroup-uniform: kept in scalar registers
     const int64_t G = uniform_i64(be.gsize);
@@ -1189,7 +1323,8 @@ __global__ void __launch_bounds__(family_max_threads<KMASK>())
             return true;
         }
         if (batched)
-            return flat_barrier(gline, (uint32_t)G, &s_bar, scr.error, scr.barrier_timeout_ticks);
+            return s_local ? local_group_barrier(gline, (uint32_t)G, &s_bar, scr.error, scr.barrier_timeout_ticks)
+                           : flat_barrier(gline, (uint32_t)G, &s_bar, scr.error, scr.barrier_timeout_ticks);
         if (xmode && s_xcd.use)
             return xcd_barrier(scr.lines, s_xcd, &s_bar, scr.error, scr.barrier_timeout_ticks, reset);
         return tree_barrier(genw, tree, (uint32_t)member, (uint32_t)G, &s_bar, scr.error, scr.barrier_timeout_ticks);
@@ -1223,7 +1358,6 @@ __global__ void __launch_bounds__(family_max_threads<KMASK>())
 
     int parity = 0;   // partials half of the next reduction
     int mparity = 0;  // max slot of the next folded MAX reduction
-    int64_t j3runs = 0;  // 3D stencil executions so far (their z direction alternates with t.zalt)
     const int64_t total = (int64_t)n_pro + (int64_t)prog.iters * prog.n_body;
     // (sidx, iter): the step and the body iteration of flattened step si,
     // advanced incrementally
@@ -1272,14 +1406,12 @@ __global__ void __launch_bounds__(family_max_threads<KMASK>())
                 }
             } else {
                 const int64_t nitems = region_items_dev(st, n, t);
-                const bool zrev = st.kind == GF_R_JACOBI3D && t.zalt && (j3runs & 1);
-                j3runs += st.kind == GF_R_JACOBI3D ? 1 : 0;
                 // fold: this workgroup's max over its items, then one atomic
                 const bool fold = red && st.red_op == GF_OP_MAX && xmode && s_xcd.use;
                 uint64_t *slot = max_slot + (mparity ? kLineWords / 2 : 0);
                 double wmax = -INFINITY;
                 for (int64_t it = worker; it < nitems; it += G) {
-                    double v = region_item<KMASK, TY, PF>(st, op, coef, n, it, t, zrev);
+                    double v = region_item<KMASK, TY, PF>(st, op, coef, n, it, t);
                     if (red) {
                         v = block_reduce_rt(st.red_op, v, s_red);
                         if (fold)
@@ -1415,7 +1547,7 @@ __global__ void __launch_bounds__(family_max_threads<KMASK>()) k_region(RegionLa
         const double coef = (st.kind == GF_R_AXPBY) ? rl.scal[st.sc[1]] * st.c : 0.0;
         const int64_t worker = worker_id(blockIdx.x, G, t.xcd_remap);
         for (int64_t it = worker; it < rl.n_items; it += G) {
-            double v = region_item<KMASK, TY, PF>(st, rl.arr, coef, rl.n, it, t, (st.flags & kStepZRev) != 0);
+            double v = region_item<KMASK, TY, PF>(st, rl.arr, coef, rl.n, it, t);
             if (red) {
                 v = block_reduce_rt(st.red_op, v, s_red);
                 if (threadIdx.x == 0)
@@ -1692,7 +1824,7 @@ typedef void (*RegionFn)(RegionLaunch, Tiling, Scratch, RpcRing);
 template <unsigned F>
 static PersistentFn persistent_for_ty(int ty, int pf)
 {
-    if constexpr (F == kFamVec || F == kFamHist) {
+    if constexpr (F == kFamVec || F == kFamHist || F == kFamJ2) {
         return ty >= 1 && pf == 1 ? k_persistent<F, 1, 1> : nullptr;
     } else {
         if constexpr (F == kFamJ3) {
@@ -1722,7 +1854,7 @@ static PersistentFn persistent_for_ty(int ty, int pf)
 template <unsigned F>
 static RegionFn region_for_ty(int ty, int pf)
 {
-    if constexpr (F == kFamVec || F == kFamHist) {
+    if constexpr (F == kFamVec || F == kFamHist || F == kFamJ2) {
         return ty >= 1 && pf == 1 ? k_region<F, 1, 1> : nullptr;
     } else {
         if constexpr (F == kFamJ3) {
@@ -1755,7 +1887,7 @@ static PersistentFn persistent_fn(unsigned fam, int ty, int pf)
 {
     switch (fam) {
     case kFamJ3: return persistent_for_ty<kFamJ3>(ty, pf);
-    case kFamJ2: return persistent_for_ty<kFamJ2>(ty, 1);
+    case kFamJ2: return persistent_for_ty<kFamJ2>(1, 1);
     case kFamVec: return persistent_for_ty<kFamVec>(1, 1);
     case kFamHist: return persistent_for_ty<kFamHist>(1, 1);
     default: return persistent_for_ty<kFamAll>(ty, 1);
@@ -1766,7 +1898,7 @@ static RegionFn region_fn(int kind, int ty, int pf)
 {
     switch (kind) {
     case GF_R_JACOBI3D: return region_for_ty<kFamJ3>(ty, pf);
-    case GF_R_JACOBI2D: return region_for_ty<kFamJ2>(ty, 1);
+    case GF_R_JACOBI2D: return region_for_ty<kFamJ2>(1, 1);
     case GF_R_HIST: return region_for_ty<kFamHist>(1, 1);
     default: return region_for_ty<kFamVec>(1, 1);
     }
@@ -1821,7 +1953,7 @@ hipError_t launch_persistent(const DProg &prog, const DInst &inst, const Tiling 
     Tiling tt = t;
     Scratch sc = scr;
     RpcRing r = rpc;
-    BatchTable bt{nullptr, nullptr};
+    BatchTable bt{nullptr, nullptr, 0};
     if (batch)
         bt = *batch;
     void *args[] = {&p, &i, &tt, &sc, &r, &bt};
@@ -2029,21 +2161,20 @@ __global__ void __launch_bounds__(kMaxWg) k_copy(const double2 *__restrict__ src
 __global__ void __launch_bounds__(kMaxWg) k_copy_tiles(const double2 *__restrict__ src, double2 *__restrict__ dst,
                                                       int64_t n)
 {
-    // streaming hints on both sides: measured the fastest copy form (1 GiB)
+    // 16-byte accesses with streaming hints on both sides: measured the
+    // fastest copy form (1 GiB)
     const int64_t base = (int64_t)blockIdx.x * blockDim.x * 4 + threadIdx.x;
-    double2 v[4];
+    GF_GLOBAL const gf_d2 *s2 = (GF_GLOBAL const gf_d2 *)src;
+    GF_GLOBAL gf_d2 *d2 = (GF_GLOBAL gf_d2 *)dst;
+    gf_d2 v[4];
 #pragma unroll
     for (int k = 0; k < 4; ++k)
-        if (base + k * blockDim.x < n) {
-            v[k].x = __builtin_nontemporal_load(&src[base + k * blockDim.x].x);
-            v[k].y = __builtin_nontemporal_load(&src[base + k * blockDim.x].y);
-        }
+        if (base + k * blockDim.x < n)
+            v[k] = __builtin_nontemporal_load(s2 + base + k * blockDim.x);
 #pragma unroll
     for (int k = 0; k < 4; ++k)
-        if (base + k * blockDim.x < n) {
-            __builtin_nontemporal_store(v[k].x, &dst[base + k * blockDim.x].x);
-            __builtin_nontemporal_store(v[k].y, &dst[base + k * blockDim.x].y);
-        }
+        if (base + k * blockDim.x < n)
+            __builtin_nontemporal_store(v[k], d2 + base + k * blockDim.x);
 }
 
 hipError_t launch_copy(void *dst, const void *src, int64_t nbytes, int num_wg, hipStream_t s)

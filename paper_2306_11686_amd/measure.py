@@ -20,6 +20,11 @@ import numpy as np
 from . import workloads
 
 MODES = (("persistent", 1), ("per_region", 0), ("per_region_graph", 2), ("kernel_split", 3))
+ONLY_MODES = None  # --modes: restrict every config to these execution modes
+
+
+def modes(sel=MODES):
+    return tuple(m for m in sel if ONLY_MODES is None or m[0] in ONLY_MODES)
 
 
 def log(msg):
@@ -54,14 +59,14 @@ def measure_2d(ctx, gf, programs, tuner, torch, reps):
     launch = _launch(tuner, "jacobi2d_256")
     for pf in (True, False):
         prog, inst, keep, _ = workloads.jacobi2d(ctx, n, sweeps, printf=pf)
-        for name, mode in MODES:
+        for name, mode in modes():
             ms = _time(ctx, torch, lambda: ctx.run(prog, inst, mode=mode, launch=launch), reps)
             ctx.take_output()
             key = name + ("" if pf else "_no_printf")
             out[key] = {"ms_per_run": round(ms, 4), "us_per_region": round(ms * 1e3 / sweeps, 3),
                         "regions_per_s": round(sweeps / (ms * 1e-3), 1),
                         "GBps_cache_resident": round(bpsweep * sweeps / (ms * 1e-3) / 1e9, 1)}
-    for name, _ in MODES:
+    for name, _ in modes():
         out[name]["printf_us_each"] = round((out[name]["ms_per_run"] - out[name + "_no_printf"]["ms_per_run"])
                                             * 1e3 / 10, 3)
     return out
@@ -77,7 +82,7 @@ def measure_cg(ctx, gf, programs, tuner, torch, reps):
     it_b = spmv_b + 16 * N + 8 * N + 3 * 24 * N
     out = {"config": f"cg_27pt_{m}^3_f64_{iters}iters", "rows": N, "nnz": nnz, "alg_bytes_per_iteration": it_b}
     launch = _launch(tuner, "cg_128")
-    for name, mode in MODES:
+    for name, mode in modes():
         reset()
         ms = _time(ctx, torch, lambda: ctx.run(prog, inst, mode=mode, launch=launch), reps)
         out[name] = {"ms_per_run": round(ms, 3), "GBps": round(iters * it_b / (ms * 1e-3) / 1e9, 1),
@@ -91,7 +96,7 @@ def measure_hist(ctx, gf, programs, tuner, torch, reps):
     launch = _launch(tuner, "hist_2^28")
     for dist in ("uniform", "zipf"):
         prog, inst, keep, _ = workloads.histogram(n, 65536, dist)
-        for name, mode in MODES[:2]:
+        for name, mode in modes(MODES[:2]):
             ms = _time(ctx, torch, lambda: ctx.run(prog, inst, mode=mode, launch=launch), reps)
             out[f"{dist}_{name}"] = {"us_per_run": round(ms * 1e3, 1),
                                      "GBps": round(out["alg_bytes"] / (ms * 1e-3) / 1e9, 1)}
@@ -108,8 +113,16 @@ def measure_batched(ctx, gf, programs, tuner, torch, reps):
     out = {"config": "batched_256x_jacobi2d_sides_64_2048_50sweeps", "sum_n2": int(sum(n * n for n in sides)),
            "alg_bytes_per_run": bytes_per_sweepset * sweeps, "regions_per_run": 256 * sweeps}
     launch = _launch(tuner, "batched_256")
-    for name, mode in MODES[:3]:          # the kernel split runs one instance
-        ms = _time(ctx, torch, lambda: ctx.run(prog, insts, mode=mode, launch=launch), reps)
+    per = tuner.lookup_batched("batched_256")   # a shape per instance, from the batched autotuner
+    out["per_instance_shapes"] = per is not None
+
+    def run(mode):
+        if per is not None:
+            return ctx.run_batched(prog, insts, per, mode=mode)
+        return ctx.run(prog, insts, mode=mode, launch=launch)
+
+    for name, mode in modes(MODES[:3]):          # the kernel split runs one instance
+        ms = _time(ctx, torch, lambda: run(mode), reps)
         out[name] = {"ms_per_run": round(ms, 3), "GBps": round(out["alg_bytes_per_run"] / (ms * 1e-3) / 1e9, 1),
                      "regions_per_s": round(256 * sweeps / (ms * 1e-3), 1)}
     return out
@@ -225,7 +238,7 @@ def measure_phases(ctx, gf, programs, tuner, torch, reps):
     inst = gf.Instance.make({0: a, 1: b}, sc, ip=(n,))
     prog = programs.phases(P, shift, owner=False)
     out = {"config": "phases_2^22_f64_100phases", "alg_bytes_per_phase": 16 * n}
-    for name, mode in MODES[:2]:
+    for name, mode in modes(MODES[:2]):
         for nwg in (256, 1024):
             launch = gf.Launch.make(wg_size=256, num_wg=nwg)
             try:
@@ -272,11 +285,25 @@ def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--configs", default="sync,2d,rpc,rpc_fprintf,phases,heap,cg,hist,batched")
     ap.add_argument("--reps", type=int, default=3)
+    ap.add_argument("--modes", default=None, help="comma list of execution modes to run (default: all)")
+    ap.add_argument("--copy-probe", action="store_true",
+                    help="copy 1 GiB three times first (calibrates rocprofv3 byte counters per dispatch)")
     args = ap.parse_args()
+    global ONLY_MODES
+    if args.modes:
+        ONLY_MODES = set(args.modes.split(","))
     import torch
     import paper_2306_11686_amd as gf
     from paper_2306_11686_amd import programs, tuner
     ctx = gf.Context(0, rpc_capture=True, rpc_thread=True)
+    if args.copy_probe:
+        a = torch.zeros(1 << 27, dtype=torch.float64, device="cuda")
+        b = torch.empty_like(a)
+        for _ in range(3):
+            ctx.copy(b, a, 1 << 30, num_wg=0)
+        torch.cuda.synchronize()
+        del a, b
+        torch.cuda.empty_cache()
     fns = {"sync": measure_sync, "2d": measure_2d, "rpc": measure_rpc, "rpc_fprintf": measure_rpc_fprintf,
            "phases": measure_phases, "heap": measure_heap, "cg": measure_cg, "hist": measure_hist,
            "batched": measure_batched}

@@ -3,6 +3,8 @@
     python -m paper_2306_11686_amd.profsum stats KERNEL_STATS_CSV [--top 8]
     python -m paper_2306_11686_amd.profsum positions KERNEL_TRACE_CSV --kernel NAME --period P --count N \\
         [--skip S] [--labels a,b,...]
+    python -m paper_2306_11686_amd.profsum traffic-positions --fetch COUNTER_CSV --write COUNTER_CSV \\
+        --kernel NAME --period P --count N [--skip S] [--labels a,b,...] [--alg b0,b1,...]
     python -m paper_2306_11686_amd.profsum traffic --fetch COUNTER_CSV --write COUNTER_CSV \\
         --workload jacobi3d_512 --kernel k_persistent --alg-bytes N [--copy-bytes 1073741824] \\
         [--update profiles/traffic.json]
@@ -83,6 +85,49 @@ def traffic(args) -> dict:
     return entry
 
 
+def _dispatch_values(path: str, counter: str, kernel: str):
+    """(copy-kernel median, the kernel's values in dispatch order) in KiB."""
+    copy, target = [], []
+    for r in _rows(path):
+        if r["Counter_Name"] != counter:
+            continue
+        v = float(r["Counter_Value"])
+        if r["Kernel_Name"].startswith("gf::k_copy_tiles"):
+            copy.append(v)
+        elif kernel in r["Kernel_Name"]:
+            target.append((int(r.get("Dispatch_Id", r.get("Correlation_Id", 0)) or 0), v))
+    if not copy or not target:
+        raise SystemExit(f"{path}: no {counter} rows for the copy kernel or for {kernel}")
+    target.sort()
+    return statistics.median(copy), [v for _, v in target]
+
+
+def traffic_positions_table(fetch: str, write: str, kernel: str, skip: int, period: int, count: int, labels,
+                            alg, copy_bytes: int = 1 << 30) -> str:
+    """HBM bytes per dispatch of one kernel by position in a repeating
+    sequence (the regions of a program's loop), each counter scaled by what
+    it reads for the copy kernel in the same run, beside the algorithmic
+    bytes of each position."""
+    fc, fv = _dispatch_values(fetch, "FETCH_SIZE", kernel)
+    wc, wv = _dispatch_values(write, "WRITE_SIZE", kernel)
+    fs, ws = copy_bytes / (fc * 1024.0), copy_bytes / (wc * 1024.0)
+    fv, wv = fv[skip:skip + count], wv[skip:skip + count]
+    if len(fv) < count or len(wv) < count:
+        raise SystemExit(f"only {min(len(fv), len(wv))} dispatches of {kernel!r} after skipping {skip}")
+    out = ["| position | region | reads (MB) | writes (MB) | total (MB) | algorithmic (MB) | measured / algorithmic |",
+           "|---|---|---|---|---|---|---|"]
+    for k in range(period):
+        rf = statistics.mean(fv[k::period]) * 1024.0 * fs
+        rw = statistics.mean(wv[k::period]) * 1024.0 * ws
+        a = alg[k] if k < len(alg) else 0
+        ratio = f"{(rf + rw) / a:.3f}" if a else ""
+        out.append(f"| {k} | {labels[k] if k < len(labels) else ''} | {rf / 1e6:.2f} | {rw / 1e6:.2f} | "
+                   f"{(rf + rw) / 1e6:.2f} | {a / 1e6:.2f} | {ratio} |")
+    out.append("")
+    out.append(f"Scale factors from the 1 GiB copy in the same run: reads x{fs:.4f}, writes x{ws:.4f}.")
+    return "\n".join(out)
+
+
 def positions_table(path: str, kernel: str, skip: int, period: int, count: int, labels) -> str:
     """Durations of the dispatches of one kernel, taken in start order, by
     their position in a repeating sequence (a program's regions): the
@@ -122,6 +167,16 @@ def main():
     q.add_argument("--period", type=int, required=True)
     q.add_argument("--count", type=int, required=True)
     q.add_argument("--labels", default="")
+    tp = sub.add_parser("traffic-positions")
+    tp.add_argument("--fetch", required=True)
+    tp.add_argument("--write", required=True)
+    tp.add_argument("--kernel", required=True)
+    tp.add_argument("--skip", type=int, default=0)
+    tp.add_argument("--period", type=int, required=True)
+    tp.add_argument("--count", type=int, required=True)
+    tp.add_argument("--labels", default="")
+    tp.add_argument("--alg", default="", help="comma list: algorithmic bytes of each position")
+    tp.add_argument("--copy-bytes", type=int, default=1 << 30)
     t = sub.add_parser("traffic")
     t.add_argument("--fetch", required=True)
     t.add_argument("--write", required=True)
@@ -133,6 +188,12 @@ def main():
     args = ap.parse_args()
     if args.cmd == "stats":
         print(stats_table(args.csv, args.top))
+        return
+    if args.cmd == "traffic-positions":
+        print(traffic_positions_table(args.fetch, args.write, args.kernel, args.skip, args.period, args.count,
+                                      [x for x in args.labels.split(",") if x] if args.labels else [],
+                                      [int(x) for x in args.alg.split(",") if x] if args.alg else [],
+                                      args.copy_bytes))
         return
     if args.cmd == "positions":
         print(positions_table(args.csv, args.kernel, args.skip, args.period, args.count,

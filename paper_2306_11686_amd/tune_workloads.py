@@ -5,7 +5,8 @@ winners in the tuning database.
 
 Every candidate runs the real program (shortened where the launch shape's
 ranking does not depend on the run length: 40 of the 200 3D sweeps, 50 of
-the 500 CG iterations). Prints one JSON line per workload with the winner
+the 500 CG iterations); the batched workload is tuned per instance by the
+batched autotuner (gf_tune_batched). Prints one JSON line per workload with the winner
 and the spread of the candidates.
 """
 from __future__ import annotations
@@ -41,6 +42,13 @@ def main():
     for key in args.only.split(","):
         log(f"[tune] {key}")
         prog, inst, keep, _ = builders[key]()
+        if key == "batched_256":
+            launches, ms = tuner.tune_batched(ctx, prog, inst, key=key, reps=args.reps, path=args.db)
+            print(json.dumps({"workload": key, "wg_size": int(launches[0].wg_size), "best_ms": round(ms, 4),
+                              "rows_per_tile": sorted({int(l.tile_y) for l in launches})}), flush=True)
+            del keep, inst
+            torch.cuda.empty_cache()
+            continue
         best, table = tuner.tune(ctx, prog, inst, key=key, mode=GF_EXEC_PERSISTENT, reps=args.reps, path=args.db)
         ctx.take_output()
         ms = [m for _, m in table if math.isfinite(m)]

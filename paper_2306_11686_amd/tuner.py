@@ -69,3 +69,26 @@ def ratio_to_best(ms) -> list:
     finite = [m for m in ms if math.isfinite(m)]
     b = min(finite)
     return [m / b if math.isfinite(m) else math.inf for m in ms]
+
+
+def lookup_batched(key: str, path: str = DEFAULT_DB):
+    """The per-instance launches a batched tuning recorded under `key`, or None."""
+    e = load_db(path).get(key)
+    if not e or "per_instance" not in e:
+        return None
+    return [Launch.make(wg_size=int(e.get("wg_size", 0)), tile_y=int(ty), num_wg=int(wt),
+                        xcd_remap=int(e.get("xcd_remap", 1))) for ty, wt in e["per_instance"]]
+
+
+def tune_batched(ctx, program, instances, key: str | None = None, reps: int = 3, path: str = DEFAULT_DB):
+    """The library's batched autotuner (gf_tune_batched): a shape per instance;
+    records (rows per tile, relative share) per instance under `key`.
+    Returns (launches, median ms of the chosen plan)."""
+    launches, ms = ctx.tune_batched(program, instances, reps=reps)
+    if key is not None:
+        db = load_db(path)
+        db[key] = {"wg_size": int(launches[0].wg_size), "xcd_remap": int(launches[0].xcd_remap),
+                   "per_instance": [[int(l.tile_y), int(l.num_wg)] for l in launches],
+                   "ms": round(ms, 4), "mode": int(GF_EXEC_PERSISTENT)}
+        save_db(db, path)
+    return launches, ms

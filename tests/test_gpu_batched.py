@@ -44,6 +44,76 @@ def test_batched_small_uneven_instances(gfx, oracle_lib, nwg):
         assert np.all(np.abs(r - r_comp) <= 1e-12 * r_comp + 1e-300), (i, n)
 
 
+def test_batched_groups_laid_out_in_order(oracle_lib, monkeypatch):
+    """GF_BATCH_ALIGN=0 (and a grid too small to split over the eight XCDs):
+    groups laid out in order, whose members may sit on several XCDs, use the
+    group barrier that writes each member's L2 back."""
+    import paper_2306_11686_amd as gf
+    from paper_2306_11686_amd import programs
+    sides, sweeps = [40, 71, 130, 9, 200], 6
+    for env, nwg in (("0", 0), ("1", 7)):
+        monkeypatch.setenv("GF_BATCH_ALIGN", env)
+        with gf.Context(0) as ctx:
+            us, ws, rs, insts = _batch(gf, programs, sides, sweeps, seed=2)
+            ctx.run(programs.jacobi2d(sweeps), insts, mode=gf.GF_EXEC_PERSISTENT,
+                    launch=gf.Launch.make(num_wg=nwg) if nwg else None)
+            ctx.sync()
+            for i, n in enumerate(sides):
+                g_ref, _, r_comp, _ = oracle_lib.jacobi2d(gi.batched_grid(i, n, 2), sweeps)
+                assert np.array_equal(host(us[i]), g_ref), (env, i, n)
+                assert np.all(np.abs(host(rs[i]) - r_comp) <= 1e-12 * r_comp), (env, i, n)
+
+
+@pytest.mark.parametrize("mode", ["persistent", "per_region", "per_region_graph"])
+def test_batched_shape_per_instance(gfx, oracle_lib, mode):
+    """Every instance with its own rows per segment (shorter and longer than
+    the register ring, longer than the grid) and its own share of the grid."""
+    import paper_2306_11686_amd as gf
+    from paper_2306_11686_amd import programs
+    sides = [3, 40, 71, 130, 9, 200, 257, 64, 1000, 33]
+    segs = [1, 3, 7, 8, 2, 64, 13, 128, 32, 5000]
+    weights = [0, 1, 5, 100, 0, 30, 2, 0, 1000, 7]
+    sweeps = 5
+    us, ws, rs, insts = _batch(gf, programs, sides, sweeps, seed=4)
+    launches = [gf.Launch.make(wg_size=128, tile_y=sg, num_wg=wt) for sg, wt in zip(segs, weights)]
+    m = {"persistent": gf.GF_EXEC_PERSISTENT, "per_region": gf.GF_EXEC_PER_REGION,
+         "per_region_graph": gf.GF_EXEC_PER_REGION_GRAPH}[mode]
+    st = gfx.run_batched(programs.jacobi2d(sweeps), insts, launches, mode=m)
+    gfx.sync()
+    if mode == "persistent":
+        assert st["launches"] == 1
+    for i, n in enumerate(sides):
+        g_ref, _, r_comp, _ = oracle_lib.jacobi2d(gi.batched_grid(i, n, 4), sweeps)
+        g = host(us[i] if sweeps % 2 == 0 else ws[i])
+        assert np.array_equal(g, g_ref), (i, n)
+        assert np.all(np.abs(host(rs[i]) - r_comp) <= 1e-12 * r_comp + 1e-300), (i, n)
+
+
+def test_batched_tuner_plan_runs_and_matches_oracle(gfx, oracle_lib):
+    """gf_tune_batched picks a shape per instance; a run with that plan
+    equals the oracle on every instance (the tuner's own runs change the
+    data, so the instances are reset first)."""
+    import paper_2306_11686_amd as gf
+    from paper_2306_11686_amd import programs
+    sides = [64, 70, 100, 130, 260, 300, 520, 700, 1100, 1500, 90, 2000]
+    sweeps = 4
+    us, ws, rs, insts = _batch(gf, programs, sides, sweeps, seed=5)
+    prog = programs.jacobi2d(sweeps)
+    launches, ms = gfx.tune_batched(prog, insts, reps=1)
+    assert ms > 0 and len(launches) == len(sides)
+    assert len({int(l.wg_size) for l in launches}) == 1 and all(int(l.tile_y) > 0 for l in launches)
+    for i, n in enumerate(sides):
+        us[i].copy_(dev(gi.batched_grid(i, n, 5)))
+        ws[i].copy_(us[i])
+    st = gfx.run_batched(prog, insts, launches)
+    gfx.sync()
+    assert st["launches"] == 1
+    for i, n in enumerate(sides):
+        g_ref, _, r_comp, _ = oracle_lib.jacobi2d(gi.batched_grid(i, n, 5), sweeps)
+        assert np.array_equal(host(us[i]), g_ref), (i, n)
+        assert np.all(np.abs(host(rs[i]) - r_comp) <= 1e-12 * r_comp), (i, n)
+
+
 def test_batched_equals_single_instance_bitwise(gfx):
     import paper_2306_11686_amd as gf
     from paper_2306_11686_amd import programs
@@ -89,7 +159,11 @@ def test_batched_256_instances_config(gfx, oracle_lib, mode):
     print(f"batched 256 instances mode={mode}, sum n^2 = {int((sides.astype(np.int64) ** 2).sum())}", flush=True)
     us, ws, rs, insts = _batch(gf, programs, sides, sweeps)
     m = gf.GF_EXEC_PERSISTENT if mode == "persistent" else gf.GF_EXEC_PER_REGION
-    st = gfx.run(programs.jacobi2d(sweeps), insts, mode=m, launch=tuner.lookup("batched_256"))
+    per = tuner.lookup_batched("batched_256")
+    if per is not None:
+        st = gfx.run_batched(programs.jacobi2d(sweeps), insts, per, mode=m)
+    else:
+        st = gfx.run(programs.jacobi2d(sweeps), insts, mode=m, launch=tuner.lookup("batched_256"))
     gfx.sync()
     if mode == "persistent":
         assert st["launches"] == 1

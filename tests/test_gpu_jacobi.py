@@ -104,13 +104,18 @@ def test_jacobi2d_small_shapes(gfx, oracle_lib, mode, n, sweeps):
     assert np.all(np.abs(r - r_comp) <= 1e-12 * r_comp + 1e-300)
 
 
-@pytest.mark.parametrize("ty", [1, 2, 4, 8, 16])
-def test_jacobi2d_tilings(gfx, oracle_lib, ty):
+@pytest.mark.parametrize("n", [75, 76, 300, 301])
+@pytest.mark.parametrize("seg,wg", [(1, 64), (2, 64), (6, 64), (7, 128), (8, 64), (15, 192), (64, 256), (1000, 64)])
+def test_jacobi2d_tilings(gfx, oracle_lib, n, seg, wg):
+    """Row segments of every length against the ring of seven rows (shorter,
+    equal, longer, ragged, longer than the grid), odd n (one column per
+    thread) and even n (two), one or several column chunks per row."""
     import paper_2306_11686_amd as gf
-    u0 = gi.grid2d(75, seed=4)
-    g_ref, _, r_comp, _ = oracle_lib.jacobi2d(u0, 4)
+    print(f"jacobi2d tiling n={n} seg={seg} wg={wg}", flush=True)
+    u0 = gi.grid2d(n, seed=4)
+    g_ref, _, r_comp, _ = oracle_lib.jacobi2d(u0, 5)
     for mode in (gf.GF_EXEC_PERSISTENT, gf.GF_EXEC_PER_REGION):
-        g, r, _ = run_jacobi2d(gfx, u0, 4, mode, launch=gf.Launch.make(tile_y=ty, wg_size=64))
+        g, r, _ = run_jacobi2d(gfx, u0, 5, mode, launch=gf.Launch.make(tile_y=seg, wg_size=wg))
         assert np.array_equal(g, g_ref)
         assert np.all(np.abs(r - r_comp) <= 1e-12 * r_comp)
 
