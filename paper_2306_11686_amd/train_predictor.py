@@ -2,7 +2,12 @@
 device, evaluate on held-out nests and save the weights.
 
     python -m paper_2306_11686_amd.train_predictor [--train 2000] [--test 200]
-           [--epochs 2000] [--out paper_2306_11686_amd/predictor_weights.json]
+           [--epochs 3000] [--reps 3] [--dataset PATH.npz] [--out paper_2306_11686_amd/predictor_weights.json]
+
+With --dataset, the tuned timings are saved there (compressed numpy, no
+pickles) or, if the file exists, loaded from it instead of tuning again, so
+the weights can be rebuilt from a committed dataset. The weights record the
+region kernels' source hash and the dataset's hash.
 
 Prints one JSON line with the held-out quality: geometric mean of
 t(predicted) / t(best) over the nests, the fraction within 1.10, and the same
@@ -58,7 +63,7 @@ def main():
         f_tr, ms_tr = predictor.collect(ctx, specs_tr, reps=args.reps, log=log)
         f_te, ms_te = predictor.collect(ctx, specs_te, reps=args.reps, log=log)
         if args.dataset:
-            np.savez(args.dataset, f_tr=f_tr, ms_tr=ms_tr, f_te=f_te, ms_te=ms_te)
+            np.savez_compressed(args.dataset, f_tr=f_tr, ms_tr=ms_tr, f_te=f_te, ms_te=ms_te)
     tune_s = time.perf_counter() - t0
     log(f"[predictor] dataset ready in {tune_s:.1f} s")
 
@@ -102,6 +107,14 @@ def main():
                    "tuner_geomean_ratio": round(ev_tuner2["geomean_ratio"], 4),
                    "tuner_frac_within_1_10": round(ev_tuner2["frac_within_1_10"], 4)}
     tune_per_nest_ms = tune_s / max(1, len(specs_tr) + len(specs_te)) * 1e3
+    import hashlib
+    from .build import kernel_source_hash
+    ds_hash = None
+    if args.dataset:
+        with open(args.dataset, "rb") as f:
+            ds_hash = hashlib.sha256(f.read()).hexdigest()[:16]
+    model.update({"kernel_source_hash": kernel_source_hash(), "dataset": args.dataset, "dataset_sha256": ds_hash,
+                  "dataset_reused": loaded})
     model.update({"train_nests": args.train, "test_nests": args.test, "epochs": args.epochs, "lr": args.lr,
                   "heldout": ev_te, "train_fit": ev_tr, "per_kind": per_kind, "fixed_shapes": fixed,
                   "heldout_retimed": recheck})
