@@ -443,6 +443,16 @@ gf_status gf_sync(gf_ctx *ctx, void *hip_stream, gf_run_stats *stats);
  * the persistent kernel that would run `prog` (0 on error). */
 int32_t gf_persistent_capacity(gf_ctx *ctx, const gf_program *prog, int32_t wg_size);
 
+/* After the last batched persistent launch of ctx has completed: the number
+ * of its workgroups that ran on another XCD than the first workgroup of their
+ * residue class (blockIdx.x mod 8; the batched table keeps each group in one
+ * class). 0: every group shared one XCD and used the group barrier without
+ * L2 write-back; > 0: all groups used the cross-XCD one. -1 if that launch
+ * made no placement check (groups laid out in order). Which XCD takes which
+ * class varies between launches and is not checked. Synchronises with the
+ * device. Diagnostic. */
+int64_t gf_batch_misplaced(gf_ctx *ctx);
+
 /* Device copy kernel (bandwidth probe for the HBM ceiling): d_dst = d_src,
  * nbytes a multiple of 16. num_wg > 0: a grid-stride loop over num_wg
  * workgroups; num_wg <= 0: one 4 x 16-byte tile per thread over the whole

@@ -256,6 +256,7 @@ _SIGS = {
     "gf_batch_plan": (ctypes.c_int32, [ctypes.c_int32, ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_double),
                                        ctypes.c_int32, ctypes.c_int32, ctypes.POINTER(ctypes.c_int32),
                                        ctypes.POINTER(ctypes.c_int32)]),
+    "gf_batch_misplaced": (ctypes.c_int64, [ctypes.c_void_p]),
     "gf_tune_batched": (ctypes.c_int32, [ctypes.c_void_p, ctypes.POINTER(Program), ctypes.POINTER(Instance),
                                          ctypes.c_int32, ctypes.c_int32, ctypes.POINTER(Launch),
                                          ctypes.POINTER(ctypes.c_float), ctypes.c_void_p]),
@@ -430,6 +431,11 @@ class Context:
         self._check(self.lib.gf_region_run_batched(self.h, ctypes.byref(program), arr, len(instances), mode, ls,
                                                    ctypes.byref(stats), _stream_handle(stream)))
         return stats.as_dict()
+
+    def batch_misplaced(self) -> int:
+        """Workgroups of the last batched persistent launch found on another
+        XCD than its table assumed (0: groups kept to one XCD; -1: no check)."""
+        return int(self.lib.gf_batch_misplaced(self.h))
 
     def tune_batched(self, program: Program, instances, reps: int = 3, stream=None):
         """The batched autotuner: returns (launches, one per instance; median ms of the best run)."""

@@ -284,6 +284,7 @@ struct gf_ctx {
     void *d_batch = nullptr;
     void *h_batch = nullptr;
     bool batch_align = true;  // keep each batched group on one XCD (GF_BATCH_ALIGN=0: lay groups out in order)
+    uint32_t batch_check_epoch = 0;  // epoch of the last batched launch that checked placement (0: none)
     hipEvent_t batch_copied = nullptr;
     bool batch_pending = false;
 
@@ -1735,6 +1736,7 @@ gf_status run_batched(gf_ctx *ctx, const DProg &p, const gf_instance *inst, int 
     DInst dummy;
     std::memset(&dummy, 0, sizeof dummy);
     ctx->scr.epoch += 1;
+    ctx->batch_check_epoch = aligned ? ctx->scr.epoch : 0;
     e = launch_persistent(p, dummy, t, wg, ctx->scr, ring_of(ctx), stream, &bt);
     if (e != hipSuccess)
         return hipfail(ctx, e, "batched persistent launch");
@@ -2125,6 +2127,24 @@ gf_status gf_copy(gf_ctx *ctx, void *d_dst, const void *d_src, int64_t nbytes, i
     if (e != hipSuccess)
         return hipfail(ctx, e, "copy launch");
     return GF_OK;
+}
+
+int64_t gf_batch_misplaced(gf_ctx *ctx)
+{
+    if (!ctx)
+        return GF_EINVAL;
+    if (!ctx->batch_check_epoch)
+        return -1;
+    hipSetDevice(ctx->device);
+    if (hipDeviceSynchronize() != hipSuccess)
+        return GF_EHIP;
+    uint64_t v = 0;
+    if (hipMemcpy(&v, ctx->scr.lines + (int64_t)kBatchPlaceLine * kLineWords, sizeof v, hipMemcpyDeviceToHost) !=
+        hipSuccess)
+        return GF_EHIP;
+    if ((uint32_t)(v >> 32) != ctx->batch_check_epoch)
+        return -1;
+    return (int64_t)(uint32_t)v;
 }
 
 gf_status gf_sync(gf_ctx *ctx, void *hip_stream, gf_run_stats *stats)

@@ -206,8 +206,10 @@ constexpr int kFinalizeSubLine0 = kXcdBadLine + 1;
 // workgroups fold a MAX reduction with one atomic each; regions alternate
 // between them.
 constexpr int kMaxSlotLine0 = kFinalizeSubLine0 + GF_MAX_INSTANCES * kNumXcd;
-// Count of the workgroups of a batched launch that found themselves on
-// another XCD than their table entry assumes (epoch << 32 | count).
+// Placement check of a batched launch, 64-bit words tagged epoch << 32:
+// word 0 counts the workgroups that found themselves on another XCD than the
+// first workgroup of their residue class (blockIdx.x mod kNumXcd); word 1 + r
+// holds that first workgroup's XCD id + 1 for class r.
 constexpr int kBatchPlaceLine = kMaxSlotLine0 + 2;
 constexpr int kNumLines = kBatchPlaceLine + 1;
 

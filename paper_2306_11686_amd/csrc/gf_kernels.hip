@@ -1267,14 +1267,31 @@ __global__ void __launch_bounds__(family_max_threads<KMASK>())
         be.part_off = 0;
     }
     if (batched && batch.aligned) {
-        // every workgroup checks that it runs where the table placed it; a
-        // tree barrier over the whole grid makes the count final
+        // The table puts every group in one residue class of blockIdx.x mod
+        // the XCD count. The dispatcher deals workgroups to XCDs round-robin,
+        // but the XCD that takes workgroup 0 varies from launch to launch, so
+        // a class lands on some one XCD, not necessarily the one its number
+        // names. Every workgroup checks that it shares an XCD with the first
+        // workgroup of its class to arrive (word 1 + class of the placement
+        // line, tagged with the launch's epoch) and counts itself in word 0
+        // if not; a tree barrier over the whole grid makes the count final.
         __shared__ BarrierState s_gbar;
         uint64_t *place = (uint64_t *)(scr.lines + (int64_t)kBatchPlaceLine * kLineWords);
         if (threadIdx.x == 0) {
             s_gbar.gen = __hip_atomic_load(scr.lines + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
             s_gbar.ok = 1;
-            const uint32_t bad = hw_xcc_id() != blockIdx.x % kNumXcd ? 1u : 0u;
+            const uint32_t xcc = hw_xcc_id();
+            uint64_t *cls = place + 1 + blockIdx.x % kNumXcd;
+            const uint64_t mine = ((uint64_t)scr.epoch << 32) | (xcc + 1u);
+            uint64_t seen = __hip_atomic_load(cls, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            while ((uint32_t)(seen >> 32) != scr.epoch) {
+                if (__hip_atomic_compare_exchange_strong(cls, &seen, mine, __ATOMIC_RELAXED, __ATOMIC_RELAXED,
+                                                         __HIP_MEMORY_SCOPE_AGENT)) {
+                    seen = mine;
+                    break;
+                }
+            }
+            const uint32_t bad = (xcc >= (uint32_t)kNumXcd || seen != mine) ? 1u : 0u;
             uint64_t old = __hip_atomic_load(place, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
             for (;;) {
                 const uint64_t nw = ((uint32_t)(old >> 32) == scr.epoch) ? old + bad

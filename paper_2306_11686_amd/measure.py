@@ -123,6 +123,8 @@ def measure_batched(ctx, gf, programs, tuner, torch, reps):
 
     for name, mode in modes(MODES[:3]):          # the kernel split runs one instance
         ms = _time(ctx, torch, lambda: run(mode), reps)
+        if mode == 1:
+            out["persistent_misplaced_workgroups"] = ctx.batch_misplaced()
         out[name] = {"ms_per_run": round(ms, 3), "GBps": round(out["alg_bytes_per_run"] / (ms * 1e-3) / 1e9, 1),
                      "regions_per_s": round(256 * sweeps / (ms * 1e-3), 1)}
     return out

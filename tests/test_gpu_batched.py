@@ -64,6 +64,30 @@ def test_batched_groups_laid_out_in_order(oracle_lib, monkeypatch):
                 assert np.all(np.abs(host(rs[i]) - r_comp) <= 1e-12 * r_comp), (env, i, n)
 
 
+def test_batched_placement_check_after_other_launches(gfx, oracle_lib):
+    """Other launches first (odd grid sizes move the XCD that takes
+    workgroup 0), then a batched launch whose groups are kept to one XCD:
+    the placement check runs (a count, not -1) and the result equals the
+    oracle."""
+    import paper_2306_11686_amd as gf
+    from paper_2306_11686_amd import programs
+    sides, sweeps = [40, 71, 130, 9, 200, 64, 33, 90, 17], 6
+    for k, pre in enumerate((0, 3, 13)):
+        for j in range(pre):
+            run_jacobi2d(gfx, gi.batched_grid(j, 37 + 2 * j, 9), 2, gf.GF_EXEC_PERSISTENT,
+                         launch=gf.Launch.make(num_wg=1 + 2 * j))
+        us, ws, rs, insts = _batch(gf, programs, sides, sweeps, seed=3 + k)
+        gfx.run(programs.jacobi2d(sweeps), insts, mode=gf.GF_EXEC_PERSISTENT, launch=gf.Launch.make(num_wg=64))
+        gfx.sync()
+        misplaced = gfx.batch_misplaced()
+        print(f"placement check after {pre} launches: {misplaced} workgroups off their class's XCD", flush=True)
+        assert misplaced >= 0
+        for i, n in enumerate(sides):
+            g_ref, _, r_comp, _ = oracle_lib.jacobi2d(gi.batched_grid(i, n, 3 + k), sweeps)
+            assert np.array_equal(host(us[i]), g_ref), (pre, i, n)
+            assert np.all(np.abs(host(rs[i]) - r_comp) <= 1e-12 * r_comp), (pre, i, n)
+
+
 @pytest.mark.parametrize("mode", ["persistent", "per_region", "per_region_graph"])
 def test_batched_shape_per_instance(gfx, oracle_lib, mode):
     """Every instance with its own rows per segment (shorter and longer than
