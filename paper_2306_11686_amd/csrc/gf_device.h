@@ -442,6 +442,56 @@ __device__ __forceinline__ bool xcd_barrier(uint32_t *lines, const XcdState &xs,
     return bs->ok != 0;
 }
 
+// The XCD barrier with a finishing step: the workgroup whose XCD leader
+// arrives last runs fin() with all its threads between the arrival and the
+// release. It first invalidates its XCD's L2, so fin() reads what every
+// other workgroup stored before arriving (their leaders wrote their L2s
+// back); what fin() publishes it writes with agent-scope atomic stores,
+// which the waiting workgroups read with agent-scope atomic loads once they
+// are released. The arrival side is the same as in xcd_barrier.
+template <class Fin>
+__device__ __forceinline__ bool xcd_barrier_fin(uint32_t *lines, const XcdState &xs, BarrierState *bs, int32_t *err,
+                                                int64_t timeout_ticks, Fin fin)
+{
+    __shared__ int32_t s_fin;
+    __builtin_amdgcn_s_waitcnt(0x0F70);
+    __syncthreads();
+    uint32_t *genw = lines + 1;
+    if (threadIdx.x == 0) {
+        uint32_t *xcnt = lines + (kXcdCntLine0 + xs.x) * kLineWords;
+        uint32_t *top = lines + kXcdTopLine * kLineWords;
+        const uint32_t g = bs->gen;
+        int32_t ok = 1, last = 0;
+        const uint32_t a = __hip_atomic_fetch_add(xcnt, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        if (a == xs.mx - 1) {
+            __hip_atomic_store(xcnt, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+            const uint32_t b = __hip_atomic_fetch_add(top, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            if (b == xs.nx - 1) {
+                __hip_atomic_store(top, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                last = 1;  // releases the others after fin()
+            } else {
+                ok = wait_equal(genw, g + 1u, err, timeout_ticks) ? 1 : 0;
+            }
+        } else {
+            ok = wait_equal(genw, g + 1u, err, timeout_ticks) ? 1 : 0;
+        }
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+        bs->gen = g + 1u;
+        bs->ok = ok;
+        s_fin = last;
+    }
+    __syncthreads();
+    if (s_fin) {
+        fin();
+        __builtin_amdgcn_s_waitcnt(0x0F70);  // fin's stores are acknowledged
+        __syncthreads();
+        if (threadIdx.x == 0)
+            __hip_atomic_store(genw, bs->gen, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+    return bs->ok != 0;
+}
+
 // Logical worker id of workgroup `wg` among `nwg`: workgroups are dispatched
 // round-robin over the 8 XCDs (each with its own L2), so with remapping the
 // workers of one XCD get consecutive ids and hence neighbouring tiles.

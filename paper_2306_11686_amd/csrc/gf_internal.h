@@ -211,7 +211,10 @@ constexpr int kMaxSlotLine0 = kFinalizeSubLine0 + GF_MAX_INSTANCES * kNumXcd;
 // first workgroup of their residue class (blockIdx.x mod kNumXcd); word 1 + r
 // holds that first workgroup's XCD id + 1 for class r.
 constexpr int kBatchPlaceLine = kMaxSlotLine0 + 2;
-constexpr int kNumLines = kBatchPlaceLine + 1;
+// The value a reduction's last arriving workgroup publishes under the XCD
+// barrier (the bits of a double).
+constexpr int kRedSlotLine = kBatchPlaceLine + 1;
+constexpr int kNumLines = kRedSlotLine + 1;
 
 // A serial step attached to a per-region launch, with its array operand
 // resolved on the host (SWAPs are applied by the host while it walks the

@@ -1439,6 +1439,28 @@ __global__ void __launch_bounds__(family_max_threads<KMASK>())
                 }
                 if (fold && threadIdx.x == 0 && worker < nitems)
                     __hip_atomic_fetch_max(slot, max_key(wmax), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                if (red && !fold && xmode && s_xcd.use && G > 1) {
+                    // Other reductions under the XCD barrier: the last
+                    // workgroup to arrive reduces the partials once (the same
+                    // fixed order as below) and publishes the value; the
+                    // others read one word instead of every partial.
+                    uint64_t *sum_slot = (uint64_t *)(scr.lines + (int64_t)kRedSlotLine * kLineWords);
+                    if (!xcd_barrier_fin(scr.lines, s_xcd, &s_bar, scr.error, scr.barrier_timeout_ticks, [&]() {
+                            const double v = reduce_partials(st.red_op, part, nitems, s_red);
+                            if (threadIdx.x == 0)
+                                __hip_atomic_store(sum_slot, (uint64_t)__double_as_longlong(v), __ATOMIC_RELAXED,
+                                                   __HIP_MEMORY_SCOPE_AGENT);
+                        }))
+                        return;
+                    if (threadIdx.x == 0)
+                        s_scal[st.sc[0]] = red_apply(
+                            st.red_op, s_scal[st.sc[0]],
+                            __longlong_as_double(
+                                (long long)__hip_atomic_load(sum_slot, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)));
+                    parity ^= 1;
+                    __syncthreads();
+                    continue;
+                }
                 // the last arrival resets the other slot, which the previous
                 // folded region used and every workgroup has read by now
                 if (need_bar && !barrier(fold ? max_slot + (mparity ? 0 : kLineWords / 2) : nullptr))
