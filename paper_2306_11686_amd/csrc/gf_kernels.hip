@@ -1230,14 +1230,23 @@ constexpr int family_max_threads()
     return KMASK == kFamHist ? kMaxWgHist : kMaxWg;
 }
 
-// Waves per SIMD the persistent kernel is compiled to fit: three 256-thread
-// workgroups per CU for the 3D stencil with tiles of one or two rows and one
-// plane in flight (its register need sits just above the 168 VGPRs that
-// allows; the compiler fits it without spilling).
+// Waves per SIMD the persistent kernel is compiled to fit (168 VGPRs for
+// three). The 3D stencil with tiles of one or two rows and one plane in
+// flight: three 256-thread workgroups per CU (its register need sits just
+// above that; the compiler fits it without spilling). The 2D stencil: left
+// alone the compiler gives the persistent kernel 187 VGPRs (two waves per
+// SIMD) although the marching tile itself needs about 86 (the per-region
+// kernel's count); at three waves it spills a few words outside the march,
+// and batched runs, whose large instances are bound by rows in flight per
+// wavefront, go 14 % faster. Four waves spill inside the march and are slower.
 template <unsigned KMASK, int TY, int PF>
 constexpr int persistent_min_waves()
 {
-    return (KMASK == ((1u << GF_R_JACOBI3D) | (1u << GF_R_OWNER)) && TY <= 2 && PF == 1) ? 3 : 1;
+    if (KMASK == ((1u << GF_R_JACOBI3D) | (1u << GF_R_OWNER)) && TY <= 2 && PF == 1)
+        return 3;
+    if (KMASK == ((1u << GF_R_JACOBI2D) | (1u << GF_R_OWNER)))
+        return 3;
+    return 1;
 }
 
 template <unsigned KMASK, int TY, int PF>
@@ -1828,6 +1837,7 @@ int phases_capacity(int wg_size, int num_cu)
 constexpr unsigned kFamJ3 = (1u << GF_R_JACOBI3D) | (1u << GF_R_OWNER);
 static_assert(persistent_min_waves<kFamJ3, 2, 1>() == 3, "3D stencil family mask");
 constexpr unsigned kFamJ2 = (1u << GF_R_JACOBI2D) | (1u << GF_R_OWNER);
+static_assert(persistent_min_waves<kFamJ2, 1, 1>() == 3, "2D stencil family mask");
 constexpr unsigned kFamVec =
     (1u << GF_R_SPMV) | (1u << GF_R_DOT) | (1u << GF_R_AXPBY) | (1u << GF_R_OWNER) | (1u << GF_R_PHASES);
 constexpr unsigned kFamAll = kFamJ3 | kFamJ2 | kFamVec;  // the histogram runs only in its own family
