@@ -14,6 +14,7 @@
 #include <cstdlib>
 #include <sys/prctl.h>
 #include <cstring>
+#include <array>
 #include <map>
 #include <mutex>
 #include <new>
@@ -236,6 +237,9 @@ struct gf_ctx {
     int device = 0;
     int num_cu = 0;
     std::string err;
+    // resident workgroups of a per-region kernel, by (region kind, workgroup
+    // size, rows per tile, prefetch)
+    std::map<std::array<int, 4>, int> region_cap;
 
     Scratch scr{};
     void *d_scratch_lines = nullptr;
@@ -1299,7 +1303,10 @@ int64_t max_items(const DProg &p, const gf_instance &in, const Tiling &t)
     return m;
 }
 
-// Grid of a per-region launch: one workgroup per work item up to 16 per CU.
+// Grid of a per-region launch: one workgroup per work item up to 16 per CU;
+// SpMV, which is latency-bound and holds an LDS tile per workgroup, at most
+// one resident round (CG at 128^3: 122 ms per 500 iterations with 1,280
+// workgroups, five per CU, against 133 ms with 4,096 in rounds).
 // Histogram grid: a multiple of the bin-part count, at most kHistRowsMax.
 int hist_grid(int64_t want, uint32_t mask)
 {
@@ -1309,7 +1316,7 @@ int hist_grid(int64_t want, uint32_t mask)
     return (int)std::max<int64_t>(g, parts);
 }
 
-int region_grid(const gf_ctx *ctx, const DStep &s, int64_t items, const Tiling &t)
+int region_grid(gf_ctx *ctx, const DStep &s, int64_t items, const Tiling &t)
 {
     if (s.kind == GF_R_OWNER)
         return std::max(1, ctx->num_cu);
@@ -1317,7 +1324,15 @@ int region_grid(const gf_ctx *ctx, const DStep &s, int64_t items, const Tiling &
         return std::max(1, std::min(ctx->num_cu, phases_capacity(t.wg_size, ctx->num_cu)));
     if (s.kind == GF_R_HIST)
         return hist_grid(std::min<int64_t>(std::max<int64_t>(items, 1), (int64_t)ctx->num_cu * 2), s.mask);
-    const int64_t cap = (int64_t)ctx->num_cu * 16;
+    int64_t cap = (int64_t)ctx->num_cu * 16;
+    if (s.kind == GF_R_SPMV) {
+        const std::array<int, 4> key{s.kind, t.wg_size, t.tile_y, t.prefetch};
+        auto it = ctx->region_cap.find(key);
+        if (it == ctx->region_cap.end())
+            it = ctx->region_cap.emplace(key, region_capacity(s.kind, t, ctx->num_cu)).first;
+        if (it->second > 0)
+            cap = it->second;
+    }
     return (int)std::max<int64_t>(1, std::min<int64_t>(items, cap));
 }
 

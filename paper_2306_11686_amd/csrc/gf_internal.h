@@ -263,6 +263,8 @@ hipError_t launch_persistent(const DProg &prog, const DInst &inst, const Tiling 
                              const Scratch &scr, const RpcRing &rpc, hipStream_t s,
                              const BatchTable *batch = nullptr);
 int persistent_capacity(const DProg &prog, const Tiling &t, int num_cu);
+// Co-resident workgroups of the per-region kernel that runs regions of `kind`.
+int region_capacity(int kind, const Tiling &t, int num_cu);
 hipError_t launch_main(const DProg &prog, const DInst &inst, const RpcRing &rpc, const Scratch &scr,
                        hipStream_t s);
 hipError_t launch_region(const RegionLaunch &rl, const Tiling &t, int num_wg, const Scratch &scr,

@@ -48,7 +48,13 @@ def _time(ctx, torch, fn, reps):
     return float(np.median(ts))
 
 
-def _launch(tuner, key):
+def _launch(tuner, key, mode=1):
+    """The tuned launch for `key`; the per-region modes (0, 2) take the one
+    tuned in per-region mode when the database has it."""
+    if mode in (0, 2):
+        per_region = tuner.lookup(key + "@per_region")
+        if per_region is not None:
+            return per_region
     return tuner.lookup(key)
 
 
@@ -81,9 +87,9 @@ def measure_cg(ctx, gf, programs, tuner, torch, reps):
     # dot(p, q) reads two vectors, dot(r, r) one; each axpby reads two and writes one
     it_b = spmv_b + 16 * N + 8 * N + 3 * 24 * N
     out = {"config": f"cg_27pt_{m}^3_f64_{iters}iters", "rows": N, "nnz": nnz, "alg_bytes_per_iteration": it_b}
-    launch = _launch(tuner, "cg_128")
     for name, mode in modes():
         reset()
+        launch = _launch(tuner, "cg_128", mode)
         ms = _time(ctx, torch, lambda: ctx.run(prog, inst, mode=mode, launch=launch), reps)
         out[name] = {"ms_per_run": round(ms, 3), "GBps": round(iters * it_b / (ms * 1e-3) / 1e9, 1),
                      "regions_per_s": round(6 * iters / (ms * 1e-3), 1)}

@@ -17,7 +17,7 @@ import math
 import sys
 
 from . import tuner, workloads
-from .binding import GF_EXEC_PERSISTENT, Context
+from .binding import GF_EXEC_PER_REGION, GF_EXEC_PERSISTENT, Context
 
 
 def log(msg):
@@ -27,7 +27,7 @@ def log(msg):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--db", default=tuner.DEFAULT_DB)
-    ap.add_argument("--only", default="jacobi3d_512,jacobi2d_256,cg_128,hist_2^28,batched_256")
+    ap.add_argument("--only", default="jacobi3d_512,jacobi2d_256,cg_128,cg_128@per_region,hist_2^28,batched_256")
     ap.add_argument("--reps", type=int, default=3)
     args = ap.parse_args()
     import torch
@@ -36,6 +36,7 @@ def main():
         "jacobi3d_512": lambda: workloads.jacobi3d(512, 40),
         "jacobi2d_256": lambda: workloads.jacobi2d(ctx, 256, 100),
         "cg_128": lambda: workloads.cg(128, 50),
+        "cg_128@per_region": lambda: workloads.cg(128, 50),
         "hist_2^28": lambda: workloads.histogram(1 << 28),
         "batched_256": lambda: workloads.batched(256, 50),
     }
@@ -49,7 +50,10 @@ def main():
             del keep, inst
             torch.cuda.empty_cache()
             continue
-        best, table = tuner.tune(ctx, prog, inst, key=key, mode=GF_EXEC_PERSISTENT, reps=args.reps, path=args.db)
+        # a key ending in @per_region is tuned in that mode (its grid choices
+        # differ: a per-region launch need not fit one resident round)
+        mode = GF_EXEC_PER_REGION if key.endswith("@per_region") else GF_EXEC_PERSISTENT
+        best, table = tuner.tune(ctx, prog, inst, key=key, mode=mode, reps=args.reps, path=args.db)
         ctx.take_output()
         ms = [m for _, m in table if math.isfinite(m)]
         print(json.dumps({"workload": key, "best": tuner.launch_to_dict(best), "best_ms": round(min(ms), 4),

@@ -84,6 +84,28 @@ def test_spmv_fallback_path_for_dense_rows(gfx, oracle_lib):
         assert np.array_equal(host(ty), oracle_lib.spmv(rowptr, col, val, x))
 
 
+@pytest.mark.parametrize("per_row", [29, 30, 31, 32])
+def test_spmv_slices_around_the_lds_tile_size(gfx, oracle_lib, per_row):
+    """32-row slices of 29..32 nonzeros per row: 928..1,024 products per
+    slice, on both sides of the wavefront's 960 LDS product slots (LDS path
+    below, row loop above); both are bit-exact."""
+    import paper_2306_11686_amd as gf
+    rng = np.random.default_rng(per_row)
+    n = 64 * 37 + 5
+    rowptr = np.arange(n + 1, dtype=np.int64) * per_row
+    rowptr = rowptr.astype(np.int32)
+    col = rng.integers(0, n, int(rowptr[-1])).astype(np.int32)
+    val = rng.standard_normal(int(rowptr[-1]))
+    x = rng.standard_normal(n)
+    ty = dev(np.zeros(n))
+    prog = gf.Program.make([gf.Step.make(gf.GF_R_SPMV, arr=(0, 1, 2, 3, 4), np=0)], [], 0)
+    inst = gf.Instance.make({0: dev(rowptr), 1: dev(col), 2: dev(val), 3: dev(x), 4: ty}, scalars(), ip=(n,))
+    for mode in (gf.GF_EXEC_PERSISTENT, gf.GF_EXEC_PER_REGION):
+        gfx.run(prog, inst, mode=mode)
+        gfx.sync()
+        assert np.array_equal(host(ty), oracle_lib.spmv(rowptr, col, val, x)), mode
+
+
 @pytest.mark.parametrize("n", [1, 257, 100003, 2097152])
 @pytest.mark.parametrize("items", [1, 4, 16])
 def test_dot_and_axpby_regions(gfx, oracle_lib, n, items):
