@@ -154,6 +154,120 @@ def positions_table(path: str, kernel: str, skip: int, period: int, count: int, 
     return "\n".join(out)
 
 
+def _row(cells) -> str:
+    return "| " + " | ".join(str(c) for c in cells) + " |"
+
+
+def other_workloads_md(path: str, command: str) -> str:
+    """The JSON lines `measure.py` prints, as the markdown summary of the
+    other workloads (one section per configuration it finds)."""
+    recs = {}
+    with open(path) as f:
+        for line in f:
+            if line.startswith("{"):
+                d = json.loads(line)
+                recs[d["config"].split("_")[0]] = d
+    modes = ("persistent", "per_region", "per_region_graph", "kernel_split")
+    out = ["# Other workloads: persistent, per-region, graph and kernel-split timings on one MI355X", "",
+           "Command (from the repository root; launch shapes from `paper_2306_11686_amd/tuning_db.json`; "
+           "the per-region modes of CG take the shape tuned in that mode):", "", "    " + command, "",
+           "Times are HIP-event medians of the repetitions after a warm-up run. \"Algorithmic\" bytes are what "
+           "the legacy loops must move (each input element read once, each output written once).", ""]
+    d = recs.get("sync")
+    if d:
+        out += [f"## Cost of one trivial region (3D Jacobi on a 4^3 grid, {d['regions']} regions)", "",
+                "| mode | us per region |", "|---|---|"]
+        out += [_row([k[: -len("_us_per_region")], v]) for k, v in d.items() if k.endswith("_us_per_region")]
+        out.append("")
+    d = recs.get("jacobi2d")
+    if d:
+        out += ["## 2D Jacobi 256^2, 100 sweeps, L2 residual, printf every 10 sweeps through the RPC", "",
+                "| mode | ms per run | us per region | regions/s | printf cost (us each) |", "|---|---|---|---|---|"]
+        for m in modes:
+            if m in d:
+                out.append(_row([m, d[m]["ms_per_run"], d[m]["us_per_region"], d[m]["regions_per_s"],
+                                 d[m].get("printf_us_each", "")]))
+        for m in modes:
+            if m + "_no_printf" in d:
+                e = d[m + "_no_printf"]
+                out.append(_row([m + " (no printf)", e["ms_per_run"], e["us_per_region"], e["regions_per_s"], ""]))
+        out.append("")
+    for d in _all_lines(path):
+        if d["config"].startswith("rpc_printf"):
+            out += ["## RPC round trips (one wavefront calling 1,000 times; the library's server thread polls)", "",
+                    f"printf with an int and a double as values: posted {d['posted']['us_per_call']} us per call, "
+                    f"blocking {d['blocking']['us_per_call']} us per call.", ""]
+    fp = [d for d in _all_lines(path) if d["config"].startswith("rpc_fprintf")]
+    if fp:
+        d = fp[-1]
+        out += ["The paper's RPC benchmark shape: 1,000 blocking fprintf calls whose format string and 128-byte "
+                "buffer are passed by reference (the buffer read-write when the callee's use is unknown, read-only "
+                "when it is known).", "",
+                "| buffer mode | us per call | device: args | copy in | wait | copy out | host: decode | call | "
+                "reply | in flight |", "|---|---|---|---|---|---|---|---|---|---|"]
+        for m in ("buffer_read_write", "buffer_read_only"):
+            st = d[m]["stages_us"]
+            out.append(_row([m[len("buffer_"):], d[m]["us_per_call"], st["dev_args_us"], st["dev_copy_in_us"],
+                             st["dev_wait_us"], st["dev_copy_out_us"], st["host_decode_us"], st["host_call_us"],
+                             st["host_reply_us"], st["transit_us"]]))
+        out += ["", f"Stage times are averages over {d['buffer_read_write']['timed_calls']:,} timed calls.", ""]
+    d = recs.get("phases")
+    if d:
+        out += ["## Manual worksharing with barriers: 2^22 doubles, 100 producer/consumer phases", "",
+                f"Algorithmic bytes per phase {d['alg_bytes_per_phase']:,}.", "",
+                "| mode | workgroups | ms per run | us per phase | algorithmic GB/s |", "|---|---|---|---|---|"]
+        for k, v in d.items():
+            if isinstance(v, dict):
+                out.append(_row([k.rsplit("_wg", 1)[0], v["grid"], v["ms_per_run"], v["us_per_phase"], v["GBps"]]))
+        out.append("")
+    d = recs.get("cg")
+    if d:
+        out += [f"## CG on the 27-point matrix at 128^3 ({d['rows']:,} rows, {d['nnz']:,} nonzeros), 500 iterations",
+                "", f"Algorithmic bytes per iteration: {d['alg_bytes_per_iteration']:,}.", "",
+                "| mode | ms per run | algorithmic GB/s | regions/s |", "|---|---|---|---|"]
+        out += [_row([m, d[m]["ms_per_run"], d[m]["GBps"], d[m]["regions_per_s"]]) for m in modes if m in d]
+        out.append("")
+    d = recs.get("hist")
+    if d:
+        out += ["## Histogram: 2^28 u32 keys into 65,536 bins", "",
+                f"Algorithmic bytes: {d['alg_bytes']:,} (keys once, bins read and written once).", "",
+                "| keys | mode | us per run | algorithmic GB/s |", "|---|---|---|---|"]
+        for k, v in d.items():
+            if isinstance(v, dict):
+                keys, mode = k.split("_", 1)
+                out.append(_row([keys, mode, v["us_per_run"], v["GBps"]]))
+        out.append("")
+    d = recs.get("batched")
+    if d:
+        out += ["## Batched: 256 uneven 2D Jacobi instances (sides 64..2047), 50 sweeps each", "",
+                f"Sum of n^2 = {d['sum_n2']:,}; {d['regions_per_run']:,} regions per run; algorithmic bytes "
+                f"{d['alg_bytes_per_run']:,}; a shape per instance from the batched autotuner: "
+                f"{'yes' if d.get('per_instance_shapes') else 'no'}; workgroups off their group's XCD in the "
+                f"persistent launch: {d.get('persistent_misplaced_workgroups', 'n/a')}.", "",
+                "| mode | ms per run | algorithmic GB/s | regions/s |", "|---|---|---|---|"]
+        out += [_row([m, d[m]["ms_per_run"], d[m]["GBps"], d[m]["regions_per_s"]]) for m in modes if m in d]
+        out.append("")
+    d = recs.get("heap")
+    if d:
+        out += ["## Allocator benchmark: every thread allocates, uses and frees 128 bytes in one kernel", "",
+                "Balanced heap with 32 thread slots x 16 team slots (the paper's configuration) and with 64 x 32; "
+                "HIP's device malloc with the same heap size.", "",
+                "| teams | threads per team | balanced 32x16 (us) | balanced 64x32 (us) | HIP device malloc (us) | "
+                "HIP / 64x32 |", "|---|---|---|---|---|---|"]
+        for k, v in d.items():
+            if isinstance(v, dict):
+                t, th = k[len("teams"):].split("_threads")
+                out.append(_row([t, th, v["balanced_us"], v["balanced64x32_us"], v["hip_malloc_us"],
+                                 v["speedup64x32"]]))
+        out.append("")
+    return "\n".join(out)
+
+
+def _all_lines(path: str):
+    with open(path) as f:
+        return [json.loads(line) for line in f if line.startswith("{")]
+
+
 def main():
     ap = argparse.ArgumentParser()
     sub = ap.add_subparsers(dest="cmd", required=True)
@@ -177,6 +291,9 @@ def main():
     tp.add_argument("--labels", default="")
     tp.add_argument("--alg", default="", help="comma list: algorithmic bytes of each position")
     tp.add_argument("--copy-bytes", type=int, default=1 << 30)
+    o = sub.add_parser("other")
+    o.add_argument("measure_out")
+    o.add_argument("--command", default="python -m paper_2306_11686_amd.measure")
     t = sub.add_parser("traffic")
     t.add_argument("--fetch", required=True)
     t.add_argument("--write", required=True)
@@ -186,6 +303,9 @@ def main():
     t.add_argument("--copy-bytes", type=int, default=1 << 30)
     t.add_argument("--update", default=None)
     args = ap.parse_args()
+    if args.cmd == "other":
+        print(other_workloads_md(args.measure_out, args.command))
+        return
     if args.cmd == "stats":
         print(stats_table(args.csv, args.top))
         return

@@ -109,3 +109,28 @@ def test_bench_reports_traffic_only_for_the_measured_code(tmp_path, monkeypatch)
     assert bench.load_traffic("other") is None
     monkeypatch.setattr(bench, "kernel_source_hash", lambda: "def")
     assert bench.load_traffic("w") is None
+
+
+def test_other_workloads_summary_from_measure_lines(tmp_path):
+    """profsum other turns measure.py's JSON lines into one table per
+    configuration, with the figures as printed."""
+    from paper_2306_11686_amd import profsum
+    lines = [
+        {"config": "cg_27pt_128^3_f64_500iters", "rows": 2097152, "nnz": 55742968,
+         "alg_bytes_per_iteration": 912185252,
+         "persistent": {"ms_per_run": 133.6, "GBps": 3413.5, "regions_per_s": 22452.4},
+         "per_region": {"ms_per_run": 120.4, "GBps": 3786.7, "regions_per_s": 24907.3}},
+        {"config": "rpc_printf_1000_calls", "calls": 1000, "posted": {"us_per_call": 3.26},
+         "blocking": {"us_per_call": 5.44}},
+        {"config": "hist_u32_2^28_keys_65536_bins", "alg_bytes": 1074266112,
+         "uniform_persistent": {"us_per_run": 293.8, "GBps": 3656.9}},
+    ]
+    p = tmp_path / "m.out"
+    p.write_text("noise\n" + "\n".join(json.dumps(x) for x in lines) + "\n")
+    md = profsum.other_workloads_md(str(p), "cmd")
+    assert "| persistent | 133.6 | 3413.5 | 22452.4 |" in md
+    assert "| per_region | 120.4 | 3786.7 | 24907.3 |" in md
+    assert "Algorithmic bytes per iteration: 912,185,252." in md
+    assert "posted 3.26 us per call, blocking 5.44 us per call" in md
+    assert "| uniform | persistent | 293.8 | 3656.9 |" in md
+    assert "    cmd" in md
