@@ -722,7 +722,8 @@ __device__ __forceinline__ void axpby_item(double *out_, const double *x_, doubl
 // falls in its part (all of a worker's items share one part because the
 // worker stride is a multiple of the part count) into 16-bit counters packed
 // two per 32-bit LDS word, with non-returning LDS atomics, then writes them
-// as its partial row of 16-bit counts. After every chunk (at most 32768
+// as its partial row of 16-bit counts. Once per 32768 keys at most (every
+// chunk, or every few when chunks are smaller; a chunk is at most 32768
 // keys, checked on the host) the workgroup moves 0x8000 of every counter
 // that reached 0x8000 into the global bin: a counter is below 0x8000 after a
 // scan and grows by at most 32768 before the next one, so it never wraps and
@@ -830,17 +831,26 @@ __device__ __forceinline__ void hist_phase1_t(uint32_t *s_h, const uint32_t *key
         s_h[i] = 0u;
     __syncthreads();
     constexpr bool kAhead = ITEMS <= 4;
+    // A chunk adds at most chunk_keys to a counter, so escaping after every
+    // `every` chunks, every * chunk_keys <= 0x8000, keeps each counter (below
+    // 0x8000 after an escape) within 16 bits; small chunks share one scan.
+    const int64_t every = g.chunk_keys >= 0x8000 ? 1 : 0x8000 / g.chunk_keys;
+    int64_t since = 0;
     gf_u4 cur[ITEMS], nxt[kAhead ? ITEMS : 1];
     if (kAhead && worker < g.nitems)
         hist_load<ITEMS>(keys, n, (worker / g.parts) * g.chunk_keys, cur);
     for (int64_t it = worker; it < g.nitems; it += G) {
         const int64_t base = (it / g.parts) * g.chunk_keys;
+        const bool scan = ++since == every;
+        if (scan)
+            since = 0;
         if constexpr (kAhead) {
             const bool more = it + G < g.nitems;
             if (more)
                 hist_load<ITEMS>(keys, n, ((it + G) / g.parts) * g.chunk_keys, nxt);
             hist_count_all<ITEMS>(s_h, cur, n, base, mask, lo, span);
-            hist_escape(s_h, bins, lo, span);
+            if (scan)
+                hist_escape(s_h, bins, lo, span);
             if (more) {
 #pragma unroll
                 for (int k = 0; k < ITEMS; ++k)
@@ -849,9 +859,14 @@ __device__ __forceinline__ void hist_phase1_t(uint32_t *s_h, const uint32_t *key
         } else {
             hist_load<ITEMS>(keys, n, base, cur);
             hist_count_all<ITEMS>(s_h, cur, n, base, mask, lo, span);
-            hist_escape(s_h, bins, lo, span);
+            if (scan)
+                hist_escape(s_h, bins, lo, span);
         }
     }
+    // the rows below hold the counters as 16-bit entries: every counter is
+    // at most 0x7FFF plus the keys of the chunks since the last escape; the
+    // workgroup's counting is complete before they are read
+    __syncthreads();
     // the packed LDS word holds bins 2w (low half) and 2w+1 (high half): as
     // a 32-bit store it lays down the two 16-bit row entries in order
     GF_GLOBAL uint32_t *row = gptr(rows_) + worker * (kHistPart / 2);

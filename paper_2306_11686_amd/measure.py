@@ -99,10 +99,10 @@ def measure_cg(ctx, gf, programs, tuner, torch, reps):
 def measure_hist(ctx, gf, programs, tuner, torch, reps):
     n = 1 << 28
     out = {"config": "hist_u32_2^28_keys_65536_bins", "alg_bytes": 4 * n + 2 * 4 * 65536}
-    launch = _launch(tuner, "hist_2^28")
     for dist in ("uniform", "zipf"):
         prog, inst, keep, _ = workloads.histogram(n, 65536, dist)
         for name, mode in modes(MODES[:2]):
+            launch = _launch(tuner, "hist_2^28", mode)
             ms = _time(ctx, torch, lambda: ctx.run(prog, inst, mode=mode, launch=launch), reps)
             out[f"{dist}_{name}"] = {"us_per_run": round(ms * 1e3, 1),
                                      "GBps": round(out["alg_bytes"] / (ms * 1e-3) / 1e9, 1)}

@@ -27,7 +27,7 @@ def log(msg):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--db", default=tuner.DEFAULT_DB)
-    ap.add_argument("--only", default="jacobi3d_512,jacobi2d_256,cg_128,cg_128@per_region,hist_2^28,batched_256")
+    ap.add_argument("--only", default="jacobi3d_512,jacobi2d_256,cg_128,cg_128@per_region,hist_2^28,hist_2^28@per_region,batched_256")
     ap.add_argument("--reps", type=int, default=3)
     args = ap.parse_args()
     import torch
@@ -38,6 +38,7 @@ def main():
         "cg_128": lambda: workloads.cg(128, 50),
         "cg_128@per_region": lambda: workloads.cg(128, 50),
         "hist_2^28": lambda: workloads.histogram(1 << 28),
+        "hist_2^28@per_region": lambda: workloads.histogram(1 << 28),
         "batched_256": lambda: workloads.batched(256, 50),
     }
     for key in args.only.split(","):
