@@ -2,6 +2,7 @@
 // per-region kernel with in-kernel reduction finalize, gf_reduce and the
 // bandwidth probe. gfx950 only; built with -ffp-contract=off so every
 // elementwise value is rounded exactly as the legacy loop writes it.
+#include <type_traits>
 #include "gf_device.h"
 
 namespace gf {
@@ -46,7 +47,7 @@ __host__ __device__ inline StencilGeom j2_geom(int64_t n, const Tiling &t)
 {
     StencilGeom g;
     const int64_t interior = n > 2 ? n - 2 : 0;
-    g.nxc = cdiv(n, ((n & 1) ? 1 : 2) * (int64_t)t.wg_size);
+    g.nxc = cdiv(n, 2 * (int64_t)t.wg_size);  // two columns per thread
     g.nyt = cdiv(interior, t.tile_y);
     g.nzs = 1;
     return g;
@@ -55,7 +56,7 @@ __host__ __device__ inline StencilGeom j2_geom(int64_t n, const Tiling &t)
 __host__ __device__ inline int64_t chunk_elems(const Tiling &t) { return (int64_t)t.wg_size * t.items; }
 
 // SpMV rows per work item: half the workgroup, so a block of a stencil-like
-// matrix (<= 32 nonzeros per row) fits the 4096-product LDS tile.
+// matrix (<= 30 nonzeros per row) fits the LDS product tile.
 __host__ __device__ inline int64_t spmv_rows(const Tiling &t) { return t.wg_size / 2; }
 
 // Histogram work: chunks of wg_size * items * 4 keys (each thread reads
@@ -393,60 +394,46 @@ __device__ __forceinline__ double j3v2_item(const double *u_, double *w_, int64_
 }
 
 // 2D 5-point Jacobi. The workgroup owns a chunk of columns and marches down
-// a segment of rows [y0, y1): each thread owns W adjacent columns (W = 2, one
-// 16-byte access per row, for even n; W = 1 for odd n, whose rows are not
-// 16-byte aligned) and keeps rows y-1, y and y+1 in registers while the next
-// kJ2Ahead rows are in flight, so every value of u is fetched once per
-// segment plus two halo rows. x-neighbours come from the adjacent lanes by
-// DPP shifts; the first and last lane of each wavefront also load their
+// a segment of rows [y0, y1): each thread owns two adjacent columns (one
+// 16-byte access per row) and keeps rows y-1, y and y+1 in registers while
+// the next kJ2Ahead rows are in flight, so every value of u is fetched once
+// per segment plus two halo rows. x-neighbours come from the adjacent lanes
+// by DPP shifts; the first and last lane of each wavefront also load their
 // outer neighbour with every row (a cache hit: the adjacent wavefront reads
 // that line), so wavefronts never wait for each other. The ring of rows is
 // indexed with compile-time slots (the step loop is unrolled by the ring
-// size). Lanes past the row end load a clamped in-bounds address and store
-// nothing.
+// size). For odd n the rows start on 8-byte boundaries, so the 16-byte
+// accesses are only 8-byte aligned (ODD), and the row's last column n-1
+// falls to a thread of its own: that thread loads the pair (n-2, n-1) and
+// passes column n-1 on as its left value. Lanes past the row end load an
+// in-bounds pair and store nothing.
 constexpr int kJ2Ahead = 4;
 constexpr int kJ2Ring = kJ2Ahead + 3;
+typedef double gf_d2u __attribute__((ext_vector_type(2), aligned(8)));
 
-template <int W>
-struct J2Vec {
-    typedef gf_d2 type;
-};
-template <>
-struct J2Vec<1> {
-    typedef double type;
-};
-
-template <int W>
+template <bool ODD>
 __device__ __forceinline__ double j2m_seg(GF_GLOBAL const double *__restrict__ u, GF_GLOBAL double *__restrict__ w,
                                           int64_t n, int64_t x, int64_t y0, int64_t y1, bool want_red)
 {
-    typedef typename J2Vec<W>::type V;
+    typedef typename std::conditional<ODD, gf_d2u, gf_d2>::type A;  // access type
     const int lane = threadIdx.x & (kWave - 1);
-    const bool xload = x < n;
-    const int64_t xs = xload ? x : n - W;  // clamped load column (W = 2: even, in bounds)
-    bool in0, in1;
-    if constexpr (W == 2) {
-        in0 = xload && x >= 1;          // column x is interior (x <= n-2 as x is even)
-        in1 = xload && x + 1 <= n - 2;  // column x+1 is interior
-    } else {
-        in0 = xload && x >= 1 && x <= n - 2;
-        in1 = false;
-    }
+    // x is even; for even n x <= n-2 whenever x < n, for odd n x may be n-1
+    const int64_t xs = x <= n - 2 ? x : n - 2;  // first column of the loaded pair
+    const bool in0 = x >= 1 && x <= n - 2;      // column x is interior
+    const bool in1 = x + 1 <= n - 2;            // column x+1 is interior
+    const bool last = ODD && x == n - 1;        // holds column n-1 alone
     // the wavefront's edge lanes read the neighbour column beyond the
     // wavefront: lane 0 the one on its left, the last lane the one on its right
-    const int64_t eoff = lane == 0 ? -1 : W;
-    const bool edge = (lane == 0 && xs >= 1) || (lane == kWave - 1 && xs + W <= n - 1);
+    const int64_t eoff = lane == 0 ? -1 : 2;
+    const bool edge = (lane == 0 && xs >= 1) || (lane == kWave - 1 && xs + 2 <= n - 1);
     const int64_t L = y1 - y0;  // rows computed; rows y0-1 .. y1 are read
     GF_GLOBAL const double *base = u + (y0 - 1) * n + xs;
-    auto ld = [&](int64_t j) -> V { return *(GF_GLOBAL const V *)(base + j * n); };
-    V ring[kJ2Ring];
+    auto ld = [&](int64_t j) -> gf_d2 { return *(GF_GLOBAL const A *)(base + j * n); };
+    gf_d2 ring[kJ2Ring];
     double eg[kJ2Ring];
 #pragma unroll
     for (int j = 0; j < kJ2Ring; ++j) {
-        if constexpr (W == 2)
-            ring[j] = gf_d2{0.0, 0.0};
-        else
-            ring[j] = 0.0;
+        ring[j] = gf_d2{0.0, 0.0};
         eg[j] = 0.0;
     }
     // rows y0-1 and y0 are only needed as the rows above; the edge value of
@@ -470,51 +457,35 @@ __device__ __forceinline__ double j2m_seg(GF_GLOBAL const double *__restrict__ u
                     if (edge && jl <= L)
                         eg[(k + kJ2Ahead + 2) % kJ2Ring] = base[jl * n + eoff];
                 }
-                const V up = ring[k];
-                const V c = ring[(k + 1) % kJ2Ring];
-                const V dn = ring[(k + 2) % kJ2Ring];
+                const gf_d2 up = ring[k];
+                const gf_d2 c = ring[(k + 1) % kJ2Ring];
+                const gf_d2 dn = ring[(k + 2) % kJ2Ring];
                 const double g = eg[(k + 1) % kJ2Ring];
-                double lo, hi;  // this thread's first and last column of the row
-                if constexpr (W == 2) {
-                    lo = c.x;
-                    hi = c.y;
-                } else {
-                    lo = c;
-                    hi = c;
-                }
+                // this thread's first and last column of the row
+                const double lo = last ? c.y : c.x;
+                const double hi = c.y;
                 const double sl = wave_shr1(hi);
                 const double sr = wave_shl1(lo);
                 const double xl = lane == 0 ? g : sl;
                 const double xr = lane == kWave - 1 ? g : sr;
                 GF_GLOBAL double *out = w + (y0 + i) * n + xs;
-                if constexpr (W == 2) {
-                    gf_d2 v;
-                    v.x = ((xl + c.y) + (up.x + dn.x)) * 0.25;
-                    v.y = ((c.x + xr) + (up.y + dn.y)) * 0.25;
-                    if (in0 && in1)
-                        *(GF_GLOBAL gf_d2 *)out = v;
-                    else if (in0)
-                        out[0] = v.x;
-                    else if (in1)
-                        out[1] = v.y;
-                    if (want_red) {
-                        if (in0) {
-                            const double d = v.x - c.x;
-                            acc = acc + d * d;
-                        }
-                        if (in1) {
-                            const double d = v.y - c.y;
-                            acc = acc + d * d;
-                        }
-                    }
-                } else {
-                    const double v = ((xl + xr) + (up + dn)) * 0.25;
+                gf_d2 v;
+                v.x = ((xl + c.y) + (up.x + dn.x)) * 0.25;
+                v.y = ((c.x + xr) + (up.y + dn.y)) * 0.25;
+                if (in0 && in1)
+                    *(GF_GLOBAL A *)out = v;
+                else if (in0)
+                    out[0] = v.x;
+                else if (in1)
+                    out[1] = v.y;
+                if (want_red) {
                     if (in0) {
-                        out[0] = v;
-                        if (want_red) {
-                            const double d = v - c;
-                            acc = acc + d * d;
-                        }
+                        const double d = v.x - c.x;
+                        acc = acc + d * d;
+                    }
+                    if (in1) {
+                        const double d = v.y - c.y;
+                        acc = acc + d * d;
                     }
                 }
             }
@@ -531,9 +502,10 @@ __device__ __forceinline__ double j2_item(const double *u_, double *w_, int64_t 
     const int64_t ys = item / g.nxc;
     const int64_t y0 = 1 + ys * t.tile_y;
     const int64_t y1 = (y0 + t.tile_y < n - 1) ? y0 + t.tile_y : n - 1;
+    const int64_t x = (xc * blockDim.x + threadIdx.x) * 2;
     if (n & 1)
-        return j2m_seg<1>(gptr(u_), gptr(w_), n, xc * blockDim.x + threadIdx.x, y0, y1, want_red);
-    return j2m_seg<2>(gptr(u_), gptr(w_), n, (xc * blockDim.x + threadIdx.x) * 2, y0, y1, want_red);
+        return j2m_seg<true>(gptr(u_), gptr(w_), n, x, y0, y1, want_red);
+    return j2m_seg<false>(gptr(u_), gptr(w_), n, x, y0, y1, want_red);
 }
 
 // CSR SpMV over a block of wg_size/2 rows (CSR-stream): the block's products

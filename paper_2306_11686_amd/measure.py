@@ -118,14 +118,15 @@ def measure_batched(ctx, gf, programs, tuner, torch, reps):
     bytes_per_sweepset = int(sum(8 * (n ** 2 - 4) + 8 * (n - 2) ** 2 for n in sides))
     out = {"config": "batched_256x_jacobi2d_sides_64_2048_50sweeps", "sum_n2": int(sum(n * n for n in sides)),
            "alg_bytes_per_run": bytes_per_sweepset * sweeps, "regions_per_run": 256 * sweeps}
-    launch = _launch(tuner, "batched_256")
     per = tuner.lookup_batched("batched_256")   # a shape per instance, from the batched autotuner
     out["per_instance_shapes"] = per is not None
 
     def run(mode):
-        if per is not None:
+        # the per-instance plan is the persistent launch's; the per-region
+        # modes launch every instance with the shape tuned in that mode
+        if per is not None and mode == 1:
             return ctx.run_batched(prog, insts, per, mode=mode)
-        return ctx.run(prog, insts, mode=mode, launch=launch)
+        return ctx.run(prog, insts, mode=mode, launch=_launch(tuner, "batched_256", mode))
 
     for name, mode in modes(MODES[:3]):          # the kernel split runs one instance
         ms = _time(ctx, torch, lambda: run(mode), reps)

@@ -27,7 +27,7 @@ def log(msg):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--db", default=tuner.DEFAULT_DB)
-    ap.add_argument("--only", default="jacobi3d_512,jacobi2d_256,cg_128,cg_128@per_region,hist_2^28,hist_2^28@per_region,batched_256")
+    ap.add_argument("--only", default="jacobi3d_512,jacobi2d_256,cg_128,cg_128@per_region,hist_2^28,hist_2^28@per_region,batched_256,batched_256@per_region")
     ap.add_argument("--reps", type=int, default=3)
     args = ap.parse_args()
     import torch
@@ -40,6 +40,7 @@ def main():
         "hist_2^28": lambda: workloads.histogram(1 << 28),
         "hist_2^28@per_region": lambda: workloads.histogram(1 << 28),
         "batched_256": lambda: workloads.batched(256, 50),
+        "batched_256@per_region": lambda: workloads.batched(256, 50),
     }
     for key in args.only.split(","):
         log(f"[tune] {key}")
