@@ -160,6 +160,19 @@ def measure_sync(ctx, gf, programs, tuner, torch, reps):
     for name, mode in MODES[1:]:
         ms = _time(ctx, torch, lambda: ctx.run(prog, inst, mode=mode, launch=launch), reps)
         out[f"{name}_us_per_region"] = round(ms * 1e3 / regions, 3)
+    # a whole program of one region, launched 200 times back to back: the
+    # fixed cost of a cooperative launch (persistent) against a plain one
+    one = programs.jacobi3d(1)
+    runs = 200
+
+    def repeat(mode, l):
+        for _ in range(runs):
+            ctx.run(one, inst, mode=mode, launch=l)
+
+    for name, mode, l in (("persistent_wg256", 1, gf.Launch.make(tile_y=1, num_wg=256)),
+                          ("per_region", 0, launch)):
+        ms = _time(ctx, torch, lambda: repeat(mode, l), reps)
+        out[f"one_region_program_{name}_us"] = round(ms * 1e3 / runs, 3)
     return out
 
 

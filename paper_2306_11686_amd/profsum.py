@@ -178,6 +178,12 @@ def other_workloads_md(path: str, command: str) -> str:
         out += [f"## Cost of one trivial region (3D Jacobi on a 4^3 grid, {d['regions']} regions)", "",
                 "| mode | us per region |", "|---|---|"]
         out += [_row([k[: -len("_us_per_region")], v]) for k, v in d.items() if k.endswith("_us_per_region")]
+        one = {k[len("one_region_program_"): -len("_us")]: v for k, v in d.items()
+               if k.startswith("one_region_program_")}
+        if one:
+            out += ["", "A program of one such region launched 200 times back to back (the fixed cost of one "
+                    "launch):", "", "| mode | us per program |", "|---|---|"]
+            out += [_row([k, v]) for k, v in one.items()]
         out.append("")
     d = recs.get("jacobi2d")
     if d:
