@@ -104,12 +104,14 @@ def test_jacobi2d_small_shapes(gfx, oracle_lib, mode, n, sweeps):
     assert np.all(np.abs(r - r_comp) <= 1e-12 * r_comp + 1e-300)
 
 
-@pytest.mark.parametrize("n", [75, 76, 300, 301])
+@pytest.mark.parametrize("n", [75, 76, 129, 300, 301])
 @pytest.mark.parametrize("seg,wg", [(1, 64), (2, 64), (6, 64), (7, 128), (8, 64), (15, 192), (64, 256), (1000, 64)])
 def test_jacobi2d_tilings(gfx, oracle_lib, n, seg, wg):
     """Row segments of every length against the ring of seven rows (shorter,
-    equal, longer, ragged, longer than the grid), odd n (one column per
-    thread) and even n (two), one or several column chunks per row."""
+    equal, longer, ragged, longer than the grid), even n and odd n (rows on
+    8-byte boundaries; the last column n-1 held alone by one thread, at
+    n = 129 with 64-thread workgroups the only column of its chunk), one or
+    several column chunks per row."""
     import paper_2306_11686_amd as gf
     print(f"jacobi2d tiling n={n} seg={seg} wg={wg}", flush=True)
     u0 = gi.grid2d(n, seed=4)
