@@ -229,7 +229,11 @@ typedef struct {
  * sized from occupancy; tiles come from the tuning database, else defaults. */
 typedef struct {
     int32_t wg_size;     /* threads per workgroup (multiple of 64, <= 1024) */
-    int32_t num_wg;      /* workgroups (persistent: <= co-resident capacity) */
+    int32_t num_wg;      /* workgroups (persistent: <= co-resident capacity);
+                            0 = default: persistent, up to two per CU with
+                            balanced rounds of work items; per region, one
+                            per work item up to 16 per CU, SpMV up to the
+                            region kernel's resident capacity */
     int32_t tile_y;      /* 3D stencil: rows per tile (1, 2, 4, 8 or 16); 2D stencil:
                           * rows per segment a workgroup marches through (>= 1) */
     int32_t tile_z;      /* 3D stencil z-segment length */
