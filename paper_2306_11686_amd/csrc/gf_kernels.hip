@@ -1231,7 +1231,7 @@ constexpr int family_max_threads()
 // SIMD) although the marching tile itself needs about 86 (the per-region
 // kernel's count); at three waves it spills a few words outside the march,
 // and batched runs, whose large instances are bound by rows in flight per
-// wavefront, go 14 % faster. Four waves spill inside the march and are slower.
+// wavefront, go 8-14 % faster. Four waves spill inside the march and are slower.
 template <unsigned KMASK, int TY, int PF>
 constexpr int persistent_min_waves()
 {
